@@ -1,0 +1,158 @@
+/*
+ * sm.h -- C ABI of libsm, exact string matching on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Tarhio, Holub and Giaquinta, "Technology Beats Algorithms (in Exact
+ * String Matching)", arXiv 1612.01506.  The library counts or reports every
+ * occurrence (overlapping ones included) of a pattern p of length m in a text
+ * t of length n (Section 1 problem statement), comparing pattern symbols in a
+ * caller-chosen order pi (Section 2.2) with the first r compares peeled out of
+ * the early-exit loop (Section 2.3, Algorithm 4).  The order and r change only
+ * the speed: every compare is ANDed into the found mask, so the result is the
+ * plain definition of Algorithm 1.
+ *
+ * Conventions for every call:
+ *   - Bytes are uint8_t; every value 0..255 is a symbol; no NUL termination.
+ *   - Positions are 0-based start offsets into t (the paper counts from 1).
+ *   - Counts are uint64 and include overlapping occurrences ("aaaa"/"aa" = 3).
+ *   - "device" pointers are HIP device memory of the current HIP device
+ *     (hipMalloc or torch CUDA tensors); "host" pointers are ordinary memory.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *   - The caller owns every buffer.  The library keeps no caller pointer after
+ *     a synchronous call returns, or after the stream work of an asynchronous
+ *     call completes.  It owns and reuses its own scratch memory (an upload
+ *     ring of pinned host + device memory and per-device scratch), freed by
+ *     sm_shutdown().
+ *   - Text reads: the kernels load whole 16-byte aligned chunks that overlap
+ *     [t, t+n); bytes of such a chunk outside the text are read but never
+ *     affect a result (an aligned 16-byte chunk never crosses a page).
+ *   - Return values: >= 0 success (a count where stated), < 0 an error code;
+ *     sm_last_error() then holds a message (thread-local).
+ *
+ * Error codes:
+ *   SM_EINVAL  null pointer with nonzero length, m == 0, an order that is not
+ *              a permutation of 0..m-1, a text pointer that is not device
+ *              memory, bad text_id, unknown flag or order kind, m >= 2^32.
+ *   SM_ENOMEM  library scratch could not be allocated.
+ *   SM_EDEVICE a HIP runtime error (message has the HIP error string).
+ * Not errors: n == 0 or m > n (count 0); cap == 0 with pos == NULL (count only).
+ */
+#ifndef SM_H
+#define SM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SM_OK 0
+#define SM_EINVAL (-1)
+#define SM_ENOMEM (-2)
+#define SM_EDEVICE (-3)
+
+/* Compare-order kinds for sm_order(). */
+#define SM_ORDER_LTR 0  /* left to right: Algorithm 2 (Section 2.1)                      */
+#define SM_ORDER_FREQ 1 /* increasing text frequency, ties by position (Section 2.2)    */
+#define SM_ORDER_H 2    /* fixed heuristic order pi_h (Section 2.4)                      */
+#define SM_ORDER_HS 3   /* pi_h with space (0x20) positions moved last: pi_hs (Section 2.4) */
+
+/* Launch tuning.  Any field 0 selects the library default.  None of them
+ * changes a result. */
+typedef struct sm_params {
+    int32_t peel;       /* r: compares done before the first zero test, 1..8 (Section 2.3); default 2 */
+    int32_t tile_kib;   /* text bytes staged per workgroup tile: 4, 8 or 16 KiB; default by n      */
+    int32_t wgs_per_cu; /* workgroups per compute unit the grid is sized for, 1..32; default 8     */
+    int32_t flags;      /* reserved, must be 0                                                     */
+} sm_params;
+
+/* ---------------------------------------------------------------- info */
+
+/* Library ABI version (major*10000 + minor*100 + patch). */
+int32_t sm_version(void);
+
+/* Message for the last error returned on this thread ("" if none). */
+const char *sm_last_error(void);
+
+/* Number of compute units of the current device, or < 0 on error. */
+int32_t sm_device_cus(void);
+
+/* Frees the library's scratch and upload ring on every device it used.
+ * The caller must make sure no library work is still running. */
+int32_t sm_shutdown(void);
+
+/* ------------------------------------------------------ preprocessing */
+
+/* Symbol histogram (Section 2.2: symbol frequencies).  hist_dev: device,
+ * 256 x uint64, overwritten with hist[b] = #{s : t[s] == b}.  Asynchronous
+ * on `stream`.  t: device, n bytes. */
+int32_t sm_histogram(const uint8_t *t, uint64_t n, uint64_t *hist_dev, void *stream);
+
+/* Compare order pi as a permutation of 0..m-1 (host, synchronous).
+ *   kind: SM_ORDER_LTR, SM_ORDER_FREQ (Section 2.2; ties keep increasing
+ *   position), SM_ORDER_H or SM_ORDER_HS (Section 2.4; the 1-based listing
+ *   1, m, 4, 7, ..., 3, 6, ..., 2, 5, ... read with each position once).
+ *   p: host, m bytes.  hist_host: host 256 x uint64, required for FREQ only.
+ *   order_out: host, m x int32. */
+int32_t sm_order(int32_t kind, const uint8_t *p, uint64_t m, const uint64_t *hist_host, int32_t *order_out);
+
+/* ------------------------------------------------------- single search */
+
+/* Count (Section 1; Algorithm 4 of Section 2.3 with pi = order, r = default):
+ * the number of s in [0, n-m] with t[s..s+m-1] == p.  Synchronous, null stream.
+ *   p: host, m bytes.  t: device, n bytes.
+ *   order: host, m x int32 permutation (compare order pi), or NULL = left to right.
+ * Returns the count (>= 0) or an error code. */
+int64_t sm_count(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n, const int32_t *order);
+
+/* sm_count with tuning (params may be NULL) on `stream`; synchronous. */
+int64_t sm_count_ex(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n, const int32_t *order,
+                    const sm_params *params, void *stream);
+
+/* Asynchronous count: ADDS the count to *count_dev (device uint64, which the
+ * caller zeroes first) on `stream` and returns SM_OK without waiting.  p and
+ * order are copied before return. */
+int32_t sm_count_async(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n, const int32_t *order,
+                       const sm_params *params, uint64_t *count_dev, void *stream);
+
+/* Report (Section 2.1: the reporting version prints each start found).
+ * Writes the min(count, cap) smallest start positions, strictly increasing,
+ * to pos_dev (device, cap x uint64) and returns the full count, so a return
+ * value > cap means the list was truncated.  Synchronous, null stream. */
+int64_t sm_report(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n, const int32_t *order,
+                  uint64_t *pos_dev, uint64_t cap);
+
+/* sm_report with tuning (params may be NULL) on `stream`; synchronous. */
+int64_t sm_report_ex(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n, const int32_t *order,
+                     const sm_params *params, uint64_t *pos_dev, uint64_t cap, void *stream);
+
+/* -------------------------------------------------------------- batches */
+
+typedef struct sm_text {
+    const uint8_t *t;      /* device, n bytes                                                  */
+    uint64_t n;
+    const uint64_t *hist;  /* host 256 x uint64 symbol histogram, or NULL                      */
+} sm_text;
+
+typedef struct sm_query {
+    uint32_t text_id;      /* index into the texts array                                       */
+    uint32_t flags;        /* must be 0                                                        */
+    const uint8_t *p;      /* host, m bytes                                                    */
+    uint64_t m;
+    const int32_t *order;  /* host permutation, or NULL: frequency order when the text has a
+                              histogram, else left to right                                    */
+} sm_query;
+
+/* Batched count: counts_dev[i] (device, nq x uint64) is overwritten with the
+ * count of query i in its text, exactly as sm_count would return it.  All
+ * queries run in one persistent launch that stages each text tile once and
+ * runs every query of an m-bucket over it.  Validation is all-or-nothing
+ * before anything is launched (the message names the first bad query).
+ * Asynchronous on `stream`: host inputs are consumed before return. */
+int32_t sm_count_batch(const sm_query *q, uint64_t nq, const sm_text *texts, uint64_t nt,
+                       uint64_t *counts_dev, const sm_params *params, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SM_H */

@@ -1,0 +1,221 @@
+"""Exact string matching on AMD Instinct MI355X (gfx950): Python binding of libsm.
+
+Implements the SIMD naive search of Tarhio, Holub and Giaquinta (arXiv
+1612.01506): every (overlapping) occurrence of a byte pattern in a byte text,
+pattern symbols compared in a chosen order (Section 2.2) with the first r
+compares peeled (Section 2.3).  This module only marshals arguments to the C
+ABI declared in include/sm.h; texts live in device memory as torch uint8
+tensors, patterns are host bytes.
+
+    import torch, paper_1612_01506_amd as sm
+    t = torch.frombuffer(bytearray(b"abracadabra"), dtype=torch.uint8).cuda()
+    sm.count(t, b"abra")                    # 2
+    sm.count(t, b"abra", order="freq")      # 2, rarest symbols compared first
+    sm.report(t, b"a")                      # tensor([0, 3, 5, 7, 10])
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Iterable, Sequence
+
+import numpy as np
+import torch
+
+from ._lib import (SM_ORDER_FREQ, SM_ORDER_H, SM_ORDER_HS, SM_ORDER_LTR, SmError, check, load,
+                   sm_params, sm_query, sm_text)
+
+__all__ = ["Text", "SmError", "histogram", "order", "count", "count_async", "report", "count_batch",
+           "version", "device_cus"]
+
+ORDER_KINDS = {"ltr": SM_ORDER_LTR, "freq": SM_ORDER_FREQ, "h": SM_ORDER_H, "hs": SM_ORDER_HS}
+
+
+# ------------------------------------------------------------------ marshalling
+def _pat(p) -> np.ndarray:
+    if isinstance(p, (bytes, bytearray, memoryview)):
+        a = np.frombuffer(bytes(p), dtype=np.uint8)
+    elif isinstance(p, str):
+        a = np.frombuffer(p.encode(), dtype=np.uint8)
+    elif isinstance(p, torch.Tensor):
+        a = p.detach().cpu().numpy()
+    else:
+        a = np.asarray(p)
+    if a.dtype != np.uint8:
+        raise TypeError("pattern must be uint8 bytes")
+    return np.ascontiguousarray(a.reshape(-1))
+
+
+def _ptr(a: np.ndarray | None):
+    return None if a is None or a.size == 0 else a.ctypes.data
+
+
+def _dev_text(t) -> tuple[int, int]:
+    if isinstance(t, Text):
+        t = t.t
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.uint8 or not t.is_cuda:
+        raise TypeError("text must be a CUDA (HIP) torch.uint8 tensor")
+    if t.dim() != 1 or not t.is_contiguous():
+        raise ValueError("text must be a contiguous 1-D tensor")
+    return t.data_ptr(), t.numel()
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def _params(peel=None, tile_kib=None, wgs_per_cu=None):
+    if peel is None and tile_kib is None and wgs_per_cu is None:
+        return None
+    return ctypes.byref(sm_params(int(peel or 0), int(tile_kib or 0), int(wgs_per_cu or 0), 0))
+
+
+# ---------------------------------------------------------------------- texts
+class Text:
+    """A device-resident text and its lazily computed symbol histogram (Section 2.2)."""
+
+    def __init__(self, t: torch.Tensor):
+        _dev_text(t)
+        self.t = t
+        self._hist: np.ndarray | None = None
+
+    @property
+    def n(self) -> int:
+        return self.t.numel()
+
+    @property
+    def hist(self) -> np.ndarray:
+        if self._hist is None:
+            self._hist = histogram(self.t).cpu().numpy().view(np.uint64).copy()
+        return self._hist
+
+
+def version() -> int:
+    return int(load().sm_version())
+
+
+def device_cus() -> int:
+    return check(load().sm_device_cus())
+
+
+def histogram(t, stream=None) -> torch.Tensor:
+    """hist[b] = number of text bytes equal to b, as a device int64 tensor of 256 (asynchronous)."""
+    ptr, n = _dev_text(t)
+    dev = t.t.device if isinstance(t, Text) else t.device
+    out = torch.empty(256, dtype=torch.int64, device=dev)
+    check(load().sm_histogram(ptr, n, out.data_ptr(), _stream(stream)))
+    return out
+
+
+def order(kind: str, p, hist=None) -> np.ndarray:
+    """Compare order pi (0-based permutation): 'ltr', 'freq' (needs hist), 'h' or 'hs'."""
+    a = _pat(p)
+    if a.size == 0:
+        raise ValueError("pattern length must be >= 1")
+    h = None
+    if hist is not None:
+        h = np.ascontiguousarray(np.asarray(hist).astype(np.uint64))
+        if h.size != 256:
+            raise ValueError("hist must have 256 entries")
+    out = np.empty(a.size, dtype=np.int32)
+    check(load().sm_order(ORDER_KINDS[kind], _ptr(a), a.size, _ptr(h), out.ctypes.data))
+    return out
+
+
+def _resolve_order(order_arg, p: np.ndarray, text) -> np.ndarray | None:
+    if order_arg is None or (isinstance(order_arg, str) and order_arg == "ltr"):
+        return None
+    if isinstance(order_arg, str):
+        if order_arg == "freq":
+            if not isinstance(text, Text):
+                text = Text(text)
+            return order("freq", p, text.hist)
+        return order(order_arg, p)
+    o = np.ascontiguousarray(np.asarray(order_arg, dtype=np.int32))
+    if o.size != p.size:
+        raise ValueError("order must have one entry per pattern position")
+    return o
+
+
+# -------------------------------------------------------------------- searches
+def count(t, p, order=None, peel=None, tile_kib=None, wgs_per_cu=None, stream=None) -> int:
+    """Number of (overlapping) occurrences of p in t; synchronous."""
+    a = _pat(p)
+    ptr, n = _dev_text(t)
+    o = _resolve_order(order, a, t)
+    return check(load().sm_count_ex(_ptr(a), a.size, ptr, n, _ptr(o),
+                                    _params(peel, tile_kib, wgs_per_cu), _stream(stream)))
+
+
+def count_async(t, p, out: torch.Tensor, order=None, peel=None, tile_kib=None, wgs_per_cu=None,
+                stream=None) -> None:
+    """ADD the count of p in t to out[0] (device int64) without waiting."""
+    a = _pat(p)
+    ptr, n = _dev_text(t)
+    if out.dtype != torch.int64 or not out.is_cuda:
+        raise TypeError("out must be a CUDA int64 tensor")
+    o = _resolve_order(order, a, t)
+    check(load().sm_count_async(_ptr(a), a.size, ptr, n, _ptr(o), _params(peel, tile_kib, wgs_per_cu),
+                                out.data_ptr(), _stream(stream)))
+
+
+def report(t, p, order=None, cap: int | None = None, peel=None, tile_kib=None, wgs_per_cu=None,
+           stream=None, return_count: bool = False):
+    """Increasing 0-based start positions of p in t (device int64 tensor); synchronous.
+
+    With cap given, at most cap positions are written; return_count=True also
+    returns the full count (> cap means truncated).
+    """
+    a = _pat(p)
+    ptr, n = _dev_text(t)
+    o = _resolve_order(order, a, t)
+    dev = t.t.device if isinstance(t, Text) else t.device
+    params = _params(peel, tile_kib, wgs_per_cu)
+    if cap is None:
+        cap = check(load().sm_count_ex(_ptr(a), a.size, ptr, n, _ptr(o), params, _stream(stream)))
+    pos = torch.empty(max(int(cap), 1), dtype=torch.int64, device=dev)
+    total = check(load().sm_report_ex(_ptr(a), a.size, ptr, n, _ptr(o), params, pos.data_ptr(), int(cap),
+                                      _stream(stream)))
+    out = pos[:min(total, int(cap))]
+    return (out, total) if return_count else out
+
+
+def count_batch(texts: Sequence, queries: Iterable, peel=None, tile_kib=None, wgs_per_cu=None,
+                stream=None, use_hist: bool = True) -> torch.Tensor:
+    """Counts of many (text_id, pattern[, order]) queries in one persistent launch (asynchronous).
+
+    Returns a device int64 tensor with one count per query.  Queries without an
+    explicit order use the frequency order when the text's histogram is known
+    (texts given as Text objects and use_hist), else left to right.
+    """
+    texts = list(texts)
+    tarr = (sm_text * max(len(texts), 1))()
+    keep = []
+    dev = None
+    for i, tx in enumerate(texts):
+        ptr, n = _dev_text(tx)
+        dev = dev or (tx.t.device if isinstance(tx, Text) else tx.device)
+        h = None
+        if use_hist and isinstance(tx, Text):
+            h = np.ascontiguousarray(tx.hist, dtype=np.uint64)
+            keep.append(h)
+        tarr[i] = sm_text(ptr, n, _ptr(h))
+    qs = list(queries)
+    qarr = (sm_query * max(len(qs), 1))()
+    for i, q in enumerate(qs):
+        tid, p = int(q[0]), _pat(q[1])
+        o = None
+        if len(q) > 2 and q[2] is not None:
+            tx = texts[tid] if 0 <= tid < len(texts) else None
+            o = _resolve_order(q[2], p, tx)
+        keep.append(p)
+        if o is not None:
+            keep.append(o)
+        qarr[i] = sm_query(tid, 0, _ptr(p), p.size, _ptr(o))
+    out = torch.empty(max(len(qs), 1), dtype=torch.int64, device=dev or "cuda")
+    check(load().sm_count_batch(qarr, len(qs), tarr, len(texts), out.data_ptr(),
+                                _params(peel, tile_kib, wgs_per_cu), _stream(stream)))
+    return out[:len(qs)]

@@ -1,0 +1,784 @@
+// C-ABI host side of libsm: validation, compare orders, step tables, the
+// upload ring, launch geometry, report scan plumbing and the batch planner.
+// The declarations and their contracts are in include/sm.h.
+#include "sm.h"
+#include "sm_internal.h"
+
+#include <algorithm>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+using namespace smk;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(SM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));      \
+    } while (0)
+
+#define SM_TRY(expr)           \
+    do {                       \
+        int rc_ = (expr);      \
+        if (rc_ < 0)           \
+            return rc_;        \
+    } while (0)
+
+inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+inline uint64_t round_up(uint64_t a, uint64_t b) { return ceil_div(a, b) * b; }
+
+// ------------------------------------------------------------------ devices
+
+struct Seg {
+    size_t begin, end;
+    hipEvent_t ev;
+};
+
+// Per-device state.  `mu` serialises every call that touches the ring or the
+// scratch buffers, so concurrent host threads are safe; overlapping device
+// work on different streams is ordered by the ring's events.
+struct Dev {
+    int id = -1;
+    int cus = 0;
+    std::mutex mu;
+    // upload ring: pinned host staging + device copy, reused in FIFO order
+    uint8_t *rh = nullptr, *rd = nullptr;
+    size_t rsize = 0, rhead = 0;
+    std::deque<Seg> inflight;
+    std::vector<hipEvent_t> evpool;
+    // scratch for the synchronous calls
+    unsigned long long *u64 = nullptr;  // [0] count, [1] report total
+    unsigned long long *hpin = nullptr; // pinned host copy of u64
+    uint32_t *bc = nullptr;
+    size_t bc_cap = 0;
+    unsigned long long *gs = nullptr, *go = nullptr;
+    size_t g_cap = 0;
+};
+
+constexpr int kMaxDev = 64;
+Dev *g_devs[kMaxDev];
+std::mutex g_devs_mu;
+constexpr size_t kRingBytes = 64u << 20;
+
+int get_dev(Dev **out)
+{
+    int id = 0;
+    HIP_TRY(hipGetDevice(&id));
+    if (id < 0 || id >= kMaxDev)
+        return fail(SM_EDEVICE, "device id out of range");
+    std::lock_guard<std::mutex> lk(g_devs_mu);
+    if (!g_devs[id]) {
+        Dev *d = new Dev();
+        d->id = id;
+        hipDeviceProp_t prop;
+        hipError_t e = hipGetDeviceProperties(&prop, id);
+        if (e == hipSuccess) {
+            d->cus = prop.multiProcessorCount;
+            d->rsize = kRingBytes;
+            e = hipHostMalloc(reinterpret_cast<void **>(&d->rh), d->rsize, hipHostMallocDefault);
+        }
+        if (e == hipSuccess)
+            e = hipMalloc(reinterpret_cast<void **>(&d->rd), d->rsize);
+        if (e == hipSuccess)
+            e = hipMalloc(reinterpret_cast<void **>(&d->u64), 2 * sizeof(unsigned long long));
+        if (e == hipSuccess)
+            e = hipHostMalloc(reinterpret_cast<void **>(&d->hpin), 2 * sizeof(unsigned long long),
+                              hipHostMallocDefault);
+        if (e != hipSuccess) {
+            if (d->rh) (void)hipHostFree(d->rh);
+            if (d->rd) (void)hipFree(d->rd);
+            if (d->u64) (void)hipFree(d->u64);
+            delete d;
+            return fail(e == hipErrorOutOfMemory ? SM_ENOMEM : SM_EDEVICE,
+                        std::string("device init: ") + hipGetErrorString(e));
+        }
+        g_devs[id] = d;
+    }
+    *out = g_devs[id];
+    return SM_OK;
+}
+
+// ------------------------------------------------------------- upload ring
+
+struct Upload {
+    uint8_t *host = nullptr;
+    uint8_t *dev = nullptr;
+    size_t begin = 0, end = 0;
+    bool dedicated = false;
+};
+
+int release_event(Dev &d, Seg s)
+{
+    HIP_TRY(hipEventSynchronize(s.ev));
+    d.evpool.push_back(s.ev);
+    return SM_OK;
+}
+
+// Reserve `bytes` of staging.  The caller fills u.host, then calls
+// ring_copy_commit after enqueuing every kernel that reads u.dev.
+int ring_reserve(Dev &d, size_t bytes, Upload *u)
+{
+    bytes = round_up(std::max<size_t>(bytes, 1), 256);
+    while (!d.inflight.empty() && hipEventQuery(d.inflight.front().ev) == hipSuccess) {
+        d.evpool.push_back(d.inflight.front().ev);
+        d.inflight.pop_front();
+    }
+    if (bytes > d.rsize / 2) {
+        u->dedicated = true;
+        HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&u->host), bytes, hipHostMallocDefault));
+        hipError_t e = hipMalloc(reinterpret_cast<void **>(&u->dev), bytes);
+        if (e != hipSuccess) {
+            (void)hipHostFree(u->host);
+            return fail(SM_ENOMEM, std::string("upload buffer: ") + hipGetErrorString(e));
+        }
+        return SM_OK;
+    }
+    size_t off = d.rhead;
+    if (off + bytes > d.rsize)
+        off = 0;
+    auto overlaps = [&](const Seg &s) { return s.begin < off + bytes && off < s.end; };
+    while (std::any_of(d.inflight.begin(), d.inflight.end(), overlaps)) {
+        Seg s = d.inflight.front();
+        d.inflight.pop_front();
+        SM_TRY(release_event(d, s));
+    }
+    d.rhead = off + bytes;
+    u->host = d.rh + off;
+    u->dev = d.rd + off;
+    u->begin = off;
+    u->end = off + bytes;
+    u->dedicated = false;
+    return SM_OK;
+}
+
+int ring_copy(const Upload &u, size_t bytes, hipStream_t s)
+{
+    HIP_TRY(hipMemcpyAsync(u.dev, u.host, bytes, hipMemcpyHostToDevice, s));
+    return SM_OK;
+}
+
+int ring_commit(Dev &d, Upload &u, hipStream_t s)
+{
+    if (u.dedicated) {
+        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(hipFree(u.dev));
+        HIP_TRY(hipHostFree(u.host));
+        u = Upload();
+        return SM_OK;
+    }
+    hipEvent_t ev;
+    if (d.evpool.empty()) {
+        HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    } else {
+        ev = d.evpool.back();
+        d.evpool.pop_back();
+    }
+    HIP_TRY(hipEventRecord(ev, s));
+    d.inflight.push_back({u.begin, u.end, ev});
+    return SM_OK;
+}
+
+// ------------------------------------------------------------ validation
+
+int check_text(const uint8_t *t, uint64_t n)
+{
+    if (n == 0)
+        return SM_OK;
+    if (!t)
+        return fail(SM_EINVAL, "t is NULL with n > 0");
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, t);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SM_EINVAL, "t is not device memory");
+    }
+    if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+        return fail(SM_EINVAL, "t is not device memory");
+    return SM_OK;
+}
+
+int check_pattern(const uint8_t *p, uint64_t m, const int32_t *order)
+{
+    if (m == 0)
+        return fail(SM_EINVAL, "pattern length m must be >= 1");
+    if (m >= (1ull << 32))
+        return fail(SM_EINVAL, "pattern length m must be < 2^32");
+    if (!p)
+        return fail(SM_EINVAL, "p is NULL");
+    if (order) {
+        std::vector<uint8_t> seen(m, 0);
+        for (uint64_t l = 0; l < m; ++l) {
+            const int64_t j = order[l];
+            if (j < 0 || (uint64_t)j >= m || seen[j])
+                return fail(SM_EINVAL, "order is not a permutation of 0..m-1");
+            seen[j] = 1;
+        }
+    }
+    return SM_OK;
+}
+
+// ----------------------------------------------------------------- orders
+
+void order_ltr(uint64_t m, int32_t *o)
+{
+    for (uint64_t j = 0; j < m; ++j)
+        o[j] = (int32_t)j;
+}
+
+// Section 2.2: increasing symbol frequency; equal frequencies keep position order.
+void order_by_freq(const uint8_t *p, uint64_t m, const uint64_t *hist, int32_t *o)
+{
+    order_ltr(m, o);
+    std::stable_sort(o, o + m, [&](int32_t a, int32_t b) { return hist[p[a]] < hist[p[b]]; });
+}
+
+// Section 2.4, 1-based listing 1, m, 4, 7, ..., 3, 6, ..., 2, 5, ...: position 1,
+// position m, then the residue chains 1, 0, 2 (mod 3) upward from 4, 3, 2,
+// each position once.
+void order_fixed_h(uint64_t m, int32_t *o)
+{
+    uint64_t k = 0;
+    o[k++] = 0;
+    if (m > 1)
+        o[k++] = (int32_t)(m - 1);
+    const uint64_t from[3] = {4, 3, 2};
+    for (uint64_t c = 0; c < 3; ++c)
+        for (uint64_t j = from[c]; j <= m; j += 3)
+            if (j != m)
+                o[k++] = (int32_t)(j - 1);
+}
+
+void order_fixed_hs(const uint8_t *p, uint64_t m, int32_t *o)
+{
+    std::vector<int32_t> h(m);
+    order_fixed_h(m, h.data());
+    std::stable_partition(h.begin(), h.end(), [&](int32_t j) { return p[j] != 0x20; });
+    std::copy(h.begin(), h.end(), o);
+}
+
+// Step table for compare order `order` (NULL: left to right).
+void build_steps(const uint8_t *p, uint64_t m, const int32_t *order, uint64_t *out)
+{
+    for (uint64_t l = 0; l < m; ++l) {
+        const uint64_t j = order ? (uint64_t)order[l] : l;
+        const uint64_t rep = (uint64_t)p[j] * 0x01010101ull;
+        out[l] = j | (rep << 32);
+    }
+    for (uint32_t l = 0; l < kStepPad; ++l)
+        out[m + l] = 0;
+}
+
+// -------------------------------------------------------------- geometry
+
+struct Tune {
+    int r;
+    int cpl;
+    int wpc;
+};
+
+Tune resolve(const sm_params *p, uint64_t m, uint64_t n)
+{
+    Tune t;
+    t.r = (p && p->peel > 0) ? std::min<int>(p->peel, (int)kMaxPeel) : 2;
+    t.r = (int)std::min<uint64_t>((uint64_t)t.r, m);
+    if (p && (p->tile_kib == 4 || p->tile_kib == 8 || p->tile_kib == 16))
+        t.cpl = p->tile_kib / 4;
+    else
+        t.cpl = n >= (64ull << 20) ? 4 : (n >= (8ull << 20) ? 2 : 1);
+    t.wpc = (p && p->wgs_per_cu > 0) ? std::min(p->wgs_per_cu, 32) : 8;
+    return t;
+}
+
+TextView make_view(const uint8_t *t, uint64_t n)
+{
+    TextView v;
+    const uintptr_t a = reinterpret_cast<uintptr_t>(t);
+    v.base = reinterpret_cast<const uint8_t *>(a & ~(uintptr_t)15);
+    v.first = a & 15u;
+    v.n = n;
+    v.end16 = round_up(v.first + n, 16);
+    return v;
+}
+
+uint32_t halo_for(uint64_t m) { return (uint32_t)round_up(m + 4, 16); }
+
+// Fills the geometry of a single search and launches the count kernel.
+int launch_count(Dev &d, const TextView &tv, uint64_t m, const uint64_t *steps_dev, const Tune &tu,
+                 unsigned long long *count_dev, uint32_t *block_counts, hipStream_t s)
+{
+    CountArgs a{};
+    a.tv = tv;
+    a.last = tv.first + tv.n - m;
+    a.nblocks = ceil_div(a.last + 1, kBlock);
+    a.steps = steps_dev;
+    a.m = (uint32_t)m;
+    a.count = count_dev;
+    a.block_counts = block_counts;
+    const uint64_t target = (uint64_t)std::max(d.cus, 1) * (uint64_t)tu.wpc;
+    int cpl = tu.cpl;
+    const uint64_t halo = halo_for(m);
+    if (4096ull * cpl + halo > kMaxLds)
+        cpl = 1;
+    if (4096ull + halo <= kMaxLds) {
+        const uint64_t T = 4096ull * cpl;
+        a.halo = (uint32_t)halo;
+        a.ntiles = ceil_div(a.last + 1, T);
+        a.tiles_per_wg = ceil_div(a.ntiles, target);
+        const uint64_t grid = ceil_div(a.ntiles, a.tiles_per_wg);
+        HIP_TRY(launch_count_staged(a, cpl, tu.r, (unsigned)grid, s));
+    } else {
+        const uint64_t grid = std::min<uint64_t>(ceil_div(a.nblocks, kWaves), target);
+        HIP_TRY(launch_count_global(a, tu.r, (unsigned)grid, s));
+    }
+    return SM_OK;
+}
+
+// Uploads the step table of one pattern through the ring.
+int upload_steps(Dev &d, const uint8_t *p, uint64_t m, const int32_t *order, hipStream_t s, Upload *u)
+{
+    const size_t bytes = (m + kStepPad) * sizeof(uint64_t);
+    SM_TRY(ring_reserve(d, bytes, u));
+    build_steps(p, m, order, reinterpret_cast<uint64_t *>(u->host));
+    return ring_copy(*u, bytes, s);
+}
+
+int ensure_report_scratch(Dev &d, uint64_t nblocks, uint64_t ngroups)
+{
+    if (d.bc_cap < nblocks) {
+        if (d.bc)
+            HIP_TRY(hipFree(d.bc));
+        d.bc = nullptr;
+        d.bc_cap = 0;
+        hipError_t e = hipMalloc(reinterpret_cast<void **>(&d.bc), nblocks * sizeof(uint32_t));
+        if (e != hipSuccess)
+            return fail(SM_ENOMEM, std::string("report scratch: ") + hipGetErrorString(e));
+        d.bc_cap = nblocks;
+    }
+    if (d.g_cap < ngroups) {
+        if (d.gs)
+            HIP_TRY(hipFree(d.gs));
+        if (d.go)
+            HIP_TRY(hipFree(d.go));
+        d.gs = d.go = nullptr;
+        d.g_cap = 0;
+        hipError_t e = hipMalloc(reinterpret_cast<void **>(&d.gs), ngroups * sizeof(unsigned long long));
+        if (e == hipSuccess)
+            e = hipMalloc(reinterpret_cast<void **>(&d.go), ngroups * sizeof(unsigned long long));
+        if (e != hipSuccess)
+            return fail(SM_ENOMEM, std::string("report scratch: ") + hipGetErrorString(e));
+        d.g_cap = ngroups;
+    }
+    return SM_OK;
+}
+
+int64_t count_sync(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n, const int32_t *order,
+                   const sm_params *params, hipStream_t s)
+{
+    g_err.clear();
+    SM_TRY(check_pattern(p, m, order));
+    SM_TRY(check_text(t, n));
+    if (m > n)
+        return 0;
+    Dev *d;
+    SM_TRY(get_dev(&d));
+    std::lock_guard<std::mutex> lk(d->mu);
+    const Tune tu = resolve(params, m, n);
+    Upload u;
+    SM_TRY(upload_steps(*d, p, m, order, s, &u));
+    HIP_TRY(hipMemsetAsync(d->u64, 0, sizeof(unsigned long long), s));
+    SM_TRY(launch_count(*d, make_view(t, n), m, reinterpret_cast<const uint64_t *>(u.dev), tu, d->u64, nullptr, s));
+    HIP_TRY(hipMemcpyAsync(d->hpin, d->u64, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    SM_TRY(ring_commit(*d, u, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return (int64_t)d->hpin[0];
+}
+
+int64_t report_sync(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n, const int32_t *order,
+                    const sm_params *params, uint64_t *pos, uint64_t cap, hipStream_t s)
+{
+    g_err.clear();
+    SM_TRY(check_pattern(p, m, order));
+    SM_TRY(check_text(t, n));
+    if (cap > 0 && !pos)
+        return fail(SM_EINVAL, "pos is NULL with cap > 0");
+    if (m > n)
+        return 0;
+    if (cap == 0)
+        return count_sync(p, m, t, n, order, params, s);
+    Dev *d;
+    SM_TRY(get_dev(&d));
+    std::lock_guard<std::mutex> lk(d->mu);
+    const Tune tu = resolve(params, m, n);
+    const TextView tv = make_view(t, n);
+    const uint64_t last = tv.first + n - m;
+    const uint64_t nblocks = ceil_div(last + 1, kBlock);
+    const uint64_t ngroups = ceil_div(nblocks, 64);
+    SM_TRY(ensure_report_scratch(*d, nblocks, ngroups));
+    Upload u;
+    SM_TRY(upload_steps(*d, p, m, order, s, &u));
+    // pass 1: per-vector counts
+    SM_TRY(launch_count(*d, tv, m, reinterpret_cast<const uint64_t *>(u.dev), tu, nullptr, d->bc, s));
+    // offsets: group sums, exclusive scan, total
+    HIP_TRY(launch_group_sums(d->bc, nblocks, ngroups, d->gs, s));
+    HIP_TRY(launch_scan_groups(d->gs, ngroups, d->go, d->u64 + 1, s));
+    // pass 2: ordered write of the vectors with matches
+    CountArgs a{};
+    a.tv = tv;
+    a.last = last;
+    a.nblocks = nblocks;
+    a.steps = reinterpret_cast<const uint64_t *>(u.dev);
+    a.m = (uint32_t)m;
+    const uint64_t target = (uint64_t)std::max(d->cus, 1) * (uint64_t)tu.wpc;
+    const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(ngroups, kWaves), target));
+    HIP_TRY(launch_report_write(a, d->bc, d->go, ngroups, reinterpret_cast<unsigned long long *>(pos), cap,
+                                (unsigned)grid, s));
+    HIP_TRY(hipMemcpyAsync(d->hpin + 1, d->u64 + 1, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    SM_TRY(ring_commit(*d, u, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return (int64_t)d->hpin[1];
+}
+
+// ------------------------------------------------------------- batch plan
+
+struct PlanQuery {
+    uint64_t idx;     // caller's query index
+    uint32_t text;
+    uint64_t m;
+    uint32_t bucket;  // halo bucket
+};
+
+}  // namespace
+
+// ======================================================================= C ABI
+
+extern "C" {
+
+int32_t sm_version(void) { return 10000; }
+
+const char *sm_last_error(void) { return g_err.c_str(); }
+
+int32_t sm_device_cus(void)
+{
+    g_err.clear();
+    Dev *d;
+    SM_TRY(get_dev(&d));
+    return d->cus;
+}
+
+int32_t sm_shutdown(void)
+{
+    g_err.clear();
+    std::lock_guard<std::mutex> lk(g_devs_mu);
+    int cur = 0;
+    HIP_TRY(hipGetDevice(&cur));
+    for (int i = 0; i < kMaxDev; ++i) {
+        Dev *d = g_devs[i];
+        if (!d)
+            continue;
+        HIP_TRY(hipSetDevice(i));
+        HIP_TRY(hipDeviceSynchronize());
+        for (auto &s : d->inflight)
+            (void)hipEventDestroy(s.ev);
+        for (auto ev : d->evpool)
+            (void)hipEventDestroy(ev);
+        (void)hipHostFree(d->rh);
+        (void)hipFree(d->rd);
+        (void)hipFree(d->u64);
+        (void)hipHostFree(d->hpin);
+        if (d->bc) (void)hipFree(d->bc);
+        if (d->gs) (void)hipFree(d->gs);
+        if (d->go) (void)hipFree(d->go);
+        delete d;
+        g_devs[i] = nullptr;
+    }
+    HIP_TRY(hipSetDevice(cur));
+    return SM_OK;
+}
+
+int32_t sm_histogram(const uint8_t *t, uint64_t n, uint64_t *hist_dev, void *stream)
+{
+    g_err.clear();
+    if (!hist_dev)
+        return fail(SM_EINVAL, "hist_dev is NULL");
+    SM_TRY(check_text(t, n));
+    Dev *d;
+    SM_TRY(get_dev(&d));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    unsigned long long *h = reinterpret_cast<unsigned long long *>(hist_dev);
+    HIP_TRY(launch_fill_u64(h, 256, 0ull, s));
+    if (n == 0)
+        return SM_OK;
+    const TextView tv = make_view(t, n);
+    const uint64_t nchunks = tv.end16 / 16;
+    const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(nchunks, kWG), (uint64_t)d->cus * 4));
+    HIP_TRY(launch_hist(tv, h, (unsigned)grid, s));
+    return SM_OK;
+}
+
+int32_t sm_order(int32_t kind, const uint8_t *p, uint64_t m, const uint64_t *hist_host, int32_t *order_out)
+{
+    g_err.clear();
+    if (m == 0 || m >= (1ull << 31))
+        return fail(SM_EINVAL, "pattern length m must be in 1..2^31-1");
+    if (!order_out)
+        return fail(SM_EINVAL, "order_out is NULL");
+    if (kind != SM_ORDER_LTR && kind != SM_ORDER_H && !p)
+        return fail(SM_EINVAL, "p is NULL");
+    switch (kind) {
+    case SM_ORDER_LTR: order_ltr(m, order_out); return SM_OK;
+    case SM_ORDER_FREQ:
+        if (!hist_host)
+            return fail(SM_EINVAL, "SM_ORDER_FREQ needs hist_host");
+        order_by_freq(p, m, hist_host, order_out);
+        return SM_OK;
+    case SM_ORDER_H: order_fixed_h(m, order_out); return SM_OK;
+    case SM_ORDER_HS: order_fixed_hs(p, m, order_out); return SM_OK;
+    default: return fail(SM_EINVAL, "unknown order kind");
+    }
+}
+
+int64_t sm_count(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n, const int32_t *order)
+{
+    return count_sync(p, m, t, n, order, nullptr, nullptr);
+}
+
+int64_t sm_count_ex(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n, const int32_t *order,
+                    const sm_params *params, void *stream)
+{
+    return count_sync(p, m, t, n, order, params, reinterpret_cast<hipStream_t>(stream));
+}
+
+int32_t sm_count_async(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n, const int32_t *order,
+                       const sm_params *params, uint64_t *count_dev, void *stream)
+{
+    g_err.clear();
+    SM_TRY(check_pattern(p, m, order));
+    SM_TRY(check_text(t, n));
+    if (!count_dev)
+        return fail(SM_EINVAL, "count_dev is NULL");
+    if (m > n)
+        return SM_OK;
+    Dev *d;
+    SM_TRY(get_dev(&d));
+    std::lock_guard<std::mutex> lk(d->mu);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const Tune tu = resolve(params, m, n);
+    Upload u;
+    SM_TRY(upload_steps(*d, p, m, order, s, &u));
+    SM_TRY(launch_count(*d, make_view(t, n), m, reinterpret_cast<const uint64_t *>(u.dev), tu,
+                        reinterpret_cast<unsigned long long *>(count_dev), nullptr, s));
+    return ring_commit(*d, u, s);
+}
+
+int64_t sm_report(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n, const int32_t *order,
+                  uint64_t *pos_dev, uint64_t cap)
+{
+    return report_sync(p, m, t, n, order, nullptr, pos_dev, cap, nullptr);
+}
+
+int64_t sm_report_ex(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n, const int32_t *order,
+                     const sm_params *params, uint64_t *pos_dev, uint64_t cap, void *stream)
+{
+    return report_sync(p, m, t, n, order, params, pos_dev, cap, reinterpret_cast<hipStream_t>(stream));
+}
+
+int32_t sm_count_batch(const sm_query *q, uint64_t nq, const sm_text *texts, uint64_t nt,
+                       uint64_t *counts_dev, const sm_params *params, void *stream)
+{
+    g_err.clear();
+    if (nq == 0)
+        return SM_OK;
+    if (!q || !counts_dev)
+        return fail(SM_EINVAL, "q or counts_dev is NULL");
+    if (nt > 0 && !texts)
+        return fail(SM_EINVAL, "texts is NULL");
+    for (uint64_t i = 0; i < nt; ++i) {
+        int rc = check_text(texts[i].t, texts[i].n);
+        if (rc < 0)
+            return fail(rc, "text " + std::to_string(i) + ": " + g_err);
+    }
+    for (uint64_t i = 0; i < nq; ++i) {
+        if (q[i].text_id >= nt)
+            return fail(SM_EINVAL, "query " + std::to_string(i) + ": text_id out of range");
+        if (q[i].flags != 0)
+            return fail(SM_EINVAL, "query " + std::to_string(i) + ": unknown flags");
+        int rc = check_pattern(q[i].p, q[i].m, q[i].order);
+        if (rc < 0)
+            return fail(rc, "query " + std::to_string(i) + ": " + g_err);
+    }
+    Dev *d;
+    SM_TRY(get_dev(&d));
+    std::lock_guard<std::mutex> lk(d->mu);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    unsigned long long *counts = reinterpret_cast<unsigned long long *>(counts_dev);
+    HIP_TRY(launch_fill_u64(counts, nq, 0ull, s));
+
+    const int cpl = (params && (params->tile_kib == 4 || params->tile_kib == 8 || params->tile_kib == 16))
+                        ? params->tile_kib / 4
+                        : 4;
+    const uint64_t T = 4096ull * cpl;
+    const int rdef = (params && params->peel > 0) ? std::min<int>(params->peel, (int)kMaxPeel) : 2;
+    const int wpc = (params && params->wgs_per_cu > 0) ? std::min(params->wgs_per_cu, 32) : 8;
+    const uint64_t target = (uint64_t)std::max(d->cus, 1) * (uint64_t)wpc;
+    const uint64_t max_halo = kMaxLds - T - kQChunk * sizeof(uint32_t);
+
+    // Split queries: staged (halo fits next to the tile) and long (global kernel).
+    std::vector<PlanQuery> staged, longq;
+    uint64_t total_steps = 0;
+    for (uint64_t i = 0; i < nq; ++i) {
+        const uint64_t n = texts[q[i].text_id].n;
+        if (q[i].m > n)
+            continue;  // count stays 0
+        PlanQuery pq{i, q[i].text_id, q[i].m, 0};
+        const uint64_t halo = halo_for(q[i].m);
+        uint64_t b = 64;
+        while (b < halo)
+            b <<= 1;
+        pq.bucket = (uint32_t)b;
+        if (halo <= max_halo)
+            staged.push_back(pq);
+        else
+            longq.push_back(pq);
+        total_steps += q[i].m + kStepPad;
+    }
+    std::stable_sort(staged.begin(), staged.end(), [](const PlanQuery &a, const PlanQuery &b) {
+        return a.text != b.text ? a.text < b.text : a.bucket < b.bucket;
+    });
+
+    // Chunks of one (text, bucket) and at most kQChunk queries.
+    struct Chunk {
+        uint32_t text;
+        uint32_t q0, q1;  // into `staged`
+        uint64_t m_min, m_max;
+    };
+    std::vector<Chunk> chunks;
+    for (uint32_t i = 0; i < staged.size();) {
+        uint32_t j = i;
+        uint64_t mn = staged[i].m, mx = staged[i].m;
+        while (j < staged.size() && j - i < kQChunk && staged[j].text == staged[i].text &&
+               staged[j].bucket == staged[i].bucket) {
+            mn = std::min(mn, staged[j].m);
+            mx = std::max(mx, staged[j].m);
+            ++j;
+        }
+        chunks.push_back({staged[i].text, i, j, mn, mx});
+        i = j;
+    }
+    uint64_t tile_work = 0;
+    for (auto &c : chunks) {
+        const uint64_t first = reinterpret_cast<uintptr_t>(texts[c.text].t) & 15u;
+        tile_work += ceil_div(first + texts[c.text].n - c.m_min + 1, T);
+    }
+    const uint64_t span = std::max<uint64_t>(1, std::min<uint64_t>(256, tile_work / (target * 4)));
+
+    std::vector<BatchItem> items;
+    uint32_t halo_max = 0;
+    for (auto &c : chunks) {
+        const sm_text &tx = texts[c.text];
+        const TextView tv = make_view(tx.t, tx.n);
+        const uint64_t ntiles = ceil_div(tv.first + tx.n - c.m_min + 1, T);
+        const uint32_t halo = halo_for(c.m_max);
+        halo_max = std::max(halo_max, halo);
+        for (uint64_t t0 = 0; t0 < ntiles; t0 += span) {
+            BatchItem it{};
+            it.tv = tv;
+            it.tile_begin = t0;
+            it.tile_end = std::min(ntiles, t0 + span);
+            it.q_begin = c.q0;
+            it.q_end = c.q1;
+            it.halo = halo;
+            items.push_back(it);
+        }
+    }
+
+    // One upload: [items | queries | steps].
+    const size_t items_bytes = round_up(items.size() * sizeof(BatchItem), 256);
+    const size_t queries_bytes = round_up(std::max<size_t>(staged.size(), 1) * sizeof(BatchQuery), 256);
+    const size_t long_off = items_bytes + queries_bytes;
+    const size_t bytes = long_off + total_steps * sizeof(uint64_t);
+    Upload u;
+    SM_TRY(ring_reserve(*d, bytes, &u));
+    BatchItem *hi = reinterpret_cast<BatchItem *>(u.host);
+    BatchQuery *hq = reinterpret_cast<BatchQuery *>(u.host + items_bytes);
+    uint64_t *hs = reinterpret_cast<uint64_t *>(u.host + long_off);
+    std::copy(items.begin(), items.end(), hi);
+    uint64_t soff = 0;
+    std::vector<int32_t> ord;
+    auto emit_steps = [&](uint64_t qi) -> uint64_t {
+        const sm_query &Q = q[qi];
+        const int32_t *o = Q.order;
+        if (!o) {
+            ord.resize(Q.m);
+            if (texts[Q.text_id].hist)
+                order_by_freq(Q.p, Q.m, texts[Q.text_id].hist, ord.data());
+            else
+                order_ltr(Q.m, ord.data());
+            o = ord.data();
+        }
+        build_steps(Q.p, Q.m, o, hs + soff);
+        const uint64_t at = soff;
+        soff += Q.m + kStepPad;
+        return at;
+    };
+    for (size_t i = 0; i < staged.size(); ++i) {
+        const PlanQuery &pq = staged[i];
+        const sm_text &tx = texts[pq.text];
+        BatchQuery bq{};
+        bq.steps_off = emit_steps(pq.idx);
+        bq.last = (reinterpret_cast<uintptr_t>(tx.t) & 15u) + tx.n - pq.m;
+        bq.m = (uint32_t)pq.m;
+        bq.r = (uint32_t)std::min<uint64_t>((uint64_t)rdef, pq.m);
+        bq.out = (uint32_t)pq.idx;
+        hq[i] = bq;
+    }
+    std::vector<uint64_t> long_steps_off;
+    for (auto &pq : longq)
+        long_steps_off.push_back(emit_steps(pq.idx));
+    SM_TRY(ring_copy(u, bytes, s));
+
+    if (!items.empty()) {
+        BatchArgs a{};
+        a.items = reinterpret_cast<const BatchItem *>(u.dev);
+        a.nitems = items.size();
+        a.queries = reinterpret_cast<const BatchQuery *>(u.dev + items_bytes);
+        a.steps = reinterpret_cast<const uint64_t *>(u.dev + long_off);
+        a.counts = counts;
+        a.tile_lds = (uint32_t)(T + halo_max);
+        const uint32_t lds = a.tile_lds + kQChunk * sizeof(uint32_t);
+        const uint64_t grid = std::min<uint64_t>(items.size(), target);
+        hipError_t e = launch_batch_staged(a, cpl, (unsigned)grid, lds, s);
+        if (e != hipSuccess) {
+            (void)ring_commit(*d, u, s);
+            return fail(SM_EDEVICE, std::string("batch launch: ") + hipGetErrorString(e));
+        }
+    }
+    for (size_t i = 0; i < longq.size(); ++i) {
+        const PlanQuery &pq = longq[i];
+        Tune tu{(int)std::min<uint64_t>((uint64_t)rdef, pq.m), 1, wpc};
+        int rc = launch_count(*d, make_view(texts[pq.text].t, texts[pq.text].n), pq.m,
+                              reinterpret_cast<const uint64_t *>(u.dev + long_off) + long_steps_off[i], tu,
+                              counts + pq.idx, nullptr, s);
+        if (rc < 0) {
+            std::string msg = g_err;
+            (void)ring_commit(*d, u, s);
+            return fail(rc, msg);
+        }
+    }
+    return ring_commit(*d, u, s);
+}
+
+}  // extern "C"

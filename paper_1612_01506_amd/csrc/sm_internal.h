@@ -1,0 +1,85 @@
+// Internal definitions shared by the kernels (sm_kernels.hip) and the C-ABI
+// host code (sm_api.hip).  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace smk {
+
+constexpr uint32_t kWG = 256;            // threads per workgroup: four wave64
+constexpr uint32_t kWaves = kWG / 64;
+constexpr uint32_t kBlock = 1024;        // starts per wave vector: 64 lanes x 4 dwords x 4 bytes
+constexpr uint32_t kMaxPeel = 8;         // largest peel factor r compiled in
+constexpr uint32_t kStepPad = 8;         // zero entries after every step table (one-ahead loads)
+constexpr uint32_t kMaxLds = 65536;      // dynamic LDS per workgroup used by the staged kernels
+constexpr uint32_t kQChunk = 512;        // queries per batch work item (LDS counters)
+
+// A text in aligned coordinates: coordinate u is the byte at address base + u.
+struct TextView {
+    const uint8_t *base;  // 16-byte aligned, <= t
+    uint64_t first;       // coordinate of t[0] (0..15)
+    uint64_t n;           // text length in bytes
+    uint64_t end16;       // first + n rounded up to 16: no chunk at or past it is loaded
+};
+
+// Step table entry, one per compare in compare order pi:
+//   bits  0..31  pattern position j = pi(l)
+//   bits 32..63  p[j] replicated into all four bytes
+// Tables are followed by kStepPad zero entries.
+
+struct CountArgs {
+    TextView tv;
+    uint64_t last;            // coordinate of the last valid start: first + n - m
+    uint64_t ntiles;          // staged: tiles covering coordinates [0, last]
+    uint64_t tiles_per_wg;    // staged: contiguous tiles per workgroup
+    uint64_t nblocks;         // ceil((last + 1) / kBlock)
+    const uint64_t *steps;    // device step table (m + kStepPad entries)
+    uint32_t m;
+    uint32_t halo;            // staged: LDS bytes past the tile (multiple of 16, >= m + 4)
+    unsigned long long *count;     // += total count (may be null)
+    uint32_t *block_counts;   // per wave-vector block counts (report pass), or null
+};
+
+struct BatchItem {
+    TextView tv;
+    uint64_t tile_begin, tile_end;  // tiles [tile_begin, tile_end) of the text
+    uint32_t q_begin, q_end;        // queries [q_begin, q_end), q_end - q_begin <= kQChunk
+    uint32_t halo;                  // LDS halo bytes for this item's queries
+    uint32_t pad;
+};
+
+struct BatchQuery {
+    uint64_t steps_off;  // index of the query's step table in the steps pool
+    uint64_t last;       // coordinate of its last valid start in its text
+    uint32_t m;
+    uint32_t r;          // peel factor, 1..min(kMaxPeel, m)
+    uint32_t out;        // output slot
+    uint32_t pad;
+};
+
+struct BatchArgs {
+    const BatchItem *items;
+    uint64_t nitems;
+    const BatchQuery *queries;
+    const uint64_t *steps;
+    unsigned long long *counts;
+    uint32_t tile_lds;   // LDS bytes for tile + largest halo; query counters follow
+    uint32_t pad;
+};
+
+// Host-side launchers (sm_kernels.hip).  Each returns a hipError_t.
+hipError_t launch_count_staged(const CountArgs &a, int cpl, int r, unsigned grid, hipStream_t s);
+hipError_t launch_count_global(const CountArgs &a, int r, unsigned grid, hipStream_t s);
+hipError_t launch_group_sums(const uint32_t *bc, uint64_t nblocks, uint64_t ngroups,
+                             unsigned long long *gs, hipStream_t s);
+hipError_t launch_scan_groups(const unsigned long long *gs, uint64_t ngroups, unsigned long long *go,
+                              unsigned long long *total, hipStream_t s);
+hipError_t launch_report_write(const CountArgs &a, const uint32_t *bc, const unsigned long long *go,
+                               uint64_t ngroups, unsigned long long *pos, uint64_t cap, unsigned grid,
+                               hipStream_t s);
+hipError_t launch_hist(const TextView &tv, unsigned long long *hist, unsigned grid, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v, hipStream_t s);
+hipError_t launch_batch_staged(const BatchArgs &a, int cpl, unsigned grid, uint32_t lds_bytes, hipStream_t s);
+
+}  // namespace smk

@@ -1,0 +1,91 @@
+"""C-ABI library checks that need no GPU: exports, argument validation, host-side orders."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1612_01506_amd as sm
+from paper_1612_01506_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    src = open(os.path.join(ROOT, "include", "sm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sm_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    syms = header_symbols()
+    assert syms, "no declarations parsed"
+    for name in syms:
+        assert hasattr(lib, name), name
+    assert set(syms) == set(_lib.EXPORTS)
+
+
+def test_version():
+    assert sm.version() == 10000
+
+
+def _err(rc):
+    assert rc < 0
+    return _lib.load().sm_last_error().decode()
+
+
+def test_validation_before_any_device_call():
+    lib = _lib.load()
+    p = np.frombuffer(b"abc", dtype=np.uint8)
+    # m == 0
+    assert "m must be" in _err(lib.sm_count(p.ctypes.data, 0, None, 0, None))
+    # p NULL
+    assert lib.sm_count(None, 3, None, 0, None) == _lib.SM_EINVAL
+    # order not a permutation
+    bad = np.array([0, 0, 2], dtype=np.int32)
+    assert "permutation" in _err(lib.sm_count(p.ctypes.data, 3, None, 0, bad.ctypes.data))
+    bad = np.array([0, 1, 3], dtype=np.int32)
+    assert "permutation" in _err(lib.sm_count(p.ctypes.data, 3, None, 0, bad.ctypes.data))
+    bad = np.array([0, -1, 2], dtype=np.int32)
+    assert "permutation" in _err(lib.sm_count(p.ctypes.data, 3, None, 0, bad.ctypes.data))
+    # m >= 2^32
+    assert "2^32" in _err(lib.sm_count(p.ctypes.data, 1 << 32, None, 0, None))
+    # t NULL with n > 0
+    assert "t is NULL" in _err(lib.sm_count(p.ctypes.data, 3, None, 10, None))
+    # report: pos NULL with cap > 0
+    assert lib.sm_report(p.ctypes.data, 3, None, 0, None, None, 5) == _lib.SM_EINVAL
+    # batch: NULL arrays
+    assert lib.sm_count_batch(None, 1, None, 0, None, None, None) == _lib.SM_EINVAL
+    # histogram: NULL output
+    assert lib.sm_histogram(None, 0, None, None) == _lib.SM_EINVAL
+
+
+def test_text_must_be_device_memory():
+    """A host pointer as text is rejected (needs the HIP runtime, which may be absent here)."""
+    lib = _lib.load()
+    p = np.frombuffer(b"abc", dtype=np.uint8)
+    t = np.frombuffer(b"xxabcxx", dtype=np.uint8)
+    rc = lib.sm_count(p.ctypes.data, 3, t.ctypes.data, t.size, None)
+    assert rc in (_lib.SM_EINVAL, _lib.SM_EDEVICE)
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 7, 64, 1000])
+def test_library_orders_match_oracle(m):
+    g = np.random.default_rng(m)
+    p = g.integers(0, 256, size=m, dtype=np.uint8).tobytes()
+    p = bytes(b if g.random() > 0.2 else 0x20 for b in p)
+    h = g.integers(0, 30, size=256).astype(np.uint64)
+    assert sm.order("freq", p, h).tolist() == oracle.order_freq(p, h).tolist()
+    assert sm.order("h", p).tolist() == oracle.order_h(m).tolist()
+    assert sm.order("hs", p).tolist() == oracle.order_hs(p).tolist()
+    assert sm.order("ltr", p).tolist() == list(range(m))
+
+
+def test_order_errors():
+    with pytest.raises(sm.SmError):
+        sm.order("freq", b"abc")          # needs a histogram
+    with pytest.raises(ValueError):
+        sm.order("h", b"")

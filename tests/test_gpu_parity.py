@@ -1,0 +1,276 @@
+"""GPU parity: every C-ABI entry point against the CPU oracle, element by element, bit exact.
+
+Sizes span several 4/8/16 KiB tiles and 1024-start wave vectors with ragged
+tails; text pointers are deliberately misaligned; patterns cover the peel
+factors, the compare orders, LDS-staged and global (long) kernels.
+"""
+import itertools
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+sm = pytest.importorskip("paper_1612_01506_amd")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def to_dev(a: np.ndarray, dev, offset: int = 0) -> torch.Tensor:
+    """Device copy of a whose data pointer is `offset` bytes past a 256-byte boundary."""
+    buf = torch.empty(a.size + offset + 64, dtype=torch.uint8, device=dev)
+    v = buf[offset:offset + a.size]
+    if a.size:
+        v.copy_(torch.from_numpy(np.ascontiguousarray(a)))
+    return v
+
+
+def rand_text(n, sigma, seed):
+    g = np.random.default_rng(seed)
+    if sigma == 256:
+        return g.integers(0, 256, size=n, dtype=np.uint8)
+    alpha = np.frombuffer(synth.ALPHABETS[sigma], dtype=np.uint8)
+    return alpha[g.integers(0, sigma, size=n)]
+
+
+def pick_pattern(t, m, g, planted=True):
+    if planted and t.size >= m:
+        o = int(g.integers(0, t.size - m + 1))
+        return bytes(t[o:o + m])
+    return bytes(g.integers(0, 256, size=m, dtype=np.uint8))
+
+
+# ------------------------------------------------------------------ worked example
+def test_fig1_prefix(dev):
+    t = to_dev(np.frombuffer(b"aabcd", dtype=np.uint8), dev)
+    assert sm.count(t, b"abcd") == 1
+    assert sm.count(t, b"abcd", order="freq") == 1
+    assert sm.report(t, b"abcd").tolist() == [1]
+    assert sm.report(t, b"a").tolist() == [0, 1]
+
+
+# ------------------------------------------------------------------ tiny exhaustive
+def test_exhaustive_binary_via_batch(dev):
+    """All {a,b} texts with n <= 8 against all patterns with m <= 4, as one batch."""
+    texts_h = [bytes(x) for n in range(1, 9) for x in itertools.product(b"ab", repeat=n)]
+    pats = [bytes(x) for m in range(1, 5) for x in itertools.product(b"ab", repeat=m)]
+    texts = [to_dev(np.frombuffer(t, dtype=np.uint8), dev, offset=i % 16) for i, t in enumerate(texts_h)]
+    queries = [(i, p) for i in range(len(texts_h)) for p in pats]
+    got = sm.count_batch(texts, queries).cpu().numpy()
+    want = [sum(1 for s in range(len(texts_h[i]) - len(p) + 1) if texts_h[i][s:s + len(p)] == p)
+            for i, p in queries]
+    assert got.tolist() == want
+    # a sample through the single-search path too
+    for i in range(0, len(queries), 97):
+        ti, p = queries[i]
+        assert sm.count(texts[ti], p) == want[i]
+
+
+# ------------------------------------------------------------ single search sweep
+SIZES = [1, 15, 16, 17, 1000, 1023, 1024, 1025, 4095, 4096, 4097, 16383, 16384, 16385,
+         3 * 16384 + 777, 200_003]
+MS = [1, 2, 3, 4, 5, 7, 8, 16, 31, 64, 100, 257, 1000]
+
+
+@pytest.mark.parametrize("sigma", [2, 4, 95, 256])
+def test_count_sweep(dev, sigma):
+    g = np.random.default_rng(1000 + sigma)
+    for n in SIZES:
+        t = rand_text(n, sigma, n * 7 + sigma)
+        off = int(g.integers(0, 16))
+        td = to_dev(t, dev, off)
+        for m in MS:
+            if m > n + 1:
+                continue
+            p = pick_pattern(t, m, g, planted=(m <= n and g.random() < 0.8))
+            want = oracle.count(p, t)
+            for order in ("ltr", "freq", "h"):
+                got = sm.count(td, p, order=order, peel=int(g.integers(1, 9)))
+                assert got == want, (sigma, n, off, m, order, got, want)
+
+
+@pytest.mark.parametrize("tile_kib", [4, 8, 16])
+@pytest.mark.parametrize("peel", [1, 2, 3, 5, 8])
+def test_count_tiles_and_peels(dev, tile_kib, peel):
+    g = np.random.default_rng(tile_kib * 10 + peel)
+    t = rand_text(300_001, 4, 99)
+    td = to_dev(t, dev, 5)
+    for m in (1, 2, 6, 12, 33, 300, 5000):
+        p = pick_pattern(t, m, g)
+        want = oracle.count(p, t)
+        perm = g.permutation(m).astype(np.int32)
+        assert sm.count(td, p, order=perm, peel=peel, tile_kib=tile_kib) == want
+        assert sm.count(td, p, order="freq", peel=peel, tile_kib=tile_kib, wgs_per_cu=1) == want
+
+
+@pytest.mark.parametrize("offset", range(16))
+def test_misaligned_text(dev, offset):
+    t = rand_text(70_000 + offset * 13, 2, offset)
+    td = to_dev(t, dev, offset)
+    g = np.random.default_rng(offset)
+    for m in (1, 4, 9, 17, 40):
+        p = pick_pattern(t, m, g)
+        assert sm.count(td, p) == oracle.count(p, t)
+    # matches at the very first and very last start
+    p0, pl = bytes(t[:11]), bytes(t[-11:])
+    assert sm.report(td, p0)[:1].tolist() == [0]
+    assert sm.report(td, pl)[-1:].tolist() == [t.size - 11]
+
+
+def test_extreme_bytes(dev):
+    g = np.random.default_rng(5)
+    t = np.array([0x00, 0x7F, 0x80, 0xFF, 0x01, 0xFE], dtype=np.uint8)[g.integers(0, 6, size=50_000)]
+    td = to_dev(t, dev, 3)
+    for m in (1, 2, 3, 5, 8, 13):
+        for _ in range(3):
+            p = pick_pattern(t, m, g)
+            assert sm.count(td, p, order="freq") == oracle.count(p, t)
+            assert np.array_equal(sm.report(td, p).cpu().numpy().astype(np.uint64), oracle.report(p, t))
+
+
+# --------------------------------------------------------------------- degenerate
+def test_degenerate(dev):
+    t = to_dev(np.frombuffer(b"abcabc", dtype=np.uint8), dev)
+    assert sm.count(t, b"abcabca") == 0                       # m > n
+    assert sm.count(t, b"abcabc") == 1                        # m == n
+    assert sm.count(t[:0], b"a") == 0                         # n == 0
+    assert sm.report(t, b"abcabca").numel() == 0
+    with pytest.raises(sm.SmError):
+        sm.count(t, b"")
+    with pytest.raises(sm.SmError):
+        sm.count(t, b"abc", order=[0, 0, 1])
+
+
+# ------------------------------------------------------------------ closed forms
+@pytest.mark.parametrize("n", [1, 1000, 65_536, 1_000_003])
+def test_unary_closed_forms(dev, n):
+    td = torch.full((n,), ord("a"), dtype=torch.uint8, device=dev)
+    for k in (1, 2, 16, 256, 4096):
+        want = max(0, n - k + 1)
+        for order in ("ltr", "freq"):
+            assert sm.count(td, b"a" * k, order=order) == want
+            assert sm.count(td, b"a" * (k - 1) + b"b", order=order) == 0
+
+
+@pytest.mark.parametrize("unit", [b"ab", b"abc", b"aab", b"GATTACA", b"abcabd"])
+def test_periodic_closed_forms(dev, unit):
+    n = 123_457
+    L = len(unit)
+    td = to_dev(synth.periodic_text(n, unit), dev, 7)
+    for o in range(L):
+        for m in (L, L + 1, 3 * L + 2, 40 * L):
+            p = (unit * (m // L + 3))[o:o + m]
+            want = (n - m - o) // L + 1 if n >= m + o else 0
+            assert sm.count(td, p, order="freq") == want
+
+
+# ------------------------------------------------------------------------ report
+@pytest.mark.parametrize("sigma", [2, 4, 95])
+def test_report_parity(dev, sigma):
+    g = np.random.default_rng(sigma)
+    for n in (17, 1025, 16385, 100_000, 1_048_583):
+        t = rand_text(n, sigma, n + sigma)
+        td = to_dev(t, dev, n % 16)
+        for m in (1, 2, 5, 12, 64, 700):
+            if m > n:
+                continue
+            p = pick_pattern(t, m, g)
+            want = oracle.report(p, t)
+            got = sm.report(td, p, order="freq").cpu().numpy().astype(np.uint64)
+            assert np.array_equal(got, want), (sigma, n, m)
+
+
+def test_report_dense_and_cap(dev):
+    n = 300_000
+    td = torch.full((n,), ord("a"), dtype=torch.uint8, device=dev)
+    pos, total = sm.report(td, b"aa", return_count=True)
+    assert total == n - 1
+    assert torch.equal(pos.cpu(), torch.arange(n - 1, dtype=torch.int64))
+    head, total = sm.report(td, b"aaa", cap=1000, return_count=True)
+    assert total == n - 2 and head.tolist() == list(range(1000))
+
+
+def test_report_long_pattern(dev):
+    n = 400_000
+    t = rand_text(n, 2, 3)
+    p = bytes(t[1000:1000 + 70_000])  # halo beyond LDS: global kernels
+    td = to_dev(t, dev, 1)
+    assert sm.count(td, p) == oracle.count(p, t)
+    assert np.array_equal(sm.report(td, p).cpu().numpy().astype(np.uint64), oracle.report(p, t))
+    u = torch.full((n,), 7, dtype=torch.uint8, device=dev)
+    assert sm.count(u, bytes([7]) * 70_000) == n - 70_000 + 1
+
+
+# --------------------------------------------------------------------- histogram
+@pytest.mark.parametrize("n", [0, 1, 15, 16, 17, 4096, 100_001, 5_000_000])
+def test_histogram(dev, n):
+    t = rand_text(n, 256, n)
+    td = to_dev(t, dev, n % 16)
+    h = sm.histogram(td).cpu().numpy()
+    assert h.tolist() == np.bincount(t, minlength=256).tolist()
+
+
+# ------------------------------------------------------------------------ batch
+def test_batch_mixed(dev):
+    g = np.random.default_rng(77)
+    texts_h = [rand_text(n, s, i) for i, (n, s) in enumerate(
+        [(50_000, 4), (1_000_003, 95), (17, 2), (300_000, 256), (70_001, 20)])]
+    texts = [sm.Text(to_dev(t, dev, i * 3 % 16)) for i, t in enumerate(texts_h)]
+    queries, want = [], []
+    for k in range(600):
+        ti = int(g.integers(0, len(texts_h)))
+        t = texts_h[ti]
+        m = int(synth.loguniform_ints(1, 2048, 1, g)[0])
+        p = pick_pattern(t, m, g, planted=g.random() < 0.7)
+        order = [None, "ltr", "freq", "h"][k % 4]
+        queries.append((ti, p, order))
+        want.append(oracle.count(p, t))
+    # a few long ones (global kernel) and empty-result ones
+    queries.append((1, bytes(texts_h[1][10:10 + 60_000]), None))
+    want.append(oracle.count(queries[-1][1], texts_h[1]))
+    queries.append((2, b"x" * 100, None))
+    want.append(0)
+    got = sm.count_batch(texts, queries).cpu().numpy().tolist()
+    assert got == want
+    got2 = sm.count_batch(texts, queries, tile_kib=4, peel=3).cpu().numpy().tolist()
+    assert got2 == want
+    single = [sm.count(texts[q[0]], q[1]) for q in queries[:50]]
+    assert single == want[:50]
+
+
+def test_batch_validation(dev):
+    td = to_dev(np.frombuffer(b"abc", dtype=np.uint8), dev)
+    with pytest.raises(sm.SmError, match="query 1"):
+        sm.count_batch([td], [(0, b"a"), (1, b"b")])
+    with pytest.raises(sm.SmError, match="query 0"):
+        sm.count_batch([td], [(0, b"")])
+
+
+def test_count_async_accumulates(dev):
+    t = rand_text(500_000, 4, 1)
+    td = to_dev(t, dev)
+    out = torch.zeros(1, dtype=torch.int64, device=dev)
+    pats = [bytes(t[i * 1000:i * 1000 + 8]) for i in range(10)]
+    for p in pats:
+        sm.count_async(td, p, out, order="freq")
+    torch.cuda.synchronize()
+    assert int(out.item()) == sum(oracle.count(p, t) for p in pats)
+
+
+def test_deterministic(dev):
+    t = rand_text(2_000_000, 2, 11)
+    td = to_dev(t, dev)
+    p = bytes(t[5:25])
+    a = sm.report(td, p, order="freq").cpu()
+    b = sm.report(td, p, order="freq").cpu()
+    assert torch.equal(a, b)
+    assert bool((a[1:] > a[:-1]).all())
