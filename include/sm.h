@@ -61,7 +61,7 @@ extern "C" {
 typedef struct sm_params {
     int32_t peel;       /* r: compares done before the first zero test, 1..8 (Section 2.3); default 2 */
     int32_t tile_kib;   /* text bytes staged per workgroup tile: 4, 8 or 16 KiB; default by n      */
-    int32_t wgs_per_cu; /* workgroups per compute unit the grid is sized for, 1..32; default 8     */
+    int32_t wgs_per_cu; /* workgroups per compute unit the grid is sized for, 1..32; default 6     */
     int32_t flags;      /* reserved, must be 0                                                     */
 } sm_params;
 
@@ -124,6 +124,31 @@ int64_t sm_report(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n, co
 /* sm_report with tuning (params may be NULL) on `stream`; synchronous. */
 int64_t sm_report_ex(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n, const int32_t *order,
                      const sm_params *params, uint64_t *pos_dev, uint64_t cap, void *stream);
+
+/* ---------------------------------------------------- prepared patterns */
+
+/* A set of patterns whose step tables (pattern position and symbol per
+ * compare, in compare order pi) are built and copied to the device once, so
+ * that later searches issue no host-to-device copy (and can be captured in a
+ * HIP graph).  Created and destroyed synchronously on the current device. */
+typedef struct sm_patterns sm_patterns;
+
+/* np patterns: p[i] (host, m[i] bytes) with compare order order[i] (host
+ * permutation, or NULL = left to right; `order` itself may be NULL).  All
+ * patterns are validated before anything is allocated. */
+int32_t sm_patterns_create(uint64_t np, const uint8_t *const *p, const uint64_t *m,
+                           const int32_t *const *order, sm_patterns **out);
+
+int32_t sm_patterns_destroy(sm_patterns *ps);
+
+/* Count of pattern i of the set in t, ADDED to *count_dev (device uint64);
+ * asynchronous on `stream`, no host-device copy. */
+int32_t sm_patterns_count(const sm_patterns *ps, uint64_t i, const uint8_t *t, uint64_t n,
+                          const sm_params *params, uint64_t *count_dev, void *stream);
+
+/* Report of pattern i of the set (as sm_report_ex); synchronous on `stream`. */
+int64_t sm_patterns_report(const sm_patterns *ps, uint64_t i, const uint8_t *t, uint64_t n,
+                           const sm_params *params, uint64_t *pos_dev, uint64_t cap, void *stream);
 
 /* -------------------------------------------------------------- batches */
 

@@ -24,8 +24,8 @@ import torch
 from ._lib import (SM_ORDER_FREQ, SM_ORDER_H, SM_ORDER_HS, SM_ORDER_LTR, SmError, check, load,
                    sm_params, sm_query, sm_text)
 
-__all__ = ["Text", "SmError", "histogram", "order", "count", "count_async", "report", "count_batch",
-           "version", "device_cus"]
+__all__ = ["Text", "Patterns", "SmError", "histogram", "order", "count", "count_async", "report",
+           "count_batch", "version", "device_cus"]
 
 ORDER_KINDS = {"ltr": SM_ORDER_LTR, "freq": SM_ORDER_FREQ, "h": SM_ORDER_H, "hs": SM_ORDER_HS}
 
@@ -219,3 +219,61 @@ def count_batch(texts: Sequence, queries: Iterable, peel=None, tile_kib=None, wg
     check(load().sm_count_batch(qarr, len(qs), tarr, len(texts), out.data_ptr(),
                                 _params(peel, tile_kib, wgs_per_cu), _stream(stream)))
     return out[:len(qs)]
+
+
+# ------------------------------------------------------------- prepared patterns
+class Patterns:
+    """Patterns whose step tables are uploaded to the device once (sm_patterns_*).
+
+    Searches through a Patterns object issue no host-to-device copy, so they can
+    run back to back on a stream (or inside a captured graph).
+    """
+
+    def __init__(self, patterns, orders=None):
+        pats = [_pat(p) for p in patterns]
+        n = len(pats)
+        self.m = [int(p.size) for p in pats]
+        ords = [None] * n if orders is None else [
+            None if o is None else np.ascontiguousarray(np.asarray(o, dtype=np.int32)) for o in orders]
+        if len(ords) != n:
+            raise ValueError("one order per pattern")
+        parr = (ctypes.c_void_p * max(n, 1))(*[_ptr(p) for p in pats])
+        marr = (ctypes.c_uint64 * max(n, 1))(*self.m)
+        oarr = (ctypes.c_void_p * max(n, 1))(*[_ptr(o) for o in ords])
+        h = ctypes.c_void_p()
+        check(load().sm_patterns_create(n, parr, marr, oarr, ctypes.byref(h)))
+        self._h = h
+
+    def __len__(self):
+        return len(self.m)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            check(load().sm_patterns_destroy(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def count_async(self, i: int, t, out: torch.Tensor, peel=None, tile_kib=None, wgs_per_cu=None,
+                    stream=None) -> None:
+        """ADD the count of pattern i in t to out[0] (device int64), asynchronously."""
+        ptr, n = _dev_text(t)
+        check(load().sm_patterns_count(self._h, i, ptr, n, _params(peel, tile_kib, wgs_per_cu),
+                                       out.data_ptr(), _stream(stream)))
+
+    def count(self, i: int, t, **kw) -> int:
+        dev = t.t.device if isinstance(t, Text) else t.device
+        out = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.count_async(i, t, out, **kw)
+        return int(out.item())
+
+    def report(self, i: int, t, out: torch.Tensor, peel=None, tile_kib=None, wgs_per_cu=None,
+               stream=None) -> int:
+        """Write up to out.numel() increasing positions of pattern i into out; return the full count."""
+        ptr, n = _dev_text(t)
+        return check(load().sm_patterns_report(self._h, i, ptr, n, _params(peel, tile_kib, wgs_per_cu),
+                                               out.data_ptr(), out.numel(), _stream(stream)))

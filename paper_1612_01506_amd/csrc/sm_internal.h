@@ -14,6 +14,7 @@ constexpr uint32_t kMaxPeel = 8;         // largest peel factor r compiled in
 constexpr uint32_t kStepPad = 8;         // zero entries after every step table (one-ahead loads)
 constexpr uint32_t kMaxLds = 65536;      // dynamic LDS per workgroup used by the staged kernels
 constexpr uint32_t kQChunk = 512;        // queries per batch work item (LDS counters)
+constexpr uint32_t kGroupBlocks = 1024;  // wave vectors per report scan group
 
 // A text in aligned coordinates: coordinate u is the byte at address base + u.
 struct TextView {
@@ -32,7 +33,8 @@ struct CountArgs {
     TextView tv;
     uint64_t last;            // coordinate of the last valid start: first + n - m
     uint64_t ntiles;          // staged: tiles covering coordinates [0, last]
-    uint64_t tiles_per_wg;    // staged: contiguous tiles per workgroup
+    uint32_t chunk_log2;      // staged: tiles are dealt out in chunks of 2^chunk_log2 contiguous tiles,
+    uint32_t pad0;            //   chunk c to workgroup c mod gridDim.x
     uint64_t nblocks;         // ceil((last + 1) / kBlock)
     const uint64_t *steps;    // device step table (m + kStepPad entries)
     uint32_t m;
@@ -71,13 +73,14 @@ struct BatchArgs {
 // Host-side launchers (sm_kernels.hip).  Each returns a hipError_t.
 hipError_t launch_count_staged(const CountArgs &a, int cpl, int r, unsigned grid, hipStream_t s);
 hipError_t launch_count_global(const CountArgs &a, int r, unsigned grid, hipStream_t s);
-hipError_t launch_group_sums(const uint32_t *bc, uint64_t nblocks, uint64_t ngroups,
-                             unsigned long long *gs, hipStream_t s);
+hipError_t launch_group_sums(const uint32_t *bc, uint64_t nblocks, uint64_t ngroups, unsigned long long *gs,
+                             unsigned grid, hipStream_t s);
 hipError_t launch_scan_groups(const unsigned long long *gs, uint64_t ngroups, unsigned long long *go,
                               unsigned long long *total, hipStream_t s);
-hipError_t launch_report_write(const CountArgs &a, const uint32_t *bc, const unsigned long long *go,
-                               uint64_t ngroups, unsigned long long *pos, uint64_t cap, unsigned grid,
-                               hipStream_t s);
+hipError_t launch_report_write(const CountArgs &a, uint32_t r, const uint32_t *bc, const unsigned long long *gs,
+                               const unsigned long long *go, uint64_t ngroups, unsigned long long *pos, uint64_t cap,
+                               uint32_t win, unsigned grid, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n, hipStream_t s);
 hipError_t launch_hist(const TextView &tv, unsigned long long *hist, unsigned grid, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_batch_staged(const BatchArgs &a, int cpl, unsigned grid, uint32_t lds_bytes, hipStream_t s);

@@ -39,6 +39,11 @@ __device__ __forceinline__ uint32_t step_rep(uint64_t st) { return (uint32_t)(st
 
 // Initial found for the wave vector at coordinate wb: starts outside
 // [first, last] are dead (byte 0xFF); all others alive (0).
+__device__ __forceinline__ uint32_t bytes_below(uint32_t c)  // low c bytes set, c in 0..4
+{
+    return c >= 4u ? 0xFFFFFFFFu : (1u << (8u * c)) - 1u;
+}
+
 __device__ __forceinline__ void init_alive(uint64_t wb, uint64_t first, uint64_t last, uint32_t lane,
                                            uint32_t (&d)[4])
 {
@@ -46,17 +51,16 @@ __device__ __forceinline__ void init_alive(uint64_t wb, uint64_t first, uint64_t
         d[0] = d[1] = d[2] = d[3] = 0u;
         return;
     }
+    // valid offsets within the vector: [lo, hi] (wave uniform, 32-bit)
+    const uint32_t lo = first > wb ? (uint32_t)(first - wb) : 0u;
+    const int64_t hi64 = (int64_t)last - (int64_t)wb;
+    const int32_t hi = hi64 > (int64_t)kBlock ? (int32_t)kBlock : (int32_t)hi64;  // may be negative
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const uint64_t u0 = wb + 256u * k + 4u * lane;
-        uint32_t inv = 0;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const uint64_t u = u0 + b;
-            if (u < first || u > last)
-                inv |= 0xFFu << (8 * b);
-        }
-        d[k] = inv;
+        const int32_t q = (int32_t)(256u * k + 4u * lane);
+        const int32_t cl = min(max((int32_t)lo - q, 0), 4), ch = min(max(hi - q + 1, 0), 4);
+        const uint32_t valid = bytes_below((uint32_t)ch) & ~bytes_below((uint32_t)cl);
+        d[k] = ~valid;
     }
 }
 
@@ -137,45 +141,149 @@ __device__ __forceinline__ uint32_t lanes_below(unsigned long long mask)
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// Text sources for the compare steps of one wave vector.
+// LdsText: the vector's window is staged in LDS; vb = byte 0 of the vector.
+struct LdsText {
+    const uint8_t *vb;
+    const uint8_t *lb;  // vb + 4 * lane
+    __device__ __forceinline__ void step(uint64_t st, uint32_t (&d)[4]) const { step_lds(lb, st, d); }
+    __device__ __forceinline__ uint32_t byte(uint32_t rel) const { return vb[rel]; }
+};
+
+// GlobalText: the window is read from global memory; wb = coordinate of the vector.
+struct GlobalText {
+    const TextView *tv;
+    uint64_t wb;
+    uint64_t lu;  // wb + 4 * lane
+    __device__ __forceinline__ void step(uint64_t st, uint32_t (&d)[4]) const { step_global(*tv, lu, st, d); }
+    __device__ __forceinline__ uint32_t byte(uint32_t rel) const
+    {
+        const uint64_t u = wb + rel;
+        return u < tv->end16 ? (uint32_t)tv->base[u] : 0u;
+    }
+};
+
+constexpr uint32_t kTestEach = 4;   // tail compares each followed by a zero test
+constexpr uint32_t kGroup = 8;      // later tail compares per zero test
+constexpr uint32_t kVerifyMin = 64; // remaining compares from which lone candidates are verified across lanes
+constexpr uint32_t kVerifyMax = 4;  // most alive starts verified one at a time
+
+__device__ __forceinline__ uint32_t wave_min32(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v = min(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    return v;
+}
+
+// Verify each alive start of the vector on compares l..m-1, 64 compares at
+// a time across the lanes (a mismatch in any lane ends that start).  The
+// AND over the remaining compares is the same; it is only grouped by start
+// instead of by compare.  Starts are visited in increasing offset `rel`
+// (256k + 4 * lane + byte) through a wave-uniform cursor; a start that fails
+// gets its byte of d set nonzero.  Leaves d final.
+template <typename Text>
+__device__ __forceinline__ void verify_candidates(const uint64_t *steps, uint32_t l, uint32_t m, uint32_t lane,
+                                                  uint32_t (&d)[4], const Text &tx)
+{
+    uint32_t cursor = 0;
+    while (true) {
+        uint32_t best = 0xFFFFFFFFu;
+#pragma unroll
+        for (int k = 3; k >= 0; --k) {
+            const uint32_t base = 256u * k + 4u * lane;
+            uint32_t z = zero_bytes(d[k]);
+            if (cursor > base)
+                z = cursor - base >= 4u ? 0u : z & (0xFFFFFFFFu << (8 * (cursor - base)));
+            if (z)
+                best = base + ((uint32_t)__builtin_ctz(z) >> 3);
+        }
+        best = wave_min32(best);
+        if (best == 0xFFFFFFFFu)
+            break;
+        bool ok = true;
+        for (uint32_t b0 = l; b0 < m; b0 += 64u) {
+            const uint32_t idx = b0 + lane;
+            bool bad = false;
+            if (idx < m) {
+                const uint64_t st = steps[idx];
+                bad = tx.byte(best + step_pos(st)) != (step_rep(st) & 0xFFu);
+            }
+            if (__any(bad)) {
+                ok = false;
+                break;
+            }
+        }
+        if (!ok && lane == ((best & 255u) >> 2)) {
+            const uint32_t k = best >> 8, dead = 0xFFu << (8 * (best & 3u));
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+                if ((uint32_t)kk == k)
+                    d[kk] |= dead;
+        }
+        cursor = best + 1u;
+    }
+}
+
+// Compares l..m-1 for a vector still alive after the peel.  The first
+// kTestEach are each followed by the zero test of Algorithm 4; later ones go
+// in groups of kGroup per test, so a lone long survivor does not serialise on
+// one load-compare-test round trip per compare.  Returns false if the vector
+// died; otherwise d is final (byte == 0 exactly at the matching starts).
+template <typename Text>
+__device__ __forceinline__ bool search_tail(const uint64_t *steps, uint32_t l, uint32_t m, uint32_t lane,
+                                            uint32_t (&d)[4], const Text &tx)
+{
+    const uint32_t l1 = min(m, l + kTestEach);
+    for (; l < l1; ++l) {
+        tx.step(steps[l], d);
+        if (!any_alive(d))
+            return false;
+    }
+    while (l < m) {
+        if (m - l >= kVerifyMin) {
+            const uint32_t alive = wave_sum32(count_alive(d));
+            if (alive <= kVerifyMax) {
+                verify_candidates(steps, l, m, lane, d, tx);
+                return true;
+            }
+        }
+        const uint32_t g = min(kGroup, m - l);
+#pragma unroll 1
+        for (uint32_t u = 0; u < g; ++u)
+            tx.step(steps[l + u], d);
+        l += g;
+        if (!any_alive(d))
+            return false;
+    }
+    return true;
+}
+
 // Algorithm 4 over one wave vector with a compile-time peel factor R (R <= m):
-// R unconditional compares, a zero test, then compare-and-test for the rest.
-// Returns this lane's share of popcount(found) (0 when the vector died).
-template <int R, typename Step>
-__device__ __forceinline__ uint32_t search_vector(const uint64_t *steps, const uint64_t (&pk)[R], uint32_t m,
-                                                  uint32_t (&d)[4], Step step)
+// R unconditional compares, a zero test, then the tail.  Returns whether any
+// start survived; d is then final.
+template <int R, typename Text>
+__device__ __forceinline__ bool search_vector(const uint64_t *steps, const uint64_t (&pk)[R], uint32_t m,
+                                              uint32_t lane, uint32_t (&d)[4], const Text &tx)
 {
 #pragma unroll
     for (int l = 0; l < R; ++l)
-        step(pk[l], d);
+        tx.step(pk[l], d);
     if (!any_alive(d))
-        return 0;
-    uint64_t nxt = steps[R];
-    for (uint32_t l = R; l < m; ++l) {
-        const uint64_t cur = nxt;
-        nxt = steps[l + 1];  // padded table: in bounds
-        step(cur, d);
-        if (!any_alive(d))
-            return 0;
-    }
-    return count_alive(d);
+        return false;
+    return search_tail(steps, R, m, lane, d, tx);
 }
 
-// Same with a run-time peel factor (batch queries carry their own r).
-template <typename Step>
-__device__ __forceinline__ uint32_t search_vector_rt(const uint64_t *steps, uint32_t r, uint32_t m,
-                                                     uint32_t (&d)[4], Step step)
+// Same with a run-time peel factor r (batch queries carry their own r).
+template <typename Text>
+__device__ __forceinline__ bool search_vector_rt(const uint64_t *steps, uint32_t r, uint32_t m, uint32_t lane,
+                                                 uint32_t (&d)[4], const Text &tx)
 {
-    uint32_t l = 0;
-    for (; l < r; ++l)
-        step(steps[l], d);
+    for (uint32_t l = 0; l < r; ++l)
+        tx.step(steps[l], d);
     if (!any_alive(d))
-        return 0;
-    for (; l < m; ++l) {
-        step(steps[l], d);
-        if (!any_alive(d))
-            return 0;
-    }
-    return count_alive(d);
+        return false;
+    return search_tail(steps, r, m, lane, d, tx);
 }
 
 // ------------------------------------------------------------- tile staging
@@ -238,38 +346,74 @@ __device__ __forceinline__ void wg_add_count(unsigned long long acc, unsigned lo
 
 // ----------------------------------------------------------- count kernels
 
-// Single search, text staged in LDS.  Workgroup g searches tiles
-// [g * tiles_per_wg, (g + 1) * tiles_per_wg); wave w takes vectors
-// w*CPL .. w*CPL + CPL - 1 of each tile.
+// Asynchronous tile load straight into LDS (global_load_lds_dwordx4): lane
+// i of a wave writes its 16 bytes at the wave-uniform LDS base + 16 * i.
+// Chunks at or past end16 are skipped; their LDS bytes keep stale values,
+// which only ever meet dead (out-of-text) starts.
+__device__ __forceinline__ void dma16(const TextView &tv, uint64_t u, uint8_t *lds_wave_base)
+{
+    if (u < tv.end16)
+        __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(tv.base + u),
+                                         (__attribute__((address_space(3))) void *)(lds_wave_base),
+                                         16, 0, 0);
+}
+
+// Issues the loads of tile [ts, ts + T) and its halo [ts + T, ts + T + 16 * hch)
+// into the LDS buffer buf.
+template <int CPL>
+__device__ __forceinline__ void dma_tile(const TextView &tv, uint64_t ts, uint32_t tid, uint32_t hch, uint8_t *buf)
+{
+    constexpr uint32_t T = kWG * 16u * CPL;
+    const uint32_t wbase = tid & ~63u, lane = tid & 63u;
+#pragma unroll
+    for (int c = 0; c < CPL; ++c)
+        dma16(tv, ts + 16ull * (tid + kWG * c), buf + 16u * (wbase + kWG * c));
+    for (uint32_t ch = tid; ch < hch; ch += kWG)
+        dma16(tv, ts + T + 16ull * ch, buf + T + 16u * (ch - lane));
+}
+
+__device__ __forceinline__ void wait_dma()
+{
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's LDS loads have landed
+}
+
+// Single search, text staged in LDS.  Tiles are dealt out in chunks of
+// 2^chunk_log2 contiguous tiles, chunk c to workgroup c mod G, so the tiles in
+// flight at any moment form a nearly contiguous window of the text (even HBM
+// channel load) while a halo is still mostly the start of the tile the same
+// workgroup loads next.  Wave w takes vectors w*CPL .. w*CPL + CPL - 1 of each
+// tile.  Two LDS buffers of T + halo bytes: the loads of the next tile are in
+// flight while the current one is searched.
 template <int CPL, int R>
 __global__ __launch_bounds__(kWG) void k_count_staged(CountArgs a)
 {
     extern __shared__ __align__(16) uint8_t lds[];
     constexpr uint32_t T = kWG * 16u * CPL;
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
-    const uint64_t t0 = (uint64_t)blockIdx.x * a.tiles_per_wg;
-    const uint64_t t1 = min(t0 + a.tiles_per_wg, a.ntiles);
     const uint32_t hch = a.halo >> 4;
+    const uint32_t TB = T + a.halo;
+    const uint64_t kmask = (1ull << a.chunk_log2) - 1u;
+    auto tile_of = [&](uint64_t i) {
+        return (((uint64_t)blockIdx.x + (i >> a.chunk_log2) * gridDim.x) << a.chunk_log2) + (i & kmask);
+    };
 
     uint64_t pk[R];
 #pragma unroll
     for (int l = 0; l < R; ++l)
         pk[l] = a.steps[l];
 
-    uint4 pre[CPL];
-    uint4 hpre = make_uint4(0, 0, 0, 0);
     unsigned long long acc = 0;
-    if (t0 < t1)
-        fetch_tile<CPL>(a.tv, t0 * T, tid, hch, pre, hpre);
-    for (uint64_t tile = t0; tile < t1; ++tile) {
+    uint64_t tile = tile_of(0);
+    if (tile < a.ntiles)
+        dma_tile<CPL>(a.tv, tile * T, tid, hch, lds);
+    for (uint64_t i = 0; tile < a.ntiles; ++i) {
         const uint64_t ts = tile * T;
-        __syncthreads();
-        put_tile<CPL>(lds, tid, hch, pre, hpre);
-        if (hch > kWG)
-            put_halo_rest(lds + T, a.tv, ts + T, tid, hch);
-        __syncthreads();
-        if (tile + 1 < t1)
-            fetch_tile<CPL>(a.tv, ts + T, tid, hch, pre, hpre);
+        uint8_t *cur = lds + (i & 1u) * TB;
+        const uint64_t next = tile_of(i + 1);
+        wait_dma();
+        __syncthreads();  // tile visible to all waves; the other buffer is free
+        if (next < a.ntiles)
+            dma_tile<CPL>(a.tv, next * T, tid, hch, lds + ((i + 1) & 1u) * TB);
 #pragma unroll
         for (int b = 0; b < CPL; ++b) {
             const uint32_t boff = (wave * CPL + b) * kBlock;
@@ -278,16 +422,16 @@ __global__ __launch_bounds__(kWG) void k_count_staged(CountArgs a)
                 break;
             uint32_t d[4];
             init_alive(wb, a.tv.first, a.last, lane, d);
-            const uint8_t *lb = lds + boff + 4u * lane;
-            const uint32_t c = search_vector<R>(a.steps, pk, a.m, d,
-                                                [&](uint64_t st, uint32_t (&dd)[4]) { step_lds(lb, st, dd); });
-            if (a.block_counts) {
+            const LdsText tx{cur + boff, cur + boff + 4u * lane};
+            const uint32_t c = search_vector<R>(a.steps, pk, a.m, lane, d, tx) ? count_alive(d) : 0u;
+            if (a.block_counts && __any(c != 0u)) {
                 const uint32_t s = wave_sum32(c);
                 if (lane == 0)
                     a.block_counts[wb / kBlock] = s;
             }
             acc += c;
         }
+        tile = next;
     }
     wg_add_count(acc, a.count, tid);
 }
@@ -308,10 +452,9 @@ __global__ __launch_bounds__(kWG) void k_count_global(CountArgs a)
         const uint64_t wb = blk * kBlock;
         uint32_t d[4];
         init_alive(wb, a.tv.first, a.last, lane, d);
-        const uint64_t lu = wb + 4u * lane;
-        const uint32_t c = search_vector<R>(a.steps, pk, a.m, d,
-                                            [&](uint64_t st, uint32_t (&dd)[4]) { step_global(a.tv, lu, st, dd); });
-        if (a.block_counts) {
+        const GlobalText tx{&a.tv, wb, wb + 4u * lane};
+        const uint32_t c = search_vector<R>(a.steps, pk, a.m, lane, d, tx) ? count_alive(d) : 0u;
+        if (a.block_counts && __any(c != 0u)) {
             const uint32_t s = wave_sum32(c);
             if (lane == 0)
                 a.block_counts[blk] = s;
@@ -322,20 +465,45 @@ __global__ __launch_bounds__(kWG) void k_count_global(CountArgs a)
 }
 
 // ---------------------------------------------------------- report kernels
+//
+// Reporting version (Section 2.1) in three steps after the count pass has
+// written the nonzero per-vector counts into a zero-filled array:
+//   k_group_sums   sum of every group of kGroupBlocks vector counts;
+//   k_scan_groups  exclusive scan of the group sums and the total;
+//   k_report_write for each group with matches: exclusive offsets of its
+//                  vectors in LDS, then every vector with matches is searched
+//                  again (its window staged in a per-wave LDS region) and its
+//                  starts are written in increasing order.  Within a vector the
+//                  order is k-major, then lane, then byte -- increasing start --
+//                  and lane offsets come from a bit-sliced ballot prefix sum.
 
-// gs[g] = sum of block counts 64g .. 64g+63 (one wave per group).
 __global__ __launch_bounds__(kWG) void k_group_sums(const uint32_t *bc, uint64_t nblocks, uint64_t ngroups,
                                                    unsigned long long *gs)
 {
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t g = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
-    if (g >= ngroups)
-        return;
-    const uint64_t b = g * 64u + lane;
-    const uint32_t c = b < nblocks ? bc[b] : 0u;
-    const uint32_t s = wave_sum32(c);
-    if (lane == 0)
-        gs[g] = s;
+    __shared__ uint32_t red[kWaves];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+    for (uint64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
+        const uint64_t b0 = g * kGroupBlocks;
+        uint32_t s = 0;
+#pragma unroll
+        for (uint32_t i = 0; i < kGroupBlocks / kWG; ++i) {
+            const uint64_t b = b0 + tid + kWG * i;
+            if (b < nblocks)
+                s += bc[b];
+        }
+        s = wave_sum32(s);
+        if (lane == 0)
+            red[wave] = s;
+        __syncthreads();
+        if (tid == 0) {
+            unsigned long long t = 0;
+#pragma unroll
+            for (uint32_t w = 0; w < kWaves; ++w)
+                t += red[w];
+            gs[g] = t;
+        }
+        __syncthreads();
+    }
 }
 
 // Exclusive scan of the group sums (one workgroup of 1024 threads), and the total.
@@ -366,61 +534,108 @@ __global__ __launch_bounds__(1024) void k_scan_groups(const unsigned long long *
         *total = part[1023];
 }
 
-// Write pass of the reporting version: every vector with a nonzero block
-// count is searched again (all m compares) and its starts are written in
-// increasing order at that block's offset.  Within a vector the order is
-// k-major, then lane, then byte -- exactly increasing start -- and lane
-// offsets come from a bit-sliced ballot prefix sum (mbcnt).
-__global__ __launch_bounds__(kWG) void k_report_write(CountArgs a, const uint32_t *bc,
-                                                     const unsigned long long *go, uint64_t ngroups,
-                                                     unsigned long long *pos, uint64_t cap)
+// Writes the starts of one vector whose final d is known, in increasing order
+// from output index o.
+__device__ __forceinline__ void write_vector(const uint32_t (&d)[4], uint64_t wb, uint64_t first, uint32_t lane,
+                                             unsigned long long o, unsigned long long *pos, uint64_t cap)
 {
-    const uint32_t tid = threadIdx.x, lane = tid & 63u;
-    const uint64_t nw = (uint64_t)gridDim.x * kWaves;
-    for (uint64_t g = (uint64_t)blockIdx.x * kWaves + (tid >> 6); g < ngroups; g += nw) {
-        const uint64_t b = g * 64u + lane;
-        const uint32_t c = b < a.nblocks ? bc[b] : 0u;
-        unsigned long long nz = __ballot(c != 0u);
-        if (nz == 0)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t z = zero_bytes(d[k]);
+        const uint32_t ck = __popc(z);
+        const unsigned long long b1 = __ballot(ck & 1u), b2 = __ballot(ck & 2u), b4 = __ballot(ck & 4u);
+        const uint32_t ex = lanes_below(b1) + 2u * lanes_below(b2) + 4u * lanes_below(b4);
+        const uint32_t tot = __popcll(b1) + 2u * __popcll(b2) + 4u * __popcll(b4);
+        unsigned long long idx = o + ex;
+#pragma unroll
+        for (int by = 0; by < 4; ++by) {
+            if (z & (0x80u << (8 * by))) {
+                if (idx < cap)
+                    pos[idx] = wb + 256u * k + 4u * lane + by - first;
+                ++idx;
+            }
+        }
+        o += tot;
+    }
+}
+
+// win: per-wave LDS window in bytes (1024 + halo), or 0 to read the text
+// from global memory (long patterns).
+__global__ __launch_bounds__(kWG) void k_report_write(CountArgs a, uint32_t r, const uint32_t *bc,
+                                                     const unsigned long long *gs, const unsigned long long *go,
+                                                     uint64_t ngroups, unsigned long long *pos, uint64_t cap,
+                                                     uint32_t win)
+{
+    extern __shared__ __align__(16) uint8_t wlds[];
+    __shared__ uint32_t off[kGroupBlocks];
+    __shared__ uint32_t wsum[kWaves];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+    uint8_t *mine = wlds + wave * win;
+    for (uint64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
+        if (gs[g] == 0)
             continue;
-        uint32_t inc = c;
+        const uint64_t b0 = g * kGroupBlocks;
+        // exclusive offsets of the group's vectors (4 consecutive per thread)
+        uint32_t c[kGroupBlocks / kWG], s = 0;
+#pragma unroll
+        for (uint32_t i = 0; i < kGroupBlocks / kWG; ++i) {
+            const uint64_t b = b0 + (kGroupBlocks / kWG) * tid + i;
+            c[i] = b < a.nblocks ? bc[b] : 0u;
+            s += c[i];
+        }
+        uint32_t inc = s;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
             const uint32_t v = __shfl_up(inc, o, 64);
             if (lane >= (uint32_t)o)
                 inc += v;
         }
-        const uint32_t excl = inc - c;
-        const unsigned long long base = go[g];
-        while (nz) {
-            const int bit = __ffsll((long long)nz) - 1;
-            nz &= nz - 1;
-            const uint64_t wb = (g * 64u + (uint64_t)bit) * kBlock;
-            unsigned long long o = base + (unsigned long long)__shfl(excl, bit, 64);
-            uint32_t d[4];
-            init_alive(wb, a.tv.first, a.last, lane, d);
-            const uint64_t lu = wb + 4u * lane;
-            for (uint32_t l = 0; l < a.m; ++l)
-                step_global(a.tv, lu, a.steps[l], d);
+        if (lane == 63u)
+            wsum[wave] = inc;
+        __syncthreads();
+        uint32_t run = inc - s;
+        for (uint32_t w = 0; w < wave; ++w)
+            run += wsum[w];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const uint32_t z = zero_bytes(d[k]);
-                const uint32_t ck = __popc(z);
-                const unsigned long long b1 = __ballot(ck & 1u), b2 = __ballot(ck & 2u), b4 = __ballot(ck & 4u);
-                const uint32_t ex = lanes_below(b1) + 2u * lanes_below(b2) + 4u * lanes_below(b4);
-                const uint32_t tot = __popcll(b1) + 2u * __popcll(b2) + 4u * __popcll(b4);
-                unsigned long long idx = o + ex;
-#pragma unroll
-                for (int by = 0; by < 4; ++by) {
-                    if (z & (0x80u << (8 * by))) {
-                        if (idx < cap)
-                            pos[idx] = wb + 256u * k + 4u * lane + by - a.tv.first;
-                        ++idx;
+        for (uint32_t i = 0; i < kGroupBlocks / kWG; ++i) {
+            off[(kGroupBlocks / kWG) * tid + i] = run;
+            run += c[i];
+        }
+        __syncthreads();
+        const unsigned long long gbase = go[g];
+        for (uint32_t j0 = wave * 64u; j0 < kGroupBlocks; j0 += kWaves * 64u) {
+            const uint64_t bb = b0 + j0 + lane;
+            unsigned long long nz = __ballot(bb < a.nblocks && bc[bb] != 0u);
+            while (nz) {
+                const int bit = __ffsll((long long)nz) - 1;
+                nz &= nz - 1;
+                const uint64_t wb = (b0 + j0 + (uint64_t)bit) * kBlock;
+                uint32_t d[4];
+                init_alive(wb, a.tv.first, a.last, lane, d);
+                bool alive;
+                if (win) {
+                    for (uint32_t ch = lane; ch < win / 16u; ch += 64u) {
+                        const uint64_t u = wb + 16ull * ch;
+                        *reinterpret_cast<uint4 *>(mine + 16u * ch) =
+                            u < a.tv.end16 ? *reinterpret_cast<const uint4 *>(a.tv.base + u) : make_uint4(0, 0, 0, 0);
                     }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    const LdsText tx{mine, mine + 4u * lane};
+                    alive = search_vector_rt(a.steps, r, a.m, lane, d, tx);
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                } else {
+                    const GlobalText tx{&a.tv, wb, wb + 4u * lane};
+                    alive = search_vector_rt(a.steps, r, a.m, lane, d, tx);
                 }
-                o += tot;
+                if (alive)
+                    write_vector(d, wb, a.tv.first, lane, gbase + off[j0 + bit], pos, cap);
             }
         }
+        __syncthreads();
     }
 }
 
@@ -461,6 +676,18 @@ __global__ __launch_bounds__(kWG) void k_hist(TextView tv, unsigned long long *h
         if (s)
             atomicAdd(&hist[bin], s);
     }
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint64_t n)
+{
+    // 16-byte stores where possible; p is 16-byte aligned (hipMalloc)
+    const uint64_t n4 = n / 4;
+    uint4 *p4 = reinterpret_cast<uint4 *>(p);
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (uint64_t)gridDim.x * blockDim.x)
+        p4[i] = make_uint4(0, 0, 0, 0);
+    for (uint64_t i = 4 * n4 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
 }
 
 __global__ void k_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v)
@@ -515,9 +742,9 @@ __global__ __launch_bounds__(kWG) void k_batch_staged(BatchArgs a)
                         break;
                     uint32_t d[4];
                     init_alive(wb, I.tv.first, Q.last, lane, d);
-                    const uint8_t *lb = lds + boff + 4u * lane;
-                    c += search_vector_rt(st, Q.r, Q.m, d,
-                                          [&](uint64_t s, uint32_t (&dd)[4]) { step_lds(lb, s, dd); });
+                    const LdsText tx{lds + boff, lds + boff + 4u * lane};
+                    if (search_vector_rt(st, Q.r, Q.m, lane, d, tx))
+                        c += count_alive(d);
                 }
                 if (__any(c != 0u)) {
                     const uint32_t s = wave_sum32(c);
@@ -541,7 +768,7 @@ template <int CPL, int R>
 static hipError_t launch_staged_t(const CountArgs &a, unsigned grid, hipStream_t s)
 {
     static bool attr_set = false;
-    const uint32_t lds = kWG * 16u * CPL + a.halo;
+    const uint32_t lds = 2u * (kWG * 16u * CPL + a.halo);
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_count_staged<CPL, R>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
@@ -602,10 +829,9 @@ hipError_t launch_count_global(const CountArgs &a, int r, unsigned grid, hipStre
 }
 
 hipError_t launch_group_sums(const uint32_t *bc, uint64_t nblocks, uint64_t ngroups, unsigned long long *gs,
-                             hipStream_t s)
+                             unsigned grid, hipStream_t s)
 {
-    const uint64_t grid = (ngroups + kWaves - 1) / kWaves;
-    hipLaunchKernelGGL(k_group_sums, dim3((unsigned)grid), dim3(kWG), 0, s, bc, nblocks, ngroups, gs);
+    hipLaunchKernelGGL(k_group_sums, dim3(grid), dim3(kWG), 0, s, bc, nblocks, ngroups, gs);
     return hipGetLastError();
 }
 
@@ -616,11 +842,28 @@ hipError_t launch_scan_groups(const unsigned long long *gs, uint64_t ngroups, un
     return hipGetLastError();
 }
 
-hipError_t launch_report_write(const CountArgs &a, const uint32_t *bc, const unsigned long long *go,
-                               uint64_t ngroups, unsigned long long *pos, uint64_t cap, unsigned grid,
-                               hipStream_t s)
+hipError_t launch_report_write(const CountArgs &a, uint32_t r, const uint32_t *bc, const unsigned long long *gs,
+                               const unsigned long long *go, uint64_t ngroups, unsigned long long *pos, uint64_t cap,
+                               uint32_t win, unsigned grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_report_write, dim3(grid), dim3(kWG), 0, s, a, bc, go, ngroups, pos, cap);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_report_write),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
+        if (e != hipSuccess)
+            return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_report_write, dim3(grid), dim3(kWG), kWaves * win, s, a, r, bc, gs, go, ngroups, pos, cap,
+                       win);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n, hipStream_t s)
+{
+    const uint64_t g = (n + 1023) / 1024;
+    const unsigned grid = (unsigned)(g < 4096 ? (g ? g : 1) : 4096);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 

@@ -274,3 +274,30 @@ def test_deterministic(dev):
     b = sm.report(td, p, order="freq").cpu()
     assert torch.equal(a, b)
     assert bool((a[1:] > a[:-1]).all())
+
+
+# ------------------------------------------------------------- prepared patterns
+def test_prepared_patterns(dev):
+    g = np.random.default_rng(31)
+    t = rand_text(1_500_007, 95, 4)
+    td = to_dev(t, dev, 9)
+    h = oracle.hist(t)
+    pats = [pick_pattern(t, int(m), g, planted=g.random() < 0.8)
+            for m in synth.loguniform_ints(1, 3000, 120, g)] + [bytes(t[5:5 + 70_000])]
+    orders = [oracle.order_freq(p, h) if i % 2 else None for i, p in enumerate(pats)]
+    ps = sm.Patterns(pats, orders)
+    out = torch.zeros(len(pats), dtype=torch.int64, device=dev)
+    for i in range(len(pats)):
+        ps.count_async(i, td, out[i:i + 1], peel=1 + i % 8)
+    torch.cuda.synchronize()
+    want = [oracle.count(p, t) for p in pats]
+    assert out.cpu().tolist() == want
+    buf = torch.empty(4096, dtype=torch.int64, device=dev)
+    for i in range(0, len(pats), 7):
+        tot = ps.report(i, td, buf)
+        assert tot == want[i]
+        if tot <= buf.numel():
+            assert np.array_equal(buf[:tot].cpu().numpy().astype(np.uint64), oracle.report(pats[i], t))
+    ps.close()
+    with pytest.raises(sm.SmError):
+        sm.Patterns([b"ab", b""])
