@@ -89,8 +89,9 @@ def run_zipf(args):
     torch.cuda.synchronize()
     patterns = [p for p, _ in pats]
     rep_idx = [i for i, (_, r) in enumerate(pats) if r]
-    cap = 1 << 20
-    posbuf = torch.empty(cap, dtype=torch.int64, device=dev)
+    cap = 4096  # positions kept per reporting search (substrings of m >= 64 occur about once)
+    posbuf = torch.empty((len(rep_idx), cap), dtype=torch.int64, device=dev)
+    totals_dev = torch.empty(len(rep_idx), dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in patterns]
 
@@ -98,23 +99,19 @@ def run_zipf(args):
 
     def step(timed: bool):
         hist = sm.histogram(t_dev).cpu().numpy().view(np.uint64)                  # symbol frequencies
-        orders = [sm.order("freq", p, hist) for p in patterns]                      # compare order pi
-        ps = sm.Patterns(patterns, orders)                                          # step tables -> HBM
+        ps = sm.Patterns(patterns, "freq", hist)                  # compare orders pi + step tables -> HBM
         counts = torch.zeros(len(patterns), dtype=torch.int64, device=dev)
         for i in range(len(patterns)):
             ev[i][0].record(stream)
             ps.count_async(i, t_dev, counts[i:i + 1], stream=stream)
             ev[i][1].record(stream)
-        totals, plist = [], []
-        for i in rep_idx:                                                           # reporting version
-            tot = ps.report(i, t_dev, posbuf, stream=stream)
-            totals.append(tot)
-            plist.append(posbuf[:min(tot, cap)].clone())
+        for k, i in enumerate(rep_idx):                                             # reporting version
+            ps.report_async(i, t_dev, posbuf[k], totals_dev[k:k + 1], stream=stream)
         torch.cuda.synchronize()
         ps.close()
         state["counts"] = counts.cpu().numpy()
-        state["totals"] = totals
-        state["plist"] = plist
+        state["totals"] = totals_dev.cpu().numpy()
+        state["plist"] = [posbuf[k, :min(int(tot), cap)] for k, tot in enumerate(state["totals"])]
         if timed:
             state.setdefault("kern_ms", []).extend(a.elapsed_time(b) for a, b in ev)
 

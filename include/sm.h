@@ -125,6 +125,15 @@ int64_t sm_report(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n, co
 int64_t sm_report_ex(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n, const int32_t *order,
                      const sm_params *params, uint64_t *pos_dev, uint64_t cap, void *stream);
 
+/* Asynchronous report: as sm_report_ex, but the full count is written to
+ * *total_dev (device uint64) and the call returns SM_OK without waiting.
+ * Reports on one device share the library's report scratch; the library
+ * orders them (a report's first kernel waits for the previous report's last
+ * one, also across streams). */
+int32_t sm_report_async(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n, const int32_t *order,
+                        const sm_params *params, uint64_t *pos_dev, uint64_t cap, uint64_t *total_dev,
+                        void *stream);
+
 /* ---------------------------------------------------- prepared patterns */
 
 /* A set of patterns whose step tables (pattern position and symbol per
@@ -139,6 +148,12 @@ typedef struct sm_patterns sm_patterns;
 int32_t sm_patterns_create(uint64_t np, const uint8_t *const *p, const uint64_t *m,
                            const int32_t *const *order, sm_patterns **out);
 
+/* As sm_patterns_create, with every compare order computed by the library:
+ * kind is an SM_ORDER_* value; hist_host (host 256 x uint64) is required for
+ * SM_ORDER_FREQ and ignored otherwise. */
+int32_t sm_patterns_create_ordered(uint64_t np, const uint8_t *const *p, const uint64_t *m, int32_t kind,
+                                   const uint64_t *hist_host, sm_patterns **out);
+
 int32_t sm_patterns_destroy(sm_patterns *ps);
 
 /* Count of pattern i of the set in t, ADDED to *count_dev (device uint64);
@@ -149,6 +164,11 @@ int32_t sm_patterns_count(const sm_patterns *ps, uint64_t i, const uint8_t *t, u
 /* Report of pattern i of the set (as sm_report_ex); synchronous on `stream`. */
 int64_t sm_patterns_report(const sm_patterns *ps, uint64_t i, const uint8_t *t, uint64_t n,
                            const sm_params *params, uint64_t *pos_dev, uint64_t cap, void *stream);
+
+/* Report of pattern i of the set (as sm_report_async); asynchronous, no host-device copy. */
+int32_t sm_patterns_report_async(const sm_patterns *ps, uint64_t i, const uint8_t *t, uint64_t n,
+                                 const sm_params *params, uint64_t *pos_dev, uint64_t cap, uint64_t *total_dev,
+                                 void *stream);
 
 /* -------------------------------------------------------------- batches */
 

@@ -25,7 +25,7 @@ from ._lib import (SM_ORDER_FREQ, SM_ORDER_H, SM_ORDER_HS, SM_ORDER_LTR, SmError
                    sm_params, sm_query, sm_text)
 
 __all__ = ["Text", "Patterns", "SmError", "histogram", "order", "count", "count_async", "report",
-           "count_batch", "version", "device_cus"]
+           "report_async", "count_batch", "version", "device_cus"]
 
 ORDER_KINDS = {"ltr": SM_ORDER_LTR, "freq": SM_ORDER_FREQ, "h": SM_ORDER_H, "hs": SM_ORDER_HS}
 
@@ -183,6 +183,17 @@ def report(t, p, order=None, cap: int | None = None, peel=None, tile_kib=None, w
     return (out, total) if return_count else out
 
 
+def report_async(t, p, out: torch.Tensor, total: torch.Tensor, order=None, peel=None, tile_kib=None,
+                 wgs_per_cu=None, stream=None) -> None:
+    """Write up to out.numel() increasing positions of p in t into out and the full count into
+    total[0] (device int64), without waiting."""
+    a = _pat(p)
+    ptr, n = _dev_text(t)
+    o = _resolve_order(order, a, t)
+    check(load().sm_report_async(_ptr(a), a.size, ptr, n, _ptr(o), _params(peel, tile_kib, wgs_per_cu),
+                                 out.data_ptr(), out.numel(), total.data_ptr(), _stream(stream)))
+
+
 def count_batch(texts: Sequence, queries: Iterable, peel=None, tile_kib=None, wgs_per_cu=None,
                 stream=None, use_hist: bool = True) -> torch.Tensor:
     """Counts of many (text_id, pattern[, order]) queries in one persistent launch (asynchronous).
@@ -229,19 +240,28 @@ class Patterns:
     run back to back on a stream (or inside a captured graph).
     """
 
-    def __init__(self, patterns, orders=None):
+    def __init__(self, patterns, orders=None, hist=None):
+        """orders: None (left to right), a list of per-pattern orders (None entries allowed), or one
+        of 'ltr', 'freq' (needs hist, the text's 256-entry histogram), 'h', 'hs' for all patterns."""
         pats = [_pat(p) for p in patterns]
         n = len(pats)
         self.m = [int(p.size) for p in pats]
-        ords = [None] * n if orders is None else [
-            None if o is None else np.ascontiguousarray(np.asarray(o, dtype=np.int32)) for o in orders]
-        if len(ords) != n:
-            raise ValueError("one order per pattern")
         parr = (ctypes.c_void_p * max(n, 1))(*[_ptr(p) for p in pats])
         marr = (ctypes.c_uint64 * max(n, 1))(*self.m)
-        oarr = (ctypes.c_void_p * max(n, 1))(*[_ptr(o) for o in ords])
         h = ctypes.c_void_p()
-        check(load().sm_patterns_create(n, parr, marr, oarr, ctypes.byref(h)))
+        if isinstance(orders, str):
+            hh = None
+            if hist is not None:
+                hh = np.ascontiguousarray(np.asarray(hist).astype(np.uint64))
+            check(load().sm_patterns_create_ordered(n, parr, marr, ORDER_KINDS[orders], _ptr(hh),
+                                                    ctypes.byref(h)))
+        else:
+            ords = [None] * n if orders is None else [
+                None if o is None else np.ascontiguousarray(np.asarray(o, dtype=np.int32)) for o in orders]
+            if len(ords) != n:
+                raise ValueError("one order per pattern")
+            oarr = (ctypes.c_void_p * max(n, 1))(*[_ptr(o) for o in ords])
+            check(load().sm_patterns_create(n, parr, marr, oarr, ctypes.byref(h)))
         self._h = h
 
     def __len__(self):
@@ -277,3 +297,10 @@ class Patterns:
         ptr, n = _dev_text(t)
         return check(load().sm_patterns_report(self._h, i, ptr, n, _params(peel, tile_kib, wgs_per_cu),
                                                out.data_ptr(), out.numel(), _stream(stream)))
+
+    def report_async(self, i: int, t, out: torch.Tensor, total: torch.Tensor, peel=None, tile_kib=None,
+                     wgs_per_cu=None, stream=None) -> None:
+        """Positions of pattern i into out (up to out.numel()), full count into total[0]; no wait."""
+        ptr, n = _dev_text(t)
+        check(load().sm_patterns_report_async(self._h, i, ptr, n, _params(peel, tile_kib, wgs_per_cu),
+                                              out.data_ptr(), out.numel(), total.data_ptr(), _stream(stream)))

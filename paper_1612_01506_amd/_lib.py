@@ -19,6 +19,7 @@ EXPORTS = (
     "sm_version", "sm_last_error", "sm_device_cus", "sm_shutdown", "sm_histogram", "sm_order",
     "sm_count", "sm_count_ex", "sm_count_async", "sm_report", "sm_report_ex", "sm_count_batch",
     "sm_patterns_create", "sm_patterns_destroy", "sm_patterns_count", "sm_patterns_report",
+    "sm_report_async", "sm_patterns_report_async", "sm_patterns_create_ordered",
 )
 
 
@@ -70,8 +71,11 @@ def load() -> ctypes.CDLL:
         "sm_count_batch": ([P(sm_query), u64, P(sm_text), u64, vp, P(sm_params), vp], i32),
         "sm_patterns_create": ([u64, P(vp), P(u64), P(vp), P(vp)], i32),
         "sm_patterns_destroy": ([vp], i32),
+        "sm_patterns_create_ordered": ([u64, P(vp), P(u64), i32, vp, P(vp)], i32),
         "sm_patterns_count": ([vp, u64, vp, u64, P(sm_params), vp, vp], i32),
         "sm_patterns_report": ([vp, u64, vp, u64, P(sm_params), vp, u64, vp], i64),
+        "sm_report_async": ([vp, u64, vp, u64, vp, P(sm_params), vp, u64, vp, vp], i32),
+        "sm_patterns_report_async": ([vp, u64, vp, u64, P(sm_params), vp, u64, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)

@@ -67,6 +67,8 @@ struct Dev {
     size_t bc_cap = 0;
     unsigned long long *gs = nullptr, *go = nullptr;
     size_t g_cap = 0;
+    hipEvent_t rep_ev = nullptr;  // recorded after each report's last kernel
+    bool rep_pending = false;
 };
 
 constexpr int kMaxDev = 64;
@@ -325,7 +327,8 @@ uint32_t halo_for(uint64_t m) { return (uint32_t)round_up(m + 4, 16); }
 
 // Fills the geometry of a single search and launches the count kernel.
 int launch_count(Dev &d, const TextView &tv, uint64_t m, const uint64_t *steps_dev, const Tune &tu,
-                 unsigned long long *count_dev, uint32_t *block_counts, hipStream_t s)
+                 unsigned long long *count_dev, uint32_t *block_counts, unsigned long long *group_sums,
+                 hipStream_t s)
 {
     CountArgs a{};
     a.tv = tv;
@@ -335,6 +338,7 @@ int launch_count(Dev &d, const TextView &tv, uint64_t m, const uint64_t *steps_d
     a.m = (uint32_t)m;
     a.count = count_dev;
     a.block_counts = block_counts;
+    a.group_sums = group_sums;
     const uint64_t target = (uint64_t)std::max(d.cus, 1) * (uint64_t)tu.wpc;
     int cpl = tu.cpl;
     const uint64_t halo = halo_for(m);
@@ -366,6 +370,8 @@ int upload_steps(Dev &d, const uint8_t *p, uint64_t m, const int32_t *order, hip
 
 int ensure_report_scratch(Dev &d, uint64_t nblocks, uint64_t ngroups)
 {
+    if ((d.bc_cap < nblocks || d.g_cap < ngroups) && d.rep_pending)
+        HIP_TRY(hipEventSynchronize(d.rep_ev));  // the old buffers may still be in use
     if (d.bc_cap < nblocks) {
         if (d.bc)
             HIP_TRY(hipFree(d.bc));
@@ -408,7 +414,7 @@ int64_t count_sync(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n, c
     Upload u;
     SM_TRY(upload_steps(*d, p, m, order, s, &u));
     HIP_TRY(hipMemsetAsync(d->u64, 0, sizeof(unsigned long long), s));
-    SM_TRY(launch_count(*d, make_view(t, n), m, reinterpret_cast<const uint64_t *>(u.dev), tu, d->u64, nullptr, s));
+    SM_TRY(launch_count(*d, make_view(t, n), m, reinterpret_cast<const uint64_t *>(u.dev), tu, d->u64, nullptr, nullptr, s));
     HIP_TRY(hipMemcpyAsync(d->hpin, d->u64, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     SM_TRY(ring_commit(*d, u, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -419,20 +425,23 @@ int64_t count_sync(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n, c
 // per-vector counts, group sums, exclusive scan, ordered write pass.  The
 // caller holds d.mu, commits any upload afterwards and synchronises `s`.
 int report_core(Dev &d, const TextView &tv, uint64_t m, const uint64_t *steps_dev, const Tune &tu, uint64_t *pos,
-                uint64_t cap, hipStream_t s)
+                uint64_t cap, unsigned long long *total_dev, hipStream_t s)
 {
     const uint64_t last = tv.first + tv.n - m;
     const uint64_t nblocks = ceil_div(last + 1, kBlock);
     const uint64_t ngroups = ceil_div(nblocks, kGroupBlocks);
     SM_TRY(ensure_report_scratch(d, nblocks, ngroups));
-    // pass 1: nonzero per-vector counts into a zeroed array
-    HIP_TRY(launch_fill_u32(d.bc, nblocks, s));
-    SM_TRY(launch_count(d, tv, m, steps_dev, tu, nullptr, d.bc, s));
-    // offsets: group sums, exclusive scan, total
+    if (!d.rep_ev)
+        HIP_TRY(hipEventCreateWithFlags(&d.rep_ev, hipEventDisableTiming));
+    if (d.rep_pending)
+        HIP_TRY(hipStreamWaitEvent(s, d.rep_ev, 0));  // scratch is shared by all reports
+    // pass 1: nonzero per-vector counts into a zeroed array, and their group sums
+    HIP_TRY(launch_fill_report(d.bc, nblocks, d.gs, ngroups, s));
+    SM_TRY(launch_count(d, tv, m, steps_dev, tu, nullptr, d.bc, d.gs, s));
+    // offsets: exclusive scan of the group sums, total
     const uint64_t target = (uint64_t)std::max(d.cus, 1) * (uint64_t)tu.wpc;
     const unsigned ggrid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(ngroups, target));
-    HIP_TRY(launch_group_sums(d.bc, nblocks, ngroups, d.gs, ggrid, s));
-    HIP_TRY(launch_scan_groups(d.gs, ngroups, d.go, d.u64 + 1, s));
+    HIP_TRY(launch_scan_groups(d.gs, ngroups, d.go, total_dev, s));
     // pass 2: ordered write of the vectors with matches
     CountArgs a{};
     a.tv = tv;
@@ -445,7 +454,8 @@ int report_core(Dev &d, const TextView &tv, uint64_t m, const uint64_t *steps_de
         win = 0;  // long pattern: read the text from global memory
     HIP_TRY(launch_report_write(a, (uint32_t)tu.r, d.bc, d.gs, d.go, ngroups,
                                 reinterpret_cast<unsigned long long *>(pos), cap, (uint32_t)win, ggrid, s));
-    HIP_TRY(hipMemcpyAsync(d.hpin + 1, d.u64 + 1, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(d.rep_ev, s));
+    d.rep_pending = true;
     return SM_OK;
 }
 
@@ -467,11 +477,39 @@ int64_t report_sync(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n, 
     const Tune tu = resolve(params, m, n);
     Upload u;
     SM_TRY(upload_steps(*d, p, m, order, s, &u));
-    const int rc = report_core(*d, make_view(t, n), m, reinterpret_cast<const uint64_t *>(u.dev), tu, pos, cap, s);
+    const int rc = report_core(*d, make_view(t, n), m, reinterpret_cast<const uint64_t *>(u.dev), tu, pos, cap,
+                               d->u64 + 1, s);
     SM_TRY(ring_commit(*d, u, s));
     SM_TRY(rc);
+    HIP_TRY(hipMemcpyAsync(d->hpin + 1, d->u64 + 1, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     return (int64_t)d->hpin[1];
+}
+
+int report_async(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n, const int32_t *order,
+                 const sm_params *params, uint64_t *pos, uint64_t cap, uint64_t *total_dev, hipStream_t s)
+{
+    g_err.clear();
+    SM_TRY(check_pattern(p, m, order));
+    SM_TRY(check_text(t, n));
+    if (cap > 0 && !pos)
+        return fail(SM_EINVAL, "pos is NULL with cap > 0");
+    if (!total_dev)
+        return fail(SM_EINVAL, "total_dev is NULL");
+    unsigned long long *tot = reinterpret_cast<unsigned long long *>(total_dev);
+    if (m > n) {
+        HIP_TRY(launch_fill_u64(tot, 1, 0ull, s));
+        return SM_OK;
+    }
+    Dev *d;
+    SM_TRY(get_dev(&d));
+    std::lock_guard<std::mutex> lk(d->mu);
+    const Tune tu = resolve(params, m, n);
+    Upload u;
+    SM_TRY(upload_steps(*d, p, m, order, s, &u));
+    const int rc = report_core(*d, make_view(t, n), m, reinterpret_cast<const uint64_t *>(u.dev), tu, pos, cap, tot, s);
+    SM_TRY(ring_commit(*d, u, s));
+    return rc;
 }
 
 // ------------------------------------------------------------- batch plan
@@ -546,6 +584,7 @@ int32_t sm_shutdown(void)
         if (d->bc) (void)hipFree(d->bc);
         if (d->gs) (void)hipFree(d->gs);
         if (d->go) (void)hipFree(d->go);
+        if (d->rep_ev) (void)hipEventDestroy(d->rep_ev);
         delete d;
         g_devs[i] = nullptr;
     }
@@ -624,7 +663,7 @@ int32_t sm_count_async(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t 
     Upload u;
     SM_TRY(upload_steps(*d, p, m, order, s, &u));
     SM_TRY(launch_count(*d, make_view(t, n), m, reinterpret_cast<const uint64_t *>(u.dev), tu,
-                        reinterpret_cast<unsigned long long *>(count_dev), nullptr, s));
+                        reinterpret_cast<unsigned long long *>(count_dev), nullptr, nullptr, s));
     return ring_commit(*d, u, s);
 }
 
@@ -638,6 +677,12 @@ int64_t sm_report_ex(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n,
                      const sm_params *params, uint64_t *pos_dev, uint64_t cap, void *stream)
 {
     return report_sync(p, m, t, n, order, params, pos_dev, cap, reinterpret_cast<hipStream_t>(stream));
+}
+
+int32_t sm_report_async(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n, const int32_t *order,
+                        const sm_params *params, uint64_t *pos_dev, uint64_t cap, uint64_t *total_dev, void *stream)
+{
+    return report_async(p, m, t, n, order, params, pos_dev, cap, total_dev, reinterpret_cast<hipStream_t>(stream));
 }
 
 int32_t sm_patterns_create(uint64_t np, const uint8_t *const *p, const uint64_t *m, const int32_t *const *order,
@@ -682,6 +727,35 @@ int32_t sm_patterns_create(uint64_t np, const uint8_t *const *p, const uint64_t 
     return SM_OK;
 }
 
+int32_t sm_patterns_create_ordered(uint64_t np, const uint8_t *const *p, const uint64_t *m, int32_t kind,
+                                   const uint64_t *hist_host, sm_patterns **out)
+{
+    g_err.clear();
+    if (kind != SM_ORDER_LTR && kind != SM_ORDER_FREQ && kind != SM_ORDER_H && kind != SM_ORDER_HS)
+        return fail(SM_EINVAL, "unknown order kind");
+    if (kind == SM_ORDER_FREQ && !hist_host)
+        return fail(SM_EINVAL, "SM_ORDER_FREQ needs hist_host");
+    if (np > 0 && (!p || !m))
+        return fail(SM_EINVAL, "p or m is NULL");
+    std::vector<std::vector<int32_t>> ords(np);
+    std::vector<const int32_t *> optr(np, nullptr);
+    for (uint64_t i = 0; i < np; ++i) {
+        if (m[i] == 0 || m[i] >= (1ull << 31) || !p[i])
+            return fail(SM_EINVAL, "pattern " + std::to_string(i) + ": bad pattern or length");
+        if (kind == SM_ORDER_LTR)
+            continue;
+        ords[i].resize(m[i]);
+        if (kind == SM_ORDER_FREQ)
+            order_by_freq(p[i], m[i], hist_host, ords[i].data());
+        else if (kind == SM_ORDER_H)
+            order_fixed_h(m[i], ords[i].data());
+        else
+            order_fixed_hs(p[i], m[i], ords[i].data());
+        optr[i] = ords[i].data();
+    }
+    return sm_patterns_create(np, p, m, optr.data(), out);
+}
+
 int32_t sm_patterns_destroy(sm_patterns *ps)
 {
     g_err.clear();
@@ -708,7 +782,7 @@ int32_t sm_patterns_count(const sm_patterns *ps, uint64_t i, const uint8_t *t, u
     SM_TRY(get_dev(&d));
     const Tune tu = resolve(params, m, n);
     return launch_count(*d, make_view(t, n), m, ps->steps + ps->off[i], tu,
-                        reinterpret_cast<unsigned long long *>(count_dev), nullptr,
+                        reinterpret_cast<unsigned long long *>(count_dev), nullptr, nullptr,
                         reinterpret_cast<hipStream_t>(stream));
 }
 
@@ -728,9 +802,35 @@ int64_t sm_patterns_report(const sm_patterns *ps, uint64_t i, const uint8_t *t, 
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     std::lock_guard<std::mutex> lk(d->mu);
     const Tune tu = resolve(params, m, n);
-    SM_TRY(report_core(*d, make_view(t, n), m, ps->steps + ps->off[i], tu, cap ? pos_dev : nullptr, cap, s));
+    SM_TRY(report_core(*d, make_view(t, n), m, ps->steps + ps->off[i], tu, cap ? pos_dev : nullptr, cap, d->u64 + 1, s));
+    HIP_TRY(hipMemcpyAsync(d->hpin + 1, d->u64 + 1, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     return (int64_t)d->hpin[1];
+}
+
+int32_t sm_patterns_report_async(const sm_patterns *ps, uint64_t i, const uint8_t *t, uint64_t n,
+                                 const sm_params *params, uint64_t *pos_dev, uint64_t cap, uint64_t *total_dev,
+                                 void *stream)
+{
+    g_err.clear();
+    SM_TRY(check_set(ps, i));
+    SM_TRY(check_text(t, n));
+    if (cap > 0 && !pos_dev)
+        return fail(SM_EINVAL, "pos is NULL with cap > 0");
+    if (!total_dev)
+        return fail(SM_EINVAL, "total_dev is NULL");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    unsigned long long *tot = reinterpret_cast<unsigned long long *>(total_dev);
+    const uint64_t m = ps->m[i];
+    if (m > n) {
+        HIP_TRY(launch_fill_u64(tot, 1, 0ull, s));
+        return SM_OK;
+    }
+    Dev *d;
+    SM_TRY(get_dev(&d));
+    std::lock_guard<std::mutex> lk(d->mu);
+    const Tune tu = resolve(params, m, n);
+    return report_core(*d, make_view(t, n), m, ps->steps + ps->off[i], tu, cap ? pos_dev : nullptr, cap, tot, s);
 }
 
 int32_t sm_count_batch(const sm_query *q, uint64_t nq, const sm_text *texts, uint64_t nt,
@@ -908,7 +1008,7 @@ int32_t sm_count_batch(const sm_query *q, uint64_t nq, const sm_text *texts, uin
         Tune tu{(int)std::min<uint64_t>((uint64_t)rdef, pq.m), 1, wpc, (int)kChunkLog2};
         int rc = launch_count(*d, make_view(texts[pq.text].t, texts[pq.text].n), pq.m,
                               reinterpret_cast<const uint64_t *>(u.dev + long_off) + long_steps_off[i], tu,
-                              counts + pq.idx, nullptr, s);
+                              counts + pq.idx, nullptr, nullptr, s);
         if (rc < 0) {
             std::string msg = g_err;
             (void)ring_commit(*d, u, s);

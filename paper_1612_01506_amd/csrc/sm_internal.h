@@ -40,7 +40,8 @@ struct CountArgs {
     uint32_t m;
     uint32_t halo;            // staged: LDS bytes past the tile (multiple of 16, >= m + 4)
     unsigned long long *count;     // += total count (may be null)
-    uint32_t *block_counts;   // per wave-vector block counts (report pass), or null
+    uint32_t *block_counts;   // report pass: nonzero per-vector counts (array zeroed before), or null
+    unsigned long long *group_sums;  // report pass: += per-vector counts of each kGroupBlocks group
 };
 
 struct BatchItem {
@@ -73,14 +74,13 @@ struct BatchArgs {
 // Host-side launchers (sm_kernels.hip).  Each returns a hipError_t.
 hipError_t launch_count_staged(const CountArgs &a, int cpl, int r, unsigned grid, hipStream_t s);
 hipError_t launch_count_global(const CountArgs &a, int r, unsigned grid, hipStream_t s);
-hipError_t launch_group_sums(const uint32_t *bc, uint64_t nblocks, uint64_t ngroups, unsigned long long *gs,
-                             unsigned grid, hipStream_t s);
 hipError_t launch_scan_groups(const unsigned long long *gs, uint64_t ngroups, unsigned long long *go,
                               unsigned long long *total, hipStream_t s);
 hipError_t launch_report_write(const CountArgs &a, uint32_t r, const uint32_t *bc, const unsigned long long *gs,
                                const unsigned long long *go, uint64_t ngroups, unsigned long long *pos, uint64_t cap,
                                uint32_t win, unsigned grid, hipStream_t s);
-hipError_t launch_fill_u32(uint32_t *p, uint64_t n, hipStream_t s);
+hipError_t launch_fill_report(uint32_t *bc, uint64_t nblocks, unsigned long long *gs, uint64_t ngroups,
+                              hipStream_t s);
 hipError_t launch_hist(const TextView &tv, unsigned long long *hist, unsigned grid, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_batch_staged(const BatchArgs &a, int cpl, unsigned grid, uint32_t lds_bytes, hipStream_t s);

@@ -426,8 +426,10 @@ __global__ __launch_bounds__(kWG) void k_count_staged(CountArgs a)
             const uint32_t c = search_vector<R>(a.steps, pk, a.m, lane, d, tx) ? count_alive(d) : 0u;
             if (a.block_counts && __any(c != 0u)) {
                 const uint32_t s = wave_sum32(c);
-                if (lane == 0)
+                if (lane == 0) {
                     a.block_counts[wb / kBlock] = s;
+                    atomicAdd(&a.group_sums[wb / kBlock / kGroupBlocks], (unsigned long long)s);
+                }
             }
             acc += c;
         }
@@ -456,8 +458,10 @@ __global__ __launch_bounds__(kWG) void k_count_global(CountArgs a)
         const uint32_t c = search_vector<R>(a.steps, pk, a.m, lane, d, tx) ? count_alive(d) : 0u;
         if (a.block_counts && __any(c != 0u)) {
             const uint32_t s = wave_sum32(c);
-            if (lane == 0)
+            if (lane == 0) {
                 a.block_counts[blk] = s;
+                atomicAdd(&a.group_sums[blk / kGroupBlocks], (unsigned long long)s);
+            }
         }
         acc += c;
     }
@@ -466,9 +470,9 @@ __global__ __launch_bounds__(kWG) void k_count_global(CountArgs a)
 
 // ---------------------------------------------------------- report kernels
 //
-// Reporting version (Section 2.1) in three steps after the count pass has
-// written the nonzero per-vector counts into a zero-filled array:
-//   k_group_sums   sum of every group of kGroupBlocks vector counts;
+// Reporting version (Section 2.1) in two steps after the count pass has
+// written the nonzero per-vector counts into a zero-filled array and added
+// them to the sums of their groups of kGroupBlocks vectors:
 //   k_scan_groups  exclusive scan of the group sums and the total;
 //   k_report_write for each group with matches: exclusive offsets of its
 //                  vectors in LDS, then every vector with matches is searched
@@ -476,35 +480,6 @@ __global__ __launch_bounds__(kWG) void k_count_global(CountArgs a)
 //                  starts are written in increasing order.  Within a vector the
 //                  order is k-major, then lane, then byte -- increasing start --
 //                  and lane offsets come from a bit-sliced ballot prefix sum.
-
-__global__ __launch_bounds__(kWG) void k_group_sums(const uint32_t *bc, uint64_t nblocks, uint64_t ngroups,
-                                                   unsigned long long *gs)
-{
-    __shared__ uint32_t red[kWaves];
-    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
-    for (uint64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
-        const uint64_t b0 = g * kGroupBlocks;
-        uint32_t s = 0;
-#pragma unroll
-        for (uint32_t i = 0; i < kGroupBlocks / kWG; ++i) {
-            const uint64_t b = b0 + tid + kWG * i;
-            if (b < nblocks)
-                s += bc[b];
-        }
-        s = wave_sum32(s);
-        if (lane == 0)
-            red[wave] = s;
-        __syncthreads();
-        if (tid == 0) {
-            unsigned long long t = 0;
-#pragma unroll
-            for (uint32_t w = 0; w < kWaves; ++w)
-                t += red[w];
-            gs[g] = t;
-        }
-        __syncthreads();
-    }
-}
 
 // Exclusive scan of the group sums (one workgroup of 1024 threads), and the total.
 __global__ __launch_bounds__(1024) void k_scan_groups(const unsigned long long *gs, uint64_t ng,
@@ -678,16 +653,18 @@ __global__ __launch_bounds__(kWG) void k_hist(TextView tv, unsigned long long *h
     }
 }
 
-__global__ void k_fill_u32(uint32_t *p, uint64_t n)
+// Zeroes the per-vector counts (16-byte stores; bc is 16-byte aligned) and the group sums.
+__global__ void k_fill_report(uint32_t *bc, uint64_t n, unsigned long long *gs, uint64_t ng)
 {
-    // 16-byte stores where possible; p is 16-byte aligned (hipMalloc)
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, nt = (uint64_t)gridDim.x * blockDim.x;
     const uint64_t n4 = n / 4;
-    uint4 *p4 = reinterpret_cast<uint4 *>(p);
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (uint64_t)gridDim.x * blockDim.x)
+    uint4 *p4 = reinterpret_cast<uint4 *>(bc);
+    for (uint64_t i = tid; i < n4; i += nt)
         p4[i] = make_uint4(0, 0, 0, 0);
-    for (uint64_t i = 4 * n4 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (uint64_t)gridDim.x * blockDim.x)
-        p[i] = 0u;
+    for (uint64_t i = 4 * n4 + tid; i < n; i += nt)
+        bc[i] = 0u;
+    for (uint64_t i = tid; i < ng; i += nt)
+        gs[i] = 0ull;
 }
 
 __global__ void k_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v)
@@ -828,13 +805,6 @@ hipError_t launch_count_global(const CountArgs &a, int r, unsigned grid, hipStre
     }
 }
 
-hipError_t launch_group_sums(const uint32_t *bc, uint64_t nblocks, uint64_t ngroups, unsigned long long *gs,
-                             unsigned grid, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_group_sums, dim3(grid), dim3(kWG), 0, s, bc, nblocks, ngroups, gs);
-    return hipGetLastError();
-}
-
 hipError_t launch_scan_groups(const unsigned long long *gs, uint64_t ngroups, unsigned long long *go,
                               unsigned long long *total, hipStream_t s)
 {
@@ -859,11 +829,12 @@ hipError_t launch_report_write(const CountArgs &a, uint32_t r, const uint32_t *b
     return hipGetLastError();
 }
 
-hipError_t launch_fill_u32(uint32_t *p, uint64_t n, hipStream_t s)
+hipError_t launch_fill_report(uint32_t *bc, uint64_t nblocks, unsigned long long *gs, uint64_t ngroups,
+                              hipStream_t s)
 {
-    const uint64_t g = (n + 1023) / 1024;
+    const uint64_t g = (nblocks + 1023) / 1024;
     const unsigned grid = (unsigned)(g < 4096 ? (g ? g : 1) : 4096);
-    hipLaunchKernelGGL(k_fill_u32, dim3(grid), dim3(256), 0, s, p, n);
+    hipLaunchKernelGGL(k_fill_report, dim3(grid), dim3(256), 0, s, bc, nblocks, gs, ngroups);
     return hipGetLastError();
 }
 

@@ -301,3 +301,50 @@ def test_prepared_patterns(dev):
     ps.close()
     with pytest.raises(sm.SmError):
         sm.Patterns([b"ab", b""])
+
+
+def test_report_async_two_streams(dev):
+    """Async reports on two streams share the library's report scratch; results must be exact."""
+    g = np.random.default_rng(8)
+    t = rand_text(3_000_017, 4, 12)
+    td = to_dev(t, dev, 6)
+    pats = [pick_pattern(t, int(m), g) for m in (6, 7, 8, 9, 10, 11, 12, 14, 16, 20, 64, 200)]
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    cap = 8192
+    outs = torch.full((len(pats), cap), -1, dtype=torch.int64, device=dev)
+    tots = torch.zeros(len(pats), dtype=torch.int64, device=dev)
+    torch.cuda.synchronize()
+    for i, p in enumerate(pats):
+        sm.report_async(td, p, outs[i], tots[i:i + 1], order="freq" if i % 2 else None,
+                        stream=s1 if i % 2 else s2)
+    torch.cuda.synchronize()
+    for i, p in enumerate(pats):
+        want = oracle.report(p, t)
+        assert int(tots[i]) == want.size
+        k = min(want.size, cap)
+        assert np.array_equal(outs[i, :k].cpu().numpy().astype(np.uint64), want[:k])
+    # prepared patterns, async, plus the m > n case (total 0)
+    ps = sm.Patterns(pats + [b"A" * (t.size + 1)])
+    tot = torch.full((len(pats) + 1,), -1, dtype=torch.int64, device=dev)
+    for i in range(len(pats) + 1):
+        ps.report_async(i, td, outs[i % len(pats)], tot[i:i + 1])
+    torch.cuda.synchronize()
+    assert tot.cpu().tolist() == [oracle.count(p, t) for p in pats] + [0]
+
+
+def test_patterns_create_ordered(dev):
+    g = np.random.default_rng(21)
+    t = rand_text(400_009, 95, 7)
+    td = to_dev(t, dev, 2)
+    h = oracle.hist(t)
+    pats = [pick_pattern(t, int(m), g) for m in synth.loguniform_ints(1, 600, 40, g)]
+    want = [oracle.count(p, t) for p in pats]
+    for kind in ("ltr", "freq", "h", "hs"):
+        ps = sm.Patterns(pats, kind, h if kind == "freq" else None)
+        out = torch.zeros(len(pats), dtype=torch.int64, device=dev)
+        for i in range(len(pats)):
+            ps.count_async(i, td, out[i:i + 1])
+        torch.cuda.synchronize()
+        assert out.cpu().tolist() == want, kind
+    with pytest.raises(sm.SmError):
+        sm.Patterns(pats, "freq")  # needs a histogram
