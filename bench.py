@@ -201,12 +201,144 @@ def run_zipf(args):
     }
 
 
+# --------------------------------------------------------------------- batched
+def _timed(fn, reps=1):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps, out
+
+
+def run_batched(args):
+    """10,000 patterns on one 2 GiB text, and 4,096 texts with one pattern each: the sequential
+    single-search form (one count launch per query, one final sync) against one sm_count_batch."""
+    import torch
+
+    import oracle
+    import paper_1612_01506_amd as sm
+    import synth
+
+    dev = torch.device("cuda:0")
+    lines = []
+    # ---- one text, many patterns
+    n = args.n if args.n != (1 << 30) else (2 << 30)
+    t0 = time.time()
+    t_host, pats = synth.batched_one_text_workload(n=n, nq=args.nq)
+    log(f"[bench] batched: {n} B text, {len(pats)} patterns in {time.time() - t0:.1f}s")
+    t_dev = torch.from_numpy(t_host).to(dev)
+    text = sm.Text(t_dev)
+    hist = text.hist
+    queries = [(0, p) for p in pats]
+
+    def sequential():
+        ps = sm.Patterns(pats, "freq", hist)
+        out = torch.zeros(len(pats), dtype=torch.int64, device=dev)
+        for i in range(len(pats)):
+            ps.count_async(i, t_dev, out[i:i + 1])
+        torch.cuda.synchronize()
+        ps.close()
+        return out
+
+    enq = []
+
+    def batched():
+        t_e = time.perf_counter()
+        out = sm.count_batch([text], queries)
+        enq.append(time.perf_counter() - t_e)
+        return out
+
+    batched()
+    tb, cb = min((_timed(batched) for _ in range(args.steps)), key=lambda x: x[0])
+    sequential()
+    ts, cs = _timed(sequential)
+    assert torch.equal(cb, cs), "batched and sequential counts differ"
+    cb = cb.cpu().numpy()
+    g = synth.rng(4, 99)
+    for i in g.choice(len(pats), size=args.oracle_samples, replace=False):
+        assert oracle.count(pats[i], t_host) == cb[i], ("oracle", i)
+    mean_m = float(np.mean([len(p) for p in pats]))
+    lines.append({
+        "metric": "batched searches/s", "value": round(len(pats) / tb, 1), "unit": "searches/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": round(tb * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic (seeded Zipf text; half substring, half random patterns)",
+        "config": {"workload": f"batched_one_text: {len(pats)} patterns, m log-uniform [2,1024] "
+                               f"(mean {mean_m:.0f}), {n}-byte Zipf(1.0) sigma=95 text",
+                   "sequential_s": round(ts, 4), "batched_s": round(tb, 4),
+                   "batched_host_enqueue_s": round(min(enq), 4),
+                   "speedup_vs_sequential": round(ts / tb, 2),
+                   "sequential_text_GBps": round(len(pats) * n / ts / 1e9, 1),
+                   "logical_text_GBps_batched": round(len(pats) * n / tb / 1e9, 1),
+                   "oracle_checked": args.oracle_samples},
+    })
+    del t_dev, text
+    torch.cuda.empty_cache()
+    # ---- many texts, one pattern each
+    texts_h, pats2 = synth.batched_many_texts_workload(ntexts=args.ntexts)
+    total = sum(t.size for t in texts_h)
+    big = torch.empty(total + 16 * len(texts_h), dtype=torch.uint8, device=dev)
+    views, off = [], 0
+    for i, th in enumerate(texts_h):
+        off += i % 16   # mixed alignments
+        v = big[off:off + th.size]
+        v.copy_(torch.from_numpy(th))
+        views.append(v)
+        off += th.size
+    q2 = [(i, p) for i, p in enumerate(pats2)]
+    packed = sm.PackedTexts(big, [v.data_ptr() - big.data_ptr() for v in views], [v.numel() for v in views])
+
+    def sequential2():
+        ps = sm.Patterns(pats2)
+        out = torch.zeros(len(pats2), dtype=torch.int64, device=dev)
+        for i in range(len(pats2)):
+            ps.count_async(i, views[i], out[i:i + 1])
+        torch.cuda.synchronize()
+        ps.close()
+        return out
+
+    enq2 = []
+
+    def batched2():
+        t_e = time.perf_counter()
+        out = sm.count_batch(packed, q2)
+        enq2.append(time.perf_counter() - t_e)
+        return out
+
+    batched2()
+    tb2, cb2 = min((_timed(batched2) for _ in range(args.steps)), key=lambda x: x[0])
+    sequential2()
+    ts2, cs2 = _timed(sequential2)
+    assert torch.equal(cb2, cs2), "batched and sequential counts differ (many texts)"
+    cb2 = cb2.cpu().numpy()
+    for i in range(0, len(pats2), max(1, len(pats2) // 64)):
+        assert oracle.count(pats2[i], texts_h[i]) == cb2[i], ("oracle many", i)
+    lines.append({
+        "metric": "batched searches/s", "value": round(len(pats2) / tb2, 1), "unit": "searches/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": round(tb2 * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic (seeded texts sigma 4/20/95, one substring pattern each)",
+        "config": {"workload": f"batched_many_texts: {len(pats2)} texts, {total} bytes in all, "
+                               "lengths log-uniform [4 KiB, 4 MiB], m log-uniform [4,256]",
+                   "sequential_s": round(ts2, 4), "batched_s": round(tb2, 4),
+                   "batched_host_enqueue_s": round(min(enq2), 4),
+                   "speedup_vs_sequential": round(ts2 / tb2, 2),
+                   "text_GBps_batched": round(total / tb2 / 1e9, 1)},
+    })
+    return lines
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="zipf", choices=["zipf"])
+    ap.add_argument("--workload", default="zipf", choices=["zipf", "batched"])
+    ap.add_argument("--nq", type=int, default=10_000, help="batched: patterns on the one text")
+    ap.add_argument("--ntexts", type=int, default=4096, help="batched: texts with one pattern each")
+    ap.add_argument("--oracle-samples", type=int, default=4, dest="oracle_samples")
     ap.add_argument("--n", type=int, default=1 << 30, help="text bytes (default 1 GiB)")
     ap.add_argument("--per-m", type=int, default=100, dest="per_m")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, dest="cpu_seconds",
@@ -222,8 +354,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
-    res = {"zipf": run_zipf}[args.workload](args)
-    print(json.dumps(res), flush=True)
+    res = {"zipf": run_zipf, "batched": run_batched}[args.workload](args)
+    for r in (res if isinstance(res, list) else [res]):
+        print(json.dumps(r), flush=True)
 
 
 if __name__ == "__main__":

@@ -24,7 +24,7 @@ import torch
 from ._lib import (SM_ORDER_FREQ, SM_ORDER_H, SM_ORDER_HS, SM_ORDER_LTR, SmError, check, load,
                    sm_params, sm_query, sm_text)
 
-__all__ = ["Text", "Patterns", "SmError", "histogram", "order", "count", "count_async", "report",
+__all__ = ["Text", "PackedTexts", "Patterns", "SmError", "histogram", "order", "count", "count_async", "report",
            "report_async", "count_batch", "version", "device_cus"]
 
 ORDER_KINDS = {"ltr": SM_ORDER_LTR, "freq": SM_ORDER_FREQ, "h": SM_ORDER_H, "hs": SM_ORDER_HS}
@@ -194,42 +194,92 @@ def report_async(t, p, out: torch.Tensor, total: torch.Tensor, order=None, peel=
                                  out.data_ptr(), out.numel(), total.data_ptr(), _stream(stream)))
 
 
+_QUERY_DT = np.dtype([("text_id", "<u4"), ("flags", "<u4"), ("p", "<u8"), ("m", "<u8"), ("order", "<u8")])
+_TEXT_DT = np.dtype([("t", "<u8"), ("n", "<u8"), ("hist", "<u8")])
+
+
+class PackedTexts:
+    """Many texts stored back to back in one device uint8 buffer: text i is
+    buf[offsets[i] : offsets[i] + lengths[i]].  hists (optional, host, shape
+    (ntexts, 256)) enables frequency orders and the bitmap mode."""
+
+    def __init__(self, buf: torch.Tensor, offsets, lengths, hists=None):
+        _dev_text(buf)
+        self.buf = buf
+        self.offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+        self.lengths = np.ascontiguousarray(lengths, dtype=np.uint64)
+        if self.offsets.shape != self.lengths.shape:
+            raise ValueError("offsets and lengths differ in size")
+        if self.offsets.size and int((self.offsets + self.lengths).max()) > buf.numel():
+            raise ValueError("a text runs past the end of the buffer")
+        self.hists = None if hists is None else np.ascontiguousarray(hists, dtype=np.uint64).reshape(-1, 256)
+
+    def __len__(self):
+        return int(self.offsets.size)
+
+    def table(self) -> np.ndarray:
+        t = np.zeros(max(len(self), 1), dtype=_TEXT_DT)
+        t["t"][:len(self)] = np.uint64(self.buf.data_ptr()) + self.offsets
+        t["n"][:len(self)] = self.lengths
+        if self.hists is not None:
+            t["hist"][:len(self)] = np.uint64(self.hists.ctypes.data) + 2048 * np.arange(len(self), dtype=np.uint64)
+        return t
+
+
 def count_batch(texts: Sequence, queries: Iterable, peel=None, tile_kib=None, wgs_per_cu=None,
                 stream=None, use_hist: bool = True) -> torch.Tensor:
     """Counts of many (text_id, pattern[, order]) queries in one persistent launch (asynchronous).
 
     Returns a device int64 tensor with one count per query.  Queries without an
     explicit order use the frequency order when the text's histogram is known
-    (texts given as Text objects and use_hist), else left to right.
+    (texts given as Text objects and use_hist), else left to right.  Texts with
+    a histogram and at least 32 queries run in the bitmap mode.
     """
-    texts = list(texts)
-    tarr = (sm_text * max(len(texts), 1))()
+    assert _TEXT_DT.itemsize == ctypes.sizeof(sm_text) and _QUERY_DT.itemsize == ctypes.sizeof(sm_query)
     keep = []
     dev = None
-    for i, tx in enumerate(texts):
-        ptr, n = _dev_text(tx)
-        dev = dev or (tx.t.device if isinstance(tx, Text) else tx.device)
-        h = None
-        if use_hist and isinstance(tx, Text):
-            h = np.ascontiguousarray(tx.hist, dtype=np.uint64)
-            keep.append(h)
-        tarr[i] = sm_text(ptr, n, _ptr(h))
+    if isinstance(texts, PackedTexts):
+        tarr, dev = texts.table(), texts.buf.device
+        keep.append(texts)
+        texts = [None] * len(texts)
+    else:
+        texts = list(texts)
+        tarr = np.zeros(max(len(texts), 1), dtype=_TEXT_DT)
+        for i, tx in enumerate(texts):
+            ptr, n = _dev_text(tx)
+            dev = dev or (tx.t.device if isinstance(tx, Text) else tx.device)
+            h = 0
+            if use_hist and isinstance(tx, Text):
+                ha = np.ascontiguousarray(tx.hist, dtype=np.uint64)
+                keep.append(ha)
+                h = ha.ctypes.data
+            tarr[i] = (ptr, n, h)
     qs = list(queries)
-    qarr = (sm_query * max(len(qs), 1))()
-    for i, q in enumerate(qs):
-        tid, p = int(q[0]), _pat(q[1])
-        o = None
-        if len(q) > 2 and q[2] is not None:
-            tx = texts[tid] if 0 <= tid < len(texts) else None
-            o = _resolve_order(q[2], p, tx)
-        keep.append(p)
-        if o is not None:
-            keep.append(o)
-        qarr[i] = sm_query(tid, 0, _ptr(p), p.size, _ptr(o))
-    out = torch.empty(max(len(qs), 1), dtype=torch.int64, device=dev or "cuda")
-    check(load().sm_count_batch(qarr, len(qs), tarr, len(texts), out.data_ptr(),
+    nq = len(qs)
+    qarr = np.zeros(max(nq, 1), dtype=_QUERY_DT)
+    if nq:
+        pats = [_pat(q[1]) for q in qs]
+        lens = np.fromiter((p.size for p in pats), dtype=np.uint64, count=nq)
+        blob = np.concatenate(pats) if int(lens.sum()) else np.zeros(1, dtype=np.uint8)
+        keep.append(blob)
+        offs = np.zeros(nq, dtype=np.uint64)
+        np.cumsum(lens[:-1], out=offs[1:])
+        qarr["text_id"][:nq] = np.fromiter((int(q[0]) for q in qs), dtype=np.int64, count=nq).astype(np.uint32)
+        qarr["p"][:nq] = np.where(lens > 0, np.uint64(blob.ctypes.data) + offs, 0)
+        qarr["m"][:nq] = lens
+        for i, q in enumerate(qs):
+            if len(q) > 2 and q[2] is not None:
+                tid = int(q[0])
+                tx = texts[tid] if 0 <= tid < len(texts) else None
+                o = _resolve_order(q[2], pats[i], tx)
+                if o is not None:
+                    keep.append(o)
+                    qarr["order"][i] = o.ctypes.data
+    out = torch.empty(max(nq, 1), dtype=torch.int64, device=dev or "cuda")
+    check(load().sm_count_batch(qarr.ctypes.data_as(ctypes.POINTER(sm_query)), nq,
+                                tarr.ctypes.data_as(ctypes.POINTER(sm_text)), len(texts), out.data_ptr(),
                                 _params(peel, tile_kib, wgs_per_cu), _stream(stream)))
-    return out[:len(qs)]
+    return out[:nq]
 
 
 # ------------------------------------------------------------- prepared patterns

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cstring>
 #include <deque>
+#include <memory>
 #include <mutex>
 #include <numeric>
 #include <string>
@@ -196,12 +197,22 @@ int ring_commit(Dev &d, Upload &u, hipStream_t s)
 
 // ------------------------------------------------------------ validation
 
-int check_text(const uint8_t *t, uint64_t n)
+// The allocation the previous text of one call was found in: texts packed
+// into one buffer are then validated without another runtime query.  Scoped
+// to a single API call, so a freed and reused range is never trusted.
+struct AllocCache {
+    uintptr_t base = 0, end = 0;
+};
+
+int check_text(const uint8_t *t, uint64_t n, AllocCache *cache = nullptr)
 {
     if (n == 0)
         return SM_OK;
     if (!t)
         return fail(SM_EINVAL, "t is NULL with n > 0");
+    const uintptr_t a = reinterpret_cast<uintptr_t>(t);
+    if (cache && a >= cache->base && a + n >= a && a + n <= cache->end)
+        return SM_OK;
     hipPointerAttribute_t attr;
     hipError_t e = hipPointerGetAttributes(&attr, t);
     if (e != hipSuccess) {
@@ -210,6 +221,20 @@ int check_text(const uint8_t *t, uint64_t n)
     }
     if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
         return fail(SM_EINVAL, "t is not device memory");
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    e = hipMemGetAddressRange(&base, &size, reinterpret_cast<hipDeviceptr_t>(const_cast<uint8_t *>(t)));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SM_EINVAL, "t is not inside a device allocation");
+    }
+    const uintptr_t b = reinterpret_cast<uintptr_t>(base);
+    if (a + n < a || a + n > b + size)
+        return fail(SM_EINVAL, "[t, t + n) runs past the end of its device allocation");
+    if (cache) {
+        cache->base = b;
+        cache->end = b + size;
+    }
     return SM_OK;
 }
 
@@ -241,12 +266,33 @@ void order_ltr(uint64_t m, int32_t *o)
         o[j] = (int32_t)j;
 }
 
-// Section 2.2: increasing symbol frequency; equal frequencies keep position order.
-void order_by_freq(const uint8_t *p, uint64_t m, const uint64_t *hist, int32_t *o)
-{
-    order_ltr(m, o);
-    std::stable_sort(o, o + m, [&](int32_t a, int32_t b) { return hist[p[a]] < hist[p[b]]; });
-}
+// Section 2.2: increasing symbol frequency; equal frequencies keep position
+// order.  A stable counting sort on frequency ranks: rank[b] orders the
+// distinct frequencies (equal frequencies share a rank), so one FreqRanks
+// serves every pattern planned against the same histogram.
+struct FreqRanks {
+    uint16_t rank[256];
+    uint32_t nranks = 0;
+    explicit FreqRanks(const uint64_t *hist)
+    {
+        std::vector<uint64_t> v(hist, hist + 256);
+        std::sort(v.begin(), v.end());
+        v.erase(std::unique(v.begin(), v.end()), v.end());
+        nranks = (uint32_t)v.size();
+        for (int b = 0; b < 256; ++b)
+            rank[b] = (uint16_t)(std::lower_bound(v.begin(), v.end(), hist[b]) - v.begin());
+    }
+    void order(const uint8_t *p, uint64_t m, int32_t *o, std::vector<uint32_t> &cnt) const
+    {
+        cnt.assign(nranks + 1, 0);
+        for (uint64_t j = 0; j < m; ++j)
+            cnt[rank[p[j]] + 1]++;
+        for (uint32_t r = 0; r < nranks; ++r)
+            cnt[r + 1] += cnt[r];
+        for (uint64_t j = 0; j < m; ++j)
+            o[cnt[rank[p[j]]]++] = (int32_t)j;
+    }
+};
 
 // Section 2.4, 1-based listing 1, m, 4, 7, ..., 3, 6, ..., 2, 5, ...: position 1,
 // position m, then the residue chains 1, 0, 2 (mod 3) upward from 4, 3, 2,
@@ -518,8 +564,11 @@ struct PlanQuery {
     uint64_t idx;     // caller's query index
     uint32_t text;
     uint64_t m;
-    uint32_t bucket;  // halo bucket
+    uint32_t bucket;  // halo (byte tiles) or pattern-length (bitmaps) bucket
 };
+
+// A text runs in bitmap mode when it has a histogram and at least this many queries.
+constexpr uint64_t kBmMinQueries = 32;
 
 }  // namespace
 
@@ -623,11 +672,13 @@ int32_t sm_order(int32_t kind, const uint8_t *p, uint64_t m, const uint64_t *his
         return fail(SM_EINVAL, "p is NULL");
     switch (kind) {
     case SM_ORDER_LTR: order_ltr(m, order_out); return SM_OK;
-    case SM_ORDER_FREQ:
+    case SM_ORDER_FREQ: {
         if (!hist_host)
             return fail(SM_EINVAL, "SM_ORDER_FREQ needs hist_host");
-        order_by_freq(p, m, hist_host, order_out);
+        std::vector<uint32_t> cnt;
+        FreqRanks(hist_host).order(p, m, order_out, cnt);
         return SM_OK;
+    }
     case SM_ORDER_H: order_fixed_h(m, order_out); return SM_OK;
     case SM_ORDER_HS: order_fixed_hs(p, m, order_out); return SM_OK;
     default: return fail(SM_EINVAL, "unknown order kind");
@@ -739,6 +790,9 @@ int32_t sm_patterns_create_ordered(uint64_t np, const uint8_t *const *p, const u
         return fail(SM_EINVAL, "p or m is NULL");
     std::vector<std::vector<int32_t>> ords(np);
     std::vector<const int32_t *> optr(np, nullptr);
+    const uint64_t zero_hist[256] = {};
+    const FreqRanks ranks(hist_host ? hist_host : zero_hist);
+    std::vector<uint32_t> cnt;
     for (uint64_t i = 0; i < np; ++i) {
         if (m[i] == 0 || m[i] >= (1ull << 31) || !p[i])
             return fail(SM_EINVAL, "pattern " + std::to_string(i) + ": bad pattern or length");
@@ -746,7 +800,7 @@ int32_t sm_patterns_create_ordered(uint64_t np, const uint8_t *const *p, const u
             continue;
         ords[i].resize(m[i]);
         if (kind == SM_ORDER_FREQ)
-            order_by_freq(p[i], m[i], hist_host, ords[i].data());
+            ranks.order(p[i], m[i], ords[i].data(), cnt);
         else if (kind == SM_ORDER_H)
             order_fixed_h(m[i], ords[i].data());
         else
@@ -841,10 +895,13 @@ int32_t sm_count_batch(const sm_query *q, uint64_t nq, const sm_text *texts, uin
         return SM_OK;
     if (!q || !counts_dev)
         return fail(SM_EINVAL, "q or counts_dev is NULL");
+    if (nq >= (1ull << 32))
+        return fail(SM_EINVAL, "too many queries");
     if (nt > 0 && !texts)
         return fail(SM_EINVAL, "texts is NULL");
+    AllocCache cache;
     for (uint64_t i = 0; i < nt; ++i) {
-        int rc = check_text(texts[i].t, texts[i].n);
+        int rc = check_text(texts[i].t, texts[i].n, &cache);
         if (rc < 0)
             return fail(rc, "text " + std::to_string(i) + ": " + g_err);
     }
@@ -866,21 +923,61 @@ int32_t sm_count_batch(const sm_query *q, uint64_t nq, const sm_text *texts, uin
 
     const int cpl = (params && (params->tile_kib == 4 || params->tile_kib == 8 || params->tile_kib == 16))
                         ? params->tile_kib / 4
-                        : 4;
+                        : 2;
     const uint64_t T = 4096ull * cpl;
     const int rdef = (params && params->peel > 0) ? std::min<int>(params->peel, (int)kMaxPeel) : 2;
-    const int wpc = (params && params->wgs_per_cu > 0) ? std::min(params->wgs_per_cu, 32) : 8;
+    const int wpc = (params && params->wgs_per_cu > 0) ? std::min(params->wgs_per_cu, 32) : 6;
     const uint64_t target = (uint64_t)std::max(d->cus, 1) * (uint64_t)wpc;
-    const uint64_t max_halo = kMaxLds - T - kQChunk * sizeof(uint32_t);
+    // two LDS tile buffers of T + halo and the query counters must fit
+    const uint64_t max_halo = (kMaxLds - kQChunk * sizeof(uint32_t)) / 2 - T;
 
-    // Split queries: staged (halo fits next to the tile) and long (global kernel).
-    std::vector<PlanQuery> staged, longq;
-    uint64_t total_steps = 0;
+    // ---- per-text alphabets (bitmap mode needs the histogram)
+    std::vector<std::vector<uint8_t>> smaps(nt);
+    std::vector<uint32_t> nslots(nt, 0);
+    std::vector<uint64_t> nbm(nt, 0);
+    for (uint64_t i = 0; i < nt; ++i) {
+        if (!texts[i].hist)
+            continue;
+        smaps[i].assign(256, 0xFF);
+        for (int b = 0; b < 256; ++b)
+            if (texts[i].hist[b])
+                smaps[i][b] = (uint8_t)nslots[i]++;
+    }
+    auto bm_wps = [](uint64_t m_max) { return (uint32_t)round_up(258 + ceil_div(m_max, 32), 4); };
+    auto bm_lds = [&](uint32_t slots, uint32_t wps) {
+        return (uint64_t)slots * wps * 4 + 256 + kBmQChunk * sizeof(uint32_t);
+    };
+    auto bm_bucket = [](uint64_t m) -> uint32_t { return m <= 256 ? 256 : (m <= 1024 ? 1024 : 4096); };
+    // a text qualifies if its alphabet fits next to the largest bucket it needs
+    std::vector<uint8_t> text_bm(nt, 0);
     for (uint64_t i = 0; i < nq; ++i) {
-        const uint64_t n = texts[q[i].text_id].n;
+        const uint32_t t = q[i].text_id;
+        if (texts[t].hist && q[i].m <= texts[t].n && q[i].m <= 4096 && nslots[t] > 0 &&
+            bm_lds(nslots[t], bm_wps(bm_bucket(q[i].m))) <= kBmMaxLds)
+            nbm[t]++;
+    }
+    for (uint64_t t = 0; t < nt; ++t)
+        text_bm[t] = nbm[t] >= kBmMinQueries;
+
+    // ---- classify queries
+    std::vector<PlanQuery> staged, longq, bmq;
+    uint64_t total_steps = 0, total_bm_steps = 0;
+    for (uint64_t i = 0; i < nq; ++i) {
+        const uint32_t t = q[i].text_id;
+        const uint64_t n = texts[t].n;
         if (q[i].m > n)
             continue;  // count stays 0
-        PlanQuery pq{i, q[i].text_id, q[i].m, 0};
+        if (text_bm[t] && q[i].m <= 4096 && bm_lds(nslots[t], bm_wps(bm_bucket(q[i].m))) <= kBmMaxLds) {
+            bool absent = false;
+            for (uint64_t j = 0; j < q[i].m && !absent; ++j)
+                absent = smaps[t][q[i].p[j]] == 0xFF;
+            if (absent)
+                continue;  // a symbol the text lacks: count 0
+            bmq.push_back({i, t, q[i].m, bm_bucket(q[i].m)});
+            total_bm_steps += q[i].m;
+            continue;
+        }
+        PlanQuery pq{i, t, q[i].m, 0};
         const uint64_t halo = halo_for(q[i].m);
         uint64_t b = 64;
         while (b < halo)
@@ -892,81 +989,126 @@ int32_t sm_count_batch(const sm_query *q, uint64_t nq, const sm_text *texts, uin
             longq.push_back(pq);
         total_steps += q[i].m + kStepPad;
     }
-    std::stable_sort(staged.begin(), staged.end(), [](const PlanQuery &a, const PlanQuery &b) {
+    auto by_text_bucket = [](const PlanQuery &a, const PlanQuery &b) {
         return a.text != b.text ? a.text < b.text : a.bucket < b.bucket;
-    });
+    };
+    std::stable_sort(staged.begin(), staged.end(), by_text_bucket);
+    std::stable_sort(bmq.begin(), bmq.end(), by_text_bucket);
 
-    // Chunks of one (text, bucket) and at most kQChunk queries.
     struct Chunk {
         uint32_t text;
-        uint32_t q0, q1;  // into `staged`
+        uint32_t q0, q1;
         uint64_t m_min, m_max;
     };
-    std::vector<Chunk> chunks;
-    for (uint32_t i = 0; i < staged.size();) {
-        uint32_t j = i;
-        uint64_t mn = staged[i].m, mx = staged[i].m;
-        while (j < staged.size() && j - i < kQChunk && staged[j].text == staged[i].text &&
-               staged[j].bucket == staged[i].bucket) {
-            mn = std::min(mn, staged[j].m);
-            mx = std::max(mx, staged[j].m);
-            ++j;
+    auto make_chunks = [](const std::vector<PlanQuery> &v, uint32_t cap) {
+        std::vector<Chunk> out;
+        for (uint32_t i = 0; i < v.size();) {
+            uint32_t j = i;
+            uint64_t mn = v[i].m, mx = v[i].m;
+            while (j < v.size() && j - i < cap && v[j].text == v[i].text && v[j].bucket == v[i].bucket) {
+                mn = std::min(mn, v[j].m);
+                mx = std::max(mx, v[j].m);
+                ++j;
+            }
+            out.push_back({v[i].text, i, j, mn, mx});
+            i = j;
         }
-        chunks.push_back({staged[i].text, i, j, mn, mx});
-        i = j;
-    }
-    uint64_t tile_work = 0;
-    for (auto &c : chunks) {
-        const uint64_t first = reinterpret_cast<uintptr_t>(texts[c.text].t) & 15u;
-        tile_work += ceil_div(first + texts[c.text].n - c.m_min + 1, T);
-    }
-    const uint64_t span = std::max<uint64_t>(1, std::min<uint64_t>(256, tile_work / (target * 4)));
+        return out;
+    };
+    const std::vector<Chunk> chunks = make_chunks(staged, kQChunk);
+    const std::vector<Chunk> bchunks = make_chunks(bmq, kBmQChunk);
 
-    std::vector<BatchItem> items;
-    uint32_t halo_max = 0;
+    // ---- byte-tile chunks in one global tile space
+    std::vector<BatchChunk> bchunks_t;
+    std::vector<uint32_t> tile_chunk;
+    uint32_t halo_max = 16;
     for (auto &c : chunks) {
         const sm_text &tx = texts[c.text];
         const TextView tv = make_view(tx.t, tx.n);
         const uint64_t ntiles = ceil_div(tv.first + tx.n - c.m_min + 1, T);
-        const uint32_t halo = halo_for(c.m_max);
-        halo_max = std::max(halo_max, halo);
-        for (uint64_t t0 = 0; t0 < ntiles; t0 += span) {
-            BatchItem it{};
+        BatchChunk bc{};
+        bc.tv = tv;
+        bc.tile0 = tile_chunk.size();
+        bc.q_begin = c.q0;
+        bc.q_end = c.q1;
+        bc.halo = halo_for(c.m_max);
+        halo_max = std::max(halo_max, bc.halo);
+        tile_chunk.insert(tile_chunk.end(), ntiles, (uint32_t)bchunks_t.size());
+        bchunks_t.push_back(bc);
+    }
+
+    // ---- bitmap items
+    const uint64_t bm_per_cu_guess = 1;
+    const uint64_t bm_grid_target = (uint64_t)std::max(d->cus, 1) * bm_per_cu_guess;
+    uint64_t bm_work = 0;
+    for (auto &c : bchunks) {
+        const uint64_t first = reinterpret_cast<uintptr_t>(texts[c.text].t) & 15u;
+        bm_work += ceil_div(first + texts[c.text].n - c.m_min + 1, kBmT);
+    }
+    const uint64_t bspan = std::max<uint64_t>(1, bm_work / (bm_grid_target * 4));
+    std::vector<BmItem> bitems;
+    uint32_t bm_words = 0;
+    for (auto &c : bchunks) {
+        const sm_text &tx = texts[c.text];
+        const TextView tv = make_view(tx.t, tx.n);
+        const uint64_t ntiles = ceil_div(tv.first + tx.n - c.m_min + 1, kBmT);
+        const uint32_t wps = bm_wps(c.m_max);
+        bm_words = std::max(bm_words, nslots[c.text] * wps);
+        for (uint64_t t0 = 0; t0 < ntiles; t0 += bspan) {
+            BmItem it{};
             it.tv = tv;
             it.tile_begin = t0;
-            it.tile_end = std::min(ntiles, t0 + span);
+            it.tile_end = std::min(ntiles, t0 + bspan);
             it.q_begin = c.q0;
             it.q_end = c.q1;
-            it.halo = halo;
-            items.push_back(it);
+            it.wps = wps;
+            it.nslots = nslots[c.text];
+            it.smap = nullptr;  // set after upload layout is known
+            bitems.push_back(it);
         }
     }
 
-    // One upload: [items | queries | steps].
-    const size_t items_bytes = round_up(items.size() * sizeof(BatchItem), 256);
-    const size_t queries_bytes = round_up(std::max<size_t>(staged.size(), 1) * sizeof(BatchQuery), 256);
-    const size_t long_off = items_bytes + queries_bytes;
-    const size_t bytes = long_off + total_steps * sizeof(uint64_t);
+    // ---- one upload: [chunks | tile->chunk | queries | steps | bitmap items | bitmap queries | outs |
+    //                   smaps | bitmap steps]
+    const size_t o_items = 0;
+    const size_t o_tchunk = o_items + round_up(bchunks_t.size() * sizeof(BatchChunk), 256);
+    const size_t o_queries = o_tchunk + round_up(tile_chunk.size() * sizeof(uint32_t), 256);
+    const size_t o_steps = o_queries + round_up(std::max<size_t>(staged.size(), 1) * sizeof(BatchQuery), 256);
+    const size_t o_bitems = o_steps + round_up(total_steps * sizeof(uint64_t), 256);
+    const size_t o_bq = o_bitems + round_up(bitems.size() * sizeof(BmItem), 256);
+    const size_t o_bout = o_bq + round_up(bmq.size() * sizeof(BmQuery), 256);
+    const size_t o_smap = o_bout + round_up(bmq.size() * sizeof(uint32_t), 256);
+    const size_t o_bsteps = o_smap + round_up(nt * 256, 256);
+    if (total_bm_steps >= (1ull << 32))
+        return fail(SM_EINVAL, "batch too large: pattern bytes in bitmap mode exceed 2^32");
+    const size_t bytes = o_bsteps + round_up(total_bm_steps * sizeof(uint32_t), 256);
     Upload u;
     SM_TRY(ring_reserve(*d, bytes, &u));
-    BatchItem *hi = reinterpret_cast<BatchItem *>(u.host);
-    BatchQuery *hq = reinterpret_cast<BatchQuery *>(u.host + items_bytes);
-    uint64_t *hs = reinterpret_cast<uint64_t *>(u.host + long_off);
-    std::copy(items.begin(), items.end(), hi);
+    std::copy(bchunks_t.begin(), bchunks_t.end(), reinterpret_cast<BatchChunk *>(u.host + o_items));
+    std::copy(tile_chunk.begin(), tile_chunk.end(), reinterpret_cast<uint32_t *>(u.host + o_tchunk));
+    BatchQuery *hq = reinterpret_cast<BatchQuery *>(u.host + o_queries);
+    uint64_t *hs = reinterpret_cast<uint64_t *>(u.host + o_steps);
     uint64_t soff = 0;
     std::vector<int32_t> ord;
+    std::vector<uint32_t> cnt;
+    std::vector<std::unique_ptr<FreqRanks>> ranks(nt);
+    auto order_of = [&](uint64_t qi) -> const int32_t * {
+        const sm_query &Q = q[qi];
+        if (Q.order)
+            return Q.order;
+        ord.resize(Q.m);
+        if (texts[Q.text_id].hist) {
+            if (!ranks[Q.text_id])
+                ranks[Q.text_id].reset(new FreqRanks(texts[Q.text_id].hist));
+            ranks[Q.text_id]->order(Q.p, Q.m, ord.data(), cnt);
+        } else {
+            order_ltr(Q.m, ord.data());
+        }
+        return ord.data();
+    };
     auto emit_steps = [&](uint64_t qi) -> uint64_t {
         const sm_query &Q = q[qi];
-        const int32_t *o = Q.order;
-        if (!o) {
-            ord.resize(Q.m);
-            if (texts[Q.text_id].hist)
-                order_by_freq(Q.p, Q.m, texts[Q.text_id].hist, ord.data());
-            else
-                order_ltr(Q.m, ord.data());
-            o = ord.data();
-        }
-        build_steps(Q.p, Q.m, o, hs + soff);
+        build_steps(Q.p, Q.m, order_of(qi), hs + soff);
         const uint64_t at = soff;
         soff += Q.m + kStepPad;
         return at;
@@ -985,34 +1127,95 @@ int32_t sm_count_batch(const sm_query *q, uint64_t nq, const sm_text *texts, uin
     std::vector<uint64_t> long_steps_off;
     for (auto &pq : longq)
         long_steps_off.push_back(emit_steps(pq.idx));
+    // bitmap part
+    BmItem *hbi = reinterpret_cast<BmItem *>(u.host + o_bitems);
+    BmQuery *hbq = reinterpret_cast<BmQuery *>(u.host + o_bq);
+    uint32_t *hbout = reinterpret_cast<uint32_t *>(u.host + o_bout);
+    uint8_t *hsm = u.host + o_smap;
+    uint32_t *hbs = reinterpret_cast<uint32_t *>(u.host + o_bsteps);
+    for (uint64_t t = 0; t < nt; ++t)
+        if (!smaps[t].empty())
+            std::copy(smaps[t].begin(), smaps[t].end(), hsm + 256 * t);
+    uint64_t bsoff = 0;
+    for (auto &c : bchunks) {
+        const uint32_t wps = bm_wps(c.m_max);
+        for (uint32_t i = c.q0; i < c.q1; ++i) {
+            const PlanQuery &pq = bmq[i];
+            const sm_query &Q = q[pq.idx];
+            const int32_t *o = order_of(pq.idx);
+            for (uint64_t l = 0; l < Q.m; ++l) {
+                const uint32_t j = (uint32_t)o[l];
+                const uint32_t slot = smaps[pq.text][Q.p[j]];
+                hbs[bsoff + l] = ((slot * wps + (j >> 5)) << 5) | (j & 31u);
+            }
+            BmQuery bq{};
+            bq.e0 = hbs[bsoff];
+            bq.e1 = Q.m > 1 ? hbs[bsoff + 1] : hbs[bsoff];
+            bq.steps_off = (uint32_t)bsoff;
+            bq.mr = (uint32_t)pq.m | ((uint32_t)std::min<uint64_t>((uint64_t)rdef, pq.m) << 24);
+            hbq[i] = bq;
+            hbout[i] = (uint32_t)pq.idx;
+            bsoff += Q.m;
+        }
+    }
+    {
+        size_t k = 0;
+        for (auto &c : bchunks) {
+            const uint64_t first = reinterpret_cast<uintptr_t>(texts[c.text].t) & 15u;
+            const uint64_t ntiles = ceil_div(first + texts[c.text].n - c.m_min + 1, kBmT);
+            for (uint64_t t0 = 0; t0 < ntiles; t0 += bspan) {
+                bitems[k].smap = u.dev + o_smap + 256 * c.text;
+                ++k;
+            }
+        }
+        std::copy(bitems.begin(), bitems.end(), hbi);
+    }
     SM_TRY(ring_copy(u, bytes, s));
 
-    if (!items.empty()) {
-        BatchArgs a{};
-        a.items = reinterpret_cast<const BatchItem *>(u.dev);
-        a.nitems = items.size();
-        a.queries = reinterpret_cast<const BatchQuery *>(u.dev + items_bytes);
-        a.steps = reinterpret_cast<const uint64_t *>(u.dev + long_off);
+    auto bail = [&](int rc, const std::string &msg) {
+        (void)ring_commit(*d, u, s);
+        return fail(rc, msg);
+    };
+    if (!bitems.empty()) {
+        BmArgs a{};
+        a.items = reinterpret_cast<const BmItem *>(u.dev + o_bitems);
+        a.nitems = bitems.size();
+        a.queries = reinterpret_cast<const BmQuery *>(u.dev + o_bq);
+        a.outs = reinterpret_cast<const uint32_t *>(u.dev + o_bout);
+        a.steps = reinterpret_cast<const uint32_t *>(u.dev + o_bsteps);
         a.counts = counts;
-        a.tile_lds = (uint32_t)(T + halo_max);
-        const uint32_t lds = a.tile_lds + kQChunk * sizeof(uint32_t);
-        const uint64_t grid = std::min<uint64_t>(items.size(), target);
-        hipError_t e = launch_batch_staged(a, cpl, (unsigned)grid, lds, s);
-        if (e != hipSuccess) {
-            (void)ring_commit(*d, u, s);
-            return fail(SM_EDEVICE, std::string("batch launch: ") + hipGetErrorString(e));
-        }
+        a.bm_words = (uint32_t)round_up(bm_words, 4);
+        const uint32_t lds = a.bm_words * 4 + 256 + kBmQChunk * sizeof(uint32_t);
+        const uint64_t per_cu = std::max<uint64_t>(1, kBmMaxLds / lds);
+        const uint64_t grid = std::min<uint64_t>(bitems.size(), (uint64_t)std::max(d->cus, 1) * std::min<uint64_t>(per_cu, 2));
+        hipError_t e = launch_batch_bitmap(a, (unsigned)grid, lds, s);
+        if (e != hipSuccess)
+            return bail(SM_EDEVICE, std::string("bitmap batch launch: ") + hipGetErrorString(e));
+    }
+    if (!tile_chunk.empty()) {
+        BatchArgs a{};
+        a.chunks = reinterpret_cast<const BatchChunk *>(u.dev + o_items);
+        a.tile_chunk = reinterpret_cast<const uint32_t *>(u.dev + o_tchunk);
+        a.ntiles = tile_chunk.size();
+        a.queries = reinterpret_cast<const BatchQuery *>(u.dev + o_queries);
+        a.steps = reinterpret_cast<const uint64_t *>(u.dev + o_steps);
+        a.counts = counts;
+        a.halo_max = halo_max;
+        a.chunk_log2 = kChunkLog2;
+        const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(a.ntiles, 1ull << kChunkLog2), target));
+        hipError_t e = launch_batch_staged(a, cpl, (unsigned)grid, s);
+        if (e != hipSuccess)
+            return bail(SM_EDEVICE, std::string("batch launch: ") + hipGetErrorString(e));
     }
     for (size_t i = 0; i < longq.size(); ++i) {
         const PlanQuery &pq = longq[i];
         Tune tu{(int)std::min<uint64_t>((uint64_t)rdef, pq.m), 1, wpc, (int)kChunkLog2};
         int rc = launch_count(*d, make_view(texts[pq.text].t, texts[pq.text].n), pq.m,
-                              reinterpret_cast<const uint64_t *>(u.dev + long_off) + long_steps_off[i], tu,
+                              reinterpret_cast<const uint64_t *>(u.dev + o_steps) + long_steps_off[i], tu,
                               counts + pq.idx, nullptr, nullptr, s);
         if (rc < 0) {
             std::string msg = g_err;
-            (void)ring_commit(*d, u, s);
-            return fail(rc, msg);
+            return bail(rc, msg);
         }
     }
     return ring_commit(*d, u, s);

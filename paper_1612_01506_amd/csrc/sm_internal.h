@@ -44,11 +44,13 @@ struct CountArgs {
     unsigned long long *group_sums;  // report pass: += per-vector counts of each kGroupBlocks group
 };
 
-struct BatchItem {
+// Byte-tile batch: a chunk is one text and up to kQChunk queries of one
+// m-bucket; its tiles occupy global tile indices [tile0, tile0 + ntiles).
+struct BatchChunk {
     TextView tv;
-    uint64_t tile_begin, tile_end;  // tiles [tile_begin, tile_end) of the text
-    uint32_t q_begin, q_end;        // queries [q_begin, q_end), q_end - q_begin <= kQChunk
-    uint32_t halo;                  // LDS halo bytes for this item's queries
+    uint64_t tile0;
+    uint32_t q_begin, q_end;  // into the BatchQuery array
+    uint32_t halo;            // LDS halo bytes for the chunk's longest pattern
     uint32_t pad;
 };
 
@@ -62,12 +64,50 @@ struct BatchQuery {
 };
 
 struct BatchArgs {
-    const BatchItem *items;
-    uint64_t nitems;
+    const BatchChunk *chunks;
+    const uint32_t *tile_chunk;  // chunk of every global tile
+    uint64_t ntiles;             // global tiles
     const BatchQuery *queries;
     const uint64_t *steps;
     unsigned long long *counts;
-    uint32_t tile_lds;   // LDS bytes for tile + largest halo; query counters follow
+    uint32_t halo_max;           // largest chunk halo (LDS buffer size)
+    uint32_t chunk_log2;         // tiles are dealt in chunks of 2^chunk_log2
+};
+
+// Batched bitmap mode: per tile, one bitmap per symbol of the text's alphabet
+// (bit i of word w of slot c: the byte at tile position 32w + i is the
+// symbol of slot c), then every query of a chunk runs over the tile with one
+// funnel shift + AND per compare.
+constexpr uint32_t kBmWG = 1024;             // threads per bitmap workgroup: 16 waves
+constexpr uint32_t kBmWaves = kBmWG / 64;
+constexpr uint32_t kBmT = 8192;              // starts per bitmap tile: 4 vectors of 64 lanes x 32 bits
+constexpr uint32_t kBmQChunk = 1024;         // queries per bitmap work item
+constexpr uint32_t kBmMaxLds = 163840;       // LDS per workgroup on gfx950
+
+struct BmItem {
+    TextView tv;
+    uint64_t tile_begin, tile_end;  // tiles of kBmT starts
+    uint32_t q_begin, q_end;        // into the BmQuery array, at most kBmQChunk
+    uint32_t wps;                   // bitmap words per slot (multiple of 4) >= 258 + ceil(m_max / 32)
+    uint32_t nslots;                // slots of the text's alphabet
+    const uint8_t *smap;            // 256 bytes: symbol -> slot, 0xFF if the symbol is absent
+};
+
+// Bitmap step entry (uint32): ((slot * wps + (j >> 5)) << 5) | (j & 31), j = pi(l).
+struct BmQuery {
+    uint32_t e0, e1;     // the first two step entries (e1 = e0 when m == 1)
+    uint32_t steps_off;  // index of the query's full step table in the bitmap step pool
+    uint32_t mr;         // m | r << 24 (m <= 4096, peel r in 1..min(8, m))
+};
+
+struct BmArgs {
+    const BmItem *items;
+    uint64_t nitems;
+    const BmQuery *queries;
+    const uint32_t *outs;  // output slot of each query
+    const uint32_t *steps;
+    unsigned long long *counts;
+    uint32_t bm_words;  // LDS words reserved for bitmaps (max nslots * wps over the items)
     uint32_t pad;
 };
 
@@ -83,6 +123,7 @@ hipError_t launch_fill_report(uint32_t *bc, uint64_t nblocks, unsigned long long
                               hipStream_t s);
 hipError_t launch_hist(const TextView &tv, unsigned long long *hist, unsigned grid, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v, hipStream_t s);
-hipError_t launch_batch_staged(const BatchArgs &a, int cpl, unsigned grid, uint32_t lds_bytes, hipStream_t s);
+hipError_t launch_batch_staged(const BatchArgs &a, int cpl, unsigned grid, hipStream_t s);
+hipError_t launch_batch_bitmap(const BmArgs &a, unsigned grid, uint32_t lds_bytes, hipStream_t s);
 
 }  // namespace smk

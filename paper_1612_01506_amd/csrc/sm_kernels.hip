@@ -34,6 +34,30 @@ namespace smk {
 
 // ------------------------------------------------------------------ helpers
 
+// Index of this wave in the workgroup, as a wave-uniform (scalar) value.
+__device__ __forceinline__ uint32_t wave_id()
+{
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+}
+
+// Load from a table the kernels never write (step tables, query records,
+// work lists) through the constant address space, so a wave-uniform address
+// becomes a scalar load.
+template <typename T>
+__device__ __forceinline__ T ldc(const T *p)
+{
+    static_assert(sizeof(T) % 4 == 0, "whole dwords only");
+    constexpr int N = sizeof(T) / 4;
+    const __attribute__((address_space(4))) uint32_t *q = (const __attribute__((address_space(4))) uint32_t *)(p);
+    uint32_t w[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+        w[i] = q[i];
+    T out;
+    __builtin_memcpy(&out, w, sizeof(T));
+    return out;
+}
+
 __device__ __forceinline__ uint32_t step_pos(uint64_t st) { return (uint32_t)st; }
 __device__ __forceinline__ uint32_t step_rep(uint64_t st) { return (uint32_t)(st >> 32); }
 
@@ -120,12 +144,25 @@ __device__ __forceinline__ uint32_t count_alive(const uint32_t (&d)[4])
     return c;
 }
 
+// Wave-wide reductions with DPP moves (no LDS traffic): quad permutes, row
+// shifts by 4 and 8, then row broadcasts of lanes 15 and 31; lane 63 ends
+// with the whole wave's value.  Lanes a DPP move does not write receive
+// `ident`.
+template <int CTRL, int ROWMASK = 0xf>
+__device__ __forceinline__ uint32_t dpp_mov(uint32_t v, uint32_t ident)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)ident, (int)v, CTRL, ROWMASK, 0xf, false);
+}
+
 __device__ __forceinline__ uint32_t wave_sum32(uint32_t v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-        v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp_mov<0xb1>(v, 0u);        // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4e>(v, 0u);        // quad_perm [2,3,0,1]
+    v += dpp_mov<0x114>(v, 0u);       // row_shr:4
+    v += dpp_mov<0x118>(v, 0u);       // row_shr:8
+    v += dpp_mov<0x142, 0xa>(v, 0u);  // row_bcast:15 into rows 1 and 3
+    v += dpp_mov<0x143, 0xc>(v, 0u);  // row_bcast:31 into rows 2 and 3
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
 __device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v)
@@ -170,10 +207,14 @@ constexpr uint32_t kVerifyMax = 4;  // most alive starts verified one at a time
 
 __device__ __forceinline__ uint32_t wave_min32(uint32_t v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-        v = min(v, (uint32_t)__shfl_xor((int)v, o, 64));
-    return v;
+    const uint32_t I = 0xFFFFFFFFu;
+    v = min(v, dpp_mov<0xb1>(v, I));
+    v = min(v, dpp_mov<0x4e>(v, I));
+    v = min(v, dpp_mov<0x114>(v, I));
+    v = min(v, dpp_mov<0x118>(v, I));
+    v = min(v, dpp_mov<0x142, 0xa>(v, I));
+    v = min(v, dpp_mov<0x143, 0xc>(v, I));
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
 // Verify each alive start of the vector on compares l..m-1, 64 compares at
@@ -236,7 +277,7 @@ __device__ __forceinline__ bool search_tail(const uint64_t *steps, uint32_t l, u
 {
     const uint32_t l1 = min(m, l + kTestEach);
     for (; l < l1; ++l) {
-        tx.step(steps[l], d);
+        tx.step(ldc(&steps[l]), d);
         if (!any_alive(d))
             return false;
     }
@@ -251,7 +292,7 @@ __device__ __forceinline__ bool search_tail(const uint64_t *steps, uint32_t l, u
         const uint32_t g = min(kGroup, m - l);
 #pragma unroll 1
         for (uint32_t u = 0; u < g; ++u)
-            tx.step(steps[l + u], d);
+            tx.step(ldc(&steps[l + u]), d);
         l += g;
         if (!any_alive(d))
             return false;
@@ -280,7 +321,7 @@ __device__ __forceinline__ bool search_vector_rt(const uint64_t *steps, uint32_t
                                                  uint32_t (&d)[4], const Text &tx)
 {
     for (uint32_t l = 0; l < r; ++l)
-        tx.step(steps[l], d);
+        tx.step(ldc(&steps[l]), d);
     if (!any_alive(d))
         return false;
     return search_tail(steps, r, m, lane, d, tx);
@@ -389,7 +430,7 @@ __global__ __launch_bounds__(kWG) void k_count_staged(CountArgs a)
 {
     extern __shared__ __align__(16) uint8_t lds[];
     constexpr uint32_t T = kWG * 16u * CPL;
-    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = wave_id();
     const uint32_t hch = a.halo >> 4;
     const uint32_t TB = T + a.halo;
     const uint64_t kmask = (1ull << a.chunk_log2) - 1u;
@@ -400,7 +441,7 @@ __global__ __launch_bounds__(kWG) void k_count_staged(CountArgs a)
     uint64_t pk[R];
 #pragma unroll
     for (int l = 0; l < R; ++l)
-        pk[l] = a.steps[l];
+        pk[l] = ldc(&a.steps[l]);
 
     unsigned long long acc = 0;
     uint64_t tile = tile_of(0);
@@ -448,9 +489,9 @@ __global__ __launch_bounds__(kWG) void k_count_global(CountArgs a)
     uint64_t pk[R];
 #pragma unroll
     for (int l = 0; l < R; ++l)
-        pk[l] = a.steps[l];
+        pk[l] = ldc(&a.steps[l]);
     unsigned long long acc = 0;
-    for (uint64_t blk = (uint64_t)blockIdx.x * kWaves + (tid >> 6); blk < a.nblocks; blk += nw) {
+    for (uint64_t blk = (uint64_t)blockIdx.x * kWaves + wave_id(); blk < a.nblocks; blk += nw) {
         const uint64_t wb = blk * kBlock;
         uint32_t d[4];
         init_alive(wb, a.tv.first, a.last, lane, d);
@@ -544,7 +585,7 @@ __global__ __launch_bounds__(kWG) void k_report_write(CountArgs a, uint32_t r, c
     extern __shared__ __align__(16) uint8_t wlds[];
     __shared__ uint32_t off[kGroupBlocks];
     __shared__ uint32_t wsum[kWaves];
-    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = wave_id();
     uint8_t *mine = wlds + wave * win;
     for (uint64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
         if (gs[g] == 0)
@@ -621,7 +662,7 @@ __global__ __launch_bounds__(kWG) void k_report_write(CountArgs a, uint32_t r, c
 __global__ __launch_bounds__(kWG) void k_hist(TextView tv, unsigned long long *hist)
 {
     __shared__ uint32_t h[kWaves][256];
-    const uint32_t tid = threadIdx.x, wave = tid >> 6;
+    const uint32_t tid = threadIdx.x, wave = wave_id();
     for (uint32_t i = tid; i < kWaves * 256u; i += kWG)
         (&h[0][0])[i] = 0u;
     __syncthreads();
@@ -675,66 +716,200 @@ __global__ void k_fill_u64(unsigned long long *p, uint64_t n, unsigned long long
 
 // ------------------------------------------------------------ batch kernel
 
-// Persistent batched count: work item = (text, contiguous tile range, chunk
-// of <= kQChunk queries of one m-bucket).  The workgroup stages each tile of
-// the range once and runs every query of the chunk over it; per-query counts
-// gather in LDS and are flushed with one 64-bit atomicAdd per nonzero query
-// and item.
+// Persistent batched count over byte tiles.  All chunks' tiles form one
+// global tile space dealt out like the single search (2^chunk_log2 tiles per
+// deal, round robin), with the same double-buffered LDS DMA; the next tile
+// may belong to another text.  Every query of the tile's chunk runs over the
+// staged tile; per-query counts gather in LDS and are flushed (one 64-bit
+// atomicAdd per nonzero query) whenever the workgroup moves to another chunk.
 template <int CPL>
 __global__ __launch_bounds__(kWG) void k_batch_staged(BatchArgs a)
 {
     extern __shared__ __align__(16) uint8_t lds[];
     constexpr uint32_t T = kWG * 16u * CPL;
-    uint32_t *qc = reinterpret_cast<uint32_t *>(lds + a.tile_lds);
-    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
-    for (uint64_t it = blockIdx.x; it < a.nitems; it += gridDim.x) {
-        const BatchItem I = a.items[it];
-        const uint32_t nq = I.q_end - I.q_begin;
-        const uint32_t hch = I.halo >> 4;
-        __syncthreads();  // previous item's counters flushed
-        for (uint32_t i = tid; i < nq; i += kWG)
-            qc[i] = 0u;
-        uint4 pre[CPL];
-        uint4 hpre = make_uint4(0, 0, 0, 0);
-        if (I.tile_begin < I.tile_end)
-            fetch_tile<CPL>(I.tv, I.tile_begin * T, tid, hch, pre, hpre);
-        for (uint64_t tile = I.tile_begin; tile < I.tile_end; ++tile) {
-            const uint64_t ts = tile * T;
-            __syncthreads();
-            put_tile<CPL>(lds, tid, hch, pre, hpre);
-            if (hch > kWG)
-                put_halo_rest(lds + T, I.tv, ts + T, tid, hch);
-            __syncthreads();
-            if (tile + 1 < I.tile_end)
-                fetch_tile<CPL>(I.tv, ts + T, tid, hch, pre, hpre);
-            for (uint32_t q = I.q_begin; q < I.q_end; ++q) {
-                const BatchQuery Q = a.queries[q];
-                const uint64_t *st = a.steps + Q.steps_off;
-                uint32_t c = 0;
-#pragma unroll 1
-                for (int b = 0; b < CPL; ++b) {
-                    const uint32_t boff = (wave * CPL + b) * kBlock;
-                    const uint64_t wb = ts + boff;
-                    if (wb > Q.last)
-                        break;
-                    uint32_t d[4];
-                    init_alive(wb, I.tv.first, Q.last, lane, d);
-                    const LdsText tx{lds + boff, lds + boff + 4u * lane};
-                    if (search_vector_rt(st, Q.r, Q.m, lane, d, tx))
-                        c += count_alive(d);
-                }
-                if (__any(c != 0u)) {
-                    const uint32_t s = wave_sum32(c);
-                    if (lane == 0)
-                        atomicAdd(&qc[q - I.q_begin], s);
-                }
-            }
-        }
-        __syncthreads();
-        for (uint32_t i = tid; i < nq; i += kWG) {
+    const uint32_t TB = T + a.halo_max;
+    uint32_t *qc = reinterpret_cast<uint32_t *>(lds + 2u * TB);
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = wave_id();
+    const uint64_t kmask = (1ull << a.chunk_log2) - 1u;
+    auto tile_of = [&](uint64_t i) {
+        return (((uint64_t)blockIdx.x + (i >> a.chunk_log2) * gridDim.x) << a.chunk_log2) + (i & kmask);
+    };
+    auto flush = [&](uint32_t c) {
+        const BatchChunk C = ldc(&a.chunks[c]);
+        for (uint32_t i = tid; i < C.q_end - C.q_begin; i += kWG) {
             const uint32_t v = qc[i];
             if (v)
-                atomicAdd(&a.counts[a.queries[I.q_begin + i].out], (unsigned long long)v);
+                atomicAdd(&a.counts[a.queries[C.q_begin + i].out], (unsigned long long)v);
+        }
+    };
+
+    uint64_t g = tile_of(0);
+    if (g < a.ntiles) {
+        const BatchChunk C = ldc(&a.chunks[ldc(&a.tile_chunk[g])]);
+        dma_tile<CPL>(C.tv, (g - C.tile0) * T, tid, C.halo >> 4, lds);
+    }
+    uint32_t cur = 0xFFFFFFFFu;
+    for (uint64_t i = 0; g < a.ntiles; ++i) {
+        const uint32_t c = ldc(&a.tile_chunk[g]);
+        const BatchChunk C = ldc(&a.chunks[c]);
+        const uint64_t ts = (g - C.tile0) * T;
+        uint8_t *buf = lds + (i & 1u) * TB;
+        const uint64_t gn = tile_of(i + 1);
+        wait_dma();
+        __syncthreads();  // tile visible; the other buffer is free
+        if (c != cur) {
+            if (cur != 0xFFFFFFFFu)
+                flush(cur);
+            __syncthreads();
+            for (uint32_t k = tid; k < C.q_end - C.q_begin; k += kWG)
+                qc[k] = 0u;
+            __syncthreads();
+            cur = c;
+        }
+        if (gn < a.ntiles) {
+            const BatchChunk N = ldc(&a.chunks[ldc(&a.tile_chunk[gn])]);
+            dma_tile<CPL>(N.tv, (gn - N.tile0) * T, tid, N.halo >> 4, lds + ((i + 1) & 1u) * TB);
+        }
+        for (uint32_t q = C.q_begin; q < C.q_end; ++q) {
+            const BatchQuery Q = ldc(&a.queries[q]);
+            const uint64_t *st = a.steps + Q.steps_off;
+            uint32_t cnt = 0;
+#pragma unroll 1
+            for (int b = 0; b < CPL; ++b) {
+                const uint32_t boff = (wave * CPL + b) * kBlock;
+                const uint64_t wb = ts + boff;
+                if (wb > Q.last)
+                    break;
+                uint32_t d[4];
+                init_alive(wb, C.tv.first, Q.last, lane, d);
+                const LdsText tx{buf + boff, buf + boff + 4u * lane};
+                if (search_vector_rt(st, Q.r, Q.m, lane, d, tx))
+                    cnt += count_alive(d);
+            }
+            if (__any(cnt != 0u)) {
+                const uint32_t s = wave_sum32(cnt);
+                if (lane == 0)
+                    atomicAdd(&qc[q - C.q_begin], s);
+            }
+        }
+        g = gn;
+    }
+    __syncthreads();
+    if (cur != 0xFFFFFFFFu)
+        flush(cur);
+}
+
+// ----------------------------------------------------- batch bitmap kernel
+
+// Valid-start bits of the 32 starts p0 .. p0 + 31: first <= p <= last.
+__device__ __forceinline__ uint32_t valid_bits(uint64_t p0, uint64_t first, uint64_t last)
+{
+    if (p0 >= first && p0 + 31u <= last)
+        return 0xFFFFFFFFu;
+    const int64_t lo = (int64_t)first - (int64_t)p0, hi = (int64_t)last - (int64_t)p0 + 1;
+    const uint32_t a = (uint32_t)min(max(lo, (int64_t)0), (int64_t)32);
+    const uint32_t b = (uint32_t)min(max(hi, (int64_t)0), (int64_t)32);
+    if (a >= b)
+        return 0u;
+    const uint32_t upto_b = b >= 32u ? 0xFFFFFFFFu : (1u << b) - 1u;
+    const uint32_t below_a = a >= 32u ? 0xFFFFFFFFu : (1u << a) - 1u;
+    return upto_b & ~below_a;
+}
+
+// One compare on the bitmaps for the four 2048-start vectors of the tile:
+// bits of the window at offset j are a funnel shift of two bitmap words.
+__device__ __forceinline__ void bm_step(const uint32_t *bm, uint32_t e, uint32_t lane, uint32_t (&f)[4])
+{
+    const uint32_t base = (e >> 5) + lane, sh = e & 31u;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+        f[v] &= __builtin_amdgcn_alignbit(bm[base + 64u * v + 1u], bm[base + 64u * v], sh);
+}
+
+// Persistent batched count over bitmap tiles.  Work item = (text, tile range,
+// chunk of <= kBmQChunk queries).  Per tile: zero the bitmaps, set one bit per
+// text byte (LDS atomic OR), then wave w runs queries w, w + 16, ... over the
+// 8192 starts of the tile: the first r compares unconditionally, then one zero
+// test (a wave-wide ballot) after each further compare (Algorithm 4).  Each
+// query's count for the item gathers in an LDS counter owned by one wave.
+__global__ __launch_bounds__(kBmWG) void k_batch_bitmap(BmArgs a)
+{
+    extern __shared__ __align__(16) uint32_t bm[];
+    uint8_t *smap = reinterpret_cast<uint8_t *>(bm + a.bm_words);
+    uint32_t *qc = reinterpret_cast<uint32_t *>(smap + 256);
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = wave_id();
+    for (uint64_t it = blockIdx.x; it < a.nitems; it += gridDim.x) {
+        const BmItem I = ldc(&a.items[it]);
+        const uint32_t nq = I.q_end - I.q_begin, wps = I.wps, nw4 = I.nslots * wps / 4u;
+        const uint64_t lo = I.tv.first, hi = I.tv.first + I.tv.n;
+        __syncthreads();  // previous item done with smap and counters
+        if (tid < 64u)
+            reinterpret_cast<uint32_t *>(smap)[tid] = reinterpret_cast<const uint32_t *>(I.smap)[tid];
+        for (uint32_t i = tid; i < nq; i += kBmWG)
+            qc[i] = 0u;
+        for (uint64_t tile = I.tile_begin; tile < I.tile_end; ++tile) {
+            const uint64_t ts = tile * kBmT;
+            for (uint32_t i = tid; i < nw4; i += kBmWG)
+                reinterpret_cast<uint4 *>(bm)[i] = make_uint4(0, 0, 0, 0);
+            __syncthreads();
+            for (uint32_t c = tid; c < 2u * wps; c += kBmWG) {
+                const uint64_t u = ts + 16ull * c;
+                if (u >= I.tv.end16)
+                    continue;
+                const uint4 v = *reinterpret_cast<const uint4 *>(I.tv.base + u);
+                const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+                const bool inner = u >= lo && u + 16u <= hi;
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    if (!inner && (u + i < lo || u + i >= hi))
+                        continue;
+                    const uint32_t slot = smap[(w4[i >> 2] >> (8 * (i & 3))) & 0xFFu];
+                    const uint32_t pos = 16u * c + (uint32_t)i;
+                    if (slot != 0xFFu)
+                        atomicOr(&bm[slot * wps + (pos >> 5)], 1u << (pos & 31u));
+                }
+            }
+            __syncthreads();
+            const uint64_t tile_end = ts + kBmT - 1u;
+            uint32_t q = I.q_begin + wave;
+            BmQuery nxt = q < I.q_end ? ldc(&a.queries[q]) : BmQuery{};
+            for (; q < I.q_end; q += kBmWaves) {
+                const BmQuery Q = nxt;
+                if (q + kBmWaves < I.q_end)
+                    nxt = ldc(&a.queries[q + kBmWaves]);  // next record in flight during this query
+                const uint32_t m = Q.mr & 0xFFFFFFu, r = Q.mr >> 24;
+                const uint64_t last = hi - m;
+                uint32_t f[4];
+                if (ts >= lo && tile_end <= last) {
+                    f[0] = f[1] = f[2] = f[3] = 0xFFFFFFFFu;
+                } else {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        f[v] = valid_bits(ts + 2048u * v + 32u * lane, lo, last);
+                }
+                const uint32_t *st = a.steps + Q.steps_off;
+                bm_step(bm, Q.e0, lane, f);
+                if (r >= 2u)
+                    bm_step(bm, Q.e1, lane, f);
+                for (uint32_t l = 2; l < r; ++l)
+                    bm_step(bm, ldc(&st[l]), lane, f);
+                bool alive = __any((f[0] | f[1] | f[2] | f[3]) != 0u);
+                for (uint32_t l = r; alive && l < m; ++l) {
+                    bm_step(bm, l == 1u ? Q.e1 : ldc(&st[l]), lane, f);
+                    alive = __any((f[0] | f[1] | f[2] | f[3]) != 0u);
+                }
+                if (alive) {
+                    const uint32_t c = wave_sum32(__popc(f[0]) + __popc(f[1]) + __popc(f[2]) + __popc(f[3]));
+                    if (lane == 0)
+                        qc[q - I.q_begin] += c;
+                }
+            }
+            __syncthreads();
+        }
+        for (uint32_t i = tid; i < nq; i += kBmWG) {
+            const uint32_t v = qc[i];
+            if (v)
+                atomicAdd(&a.counts[a.outs[I.q_begin + i]], (unsigned long long)v);
         }
     }
 }
@@ -853,7 +1028,7 @@ hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long
 }
 
 template <int CPL>
-static hipError_t launch_batch_t(const BatchArgs &a, unsigned grid, uint32_t lds, hipStream_t s)
+static hipError_t launch_batch_t(const BatchArgs &a, unsigned grid, hipStream_t s)
 {
     static bool attr_set = false;
     if (!attr_set) {
@@ -863,18 +1038,35 @@ static hipError_t launch_batch_t(const BatchArgs &a, unsigned grid, uint32_t lds
             return e;
         attr_set = true;
     }
+    const uint32_t lds = 2u * (kWG * 16u * CPL + a.halo_max) + kQChunk * (uint32_t)sizeof(uint32_t);
     hipLaunchKernelGGL((k_batch_staged<CPL>), dim3(grid), dim3(kWG), lds, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_batch_staged(const BatchArgs &a, int cpl, unsigned grid, uint32_t lds_bytes, hipStream_t s)
+hipError_t launch_batch_staged(const BatchArgs &a, int cpl, unsigned grid, hipStream_t s)
 {
     switch (cpl) {
-    case 1: return launch_batch_t<1>(a, grid, lds_bytes, s);
-    case 2: return launch_batch_t<2>(a, grid, lds_bytes, s);
-    case 4: return launch_batch_t<4>(a, grid, lds_bytes, s);
+    case 1: return launch_batch_t<1>(a, grid, s);
+    case 2: return launch_batch_t<2>(a, grid, s);
+    case 4: return launch_batch_t<4>(a, grid, s);
     default: return hipErrorInvalidValue;
     }
 }
 
+}  // namespace smk
+
+namespace smk {
+hipError_t launch_batch_bitmap(const BmArgs &a, unsigned grid, uint32_t lds_bytes, hipStream_t s)
+{
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch_bitmap),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBmMaxLds);
+        if (e != hipSuccess)
+            return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_batch_bitmap, dim3(grid), dim3(kBmWG), lds_bytes, s, a);
+    return hipGetLastError();
+}
 }  // namespace smk

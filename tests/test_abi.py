@@ -89,3 +89,14 @@ def test_order_errors():
         sm.order("freq", b"abc")          # needs a histogram
     with pytest.raises(ValueError):
         sm.order("h", b"")
+
+
+def test_freq_order_ties_and_skew():
+    """Equal frequencies of different symbols keep position order (ties across symbols)."""
+    h = np.zeros(256, np.uint64)
+    h[ord("a")] = 5
+    h[ord("b")] = 5
+    h[ord("c")] = 1
+    h[ord("d")] = 9
+    for p in (b"abcdab", b"ddddc", b"babab", b"c", bytes(range(256)), b"dcba" * 50):
+        assert sm.order("freq", p, h).tolist() == oracle.order_freq(p, h).tolist()

@@ -348,3 +348,74 @@ def test_patterns_create_ordered(dev):
         assert out.cpu().tolist() == want, kind
     with pytest.raises(sm.SmError):
         sm.Patterns(pats, "freq")  # needs a histogram
+
+
+@pytest.mark.parametrize("sigma", [2, 4, 20, 95])
+def test_batch_bitmap_mode(dev, sigma):
+    """Texts with histograms and >= 32 queries each run in the bitmap mode."""
+    g = np.random.default_rng(300 + sigma)
+    sizes = [5_000, 8_192, 8_193, 70_001, 1_234_567]
+    texts_h = [rand_text(n, sigma, 50 + i) if sigma != 95 else
+               synth.zipf_text(n, 95, 1.0, config=9, stream=i) for i, n in enumerate(sizes)]
+    texts = [sm.Text(to_dev(t, dev, (7 * i) % 16)) for i, t in enumerate(texts_h)]
+    queries, want = [], []
+    for ti, t in enumerate(texts_h):
+        for k in range(150):
+            m = int(synth.loguniform_ints(1, 4096, 1, g)[0])
+            if k % 3 == 0:
+                p = bytes(g.integers(0, 256, size=min(m, 16), dtype=np.uint8))   # mostly absent symbols
+            elif k % 3 == 1:
+                p = pick_pattern(t, min(m, t.size), g)
+            else:
+                alpha = np.unique(t)
+                p = bytes(alpha[g.integers(0, alpha.size, size=m)])
+            queries.append((ti, p))
+            want.append(oracle.count(p, t))
+    queries.append((0, bytes(texts_h[0]) + b"x"))     # m > n
+    want.append(0)
+    got = sm.count_batch(texts, queries).cpu().numpy().tolist()
+    assert got == want
+    got = sm.count_batch(texts, queries, peel=4).cpu().numpy().tolist()
+    assert got == want
+
+
+def test_batch_bitmap_unary_closed_form(dev):
+    n = 100_003
+    td = sm.Text(torch.full((n,), ord("a"), dtype=torch.uint8, device=dev))
+    ks = list(range(1, 60)) + [100, 1000, 4096]
+    queries = [(0, b"a" * k) for k in ks] + [(0, b"a" * (k - 1) + b"b") for k in ks]
+    got = sm.count_batch([td], queries).cpu().tolist()
+    assert got == [n - k + 1 for k in ks] + [0] * len(ks)
+
+
+def test_packed_texts_batch(dev):
+    g = np.random.default_rng(44)
+    lens = [int(x) for x in synth.loguniform_ints(1, 300_000, 200, g)]
+    texts_h = [rand_text(n, (4, 20, 95)[i % 3], 900 + i) for i, n in enumerate(lens)]
+    offs, pos = [], 0
+    for i, th in enumerate(texts_h):
+        pos += i % 16
+        offs.append(pos)
+        pos += th.size
+    buf = torch.zeros(pos, dtype=torch.uint8, device=dev)
+    for o, th in zip(offs, texts_h):
+        buf[o:o + th.size].copy_(torch.from_numpy(th))
+    hists = np.stack([oracle.hist(th) for th in texts_h])
+    queries, want = [], []
+    for i, th in enumerate(texts_h):
+        for k in range(2):
+            p = pick_pattern(th, int(synth.loguniform_ints(1, 64, 1, g)[0]), g)
+            queries.append((i, p))
+            want.append(oracle.count(p, th))
+    for h in (None, hists):
+        got = sm.count_batch(sm.PackedTexts(buf, offs, lens, h), queries).cpu().tolist()
+        assert got == want
+
+
+def test_text_past_allocation_rejected(dev):
+    td = torch.zeros(1 << 20, dtype=torch.uint8, device=dev)
+    lib = sm._lib.load()
+    p = np.frombuffer(b"ab", dtype=np.uint8)
+    rc = lib.sm_count(p.ctypes.data, 2, td.data_ptr(), 1 << 40, None)
+    assert rc == sm._lib.SM_EINVAL
+    assert "past the end" in lib.sm_last_error().decode()
