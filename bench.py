@@ -330,12 +330,119 @@ def run_batched(args):
     return lines
 
 
+# ----------------------------------------------------------------------- serve
+def run_serve(args):
+    """Open-loop Poisson requests against 8 resident texts, swept offered load."""
+    import torch
+
+    import paper_1612_01506_amd as sm
+    import synth
+    from paper_1612_01506_amd.serve import GpuExecutor, Server
+
+    n = args.n
+    mixes = [("uniform", 2), ("uniform", 4), ("zipf", 4), ("uniform", 20), ("zipf", 20), ("uniform", 95),
+             ("zipf", 95), ("zipf", 95)]
+    t0 = time.time()
+    texts_h = []
+    for i, (kind, sigma) in enumerate(mixes):
+        if kind == "zipf":
+            texts_h.append(synth.zipf_text(n, sigma, 1.0, config=5, stream=i))
+        else:
+            texts_h.append(synth.uniform_text(n, sigma, config=5, stream=i))
+    log(f"[bench] serve: 8 texts of {n} B generated in {time.time() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    ex = GpuExecutor([torch.from_numpy(t).to(dev) for t in texts_h], nstreams=args.streams)
+    alphabets = [bytes(np.unique(t[:1 << 20])) for t in texts_h]
+    g = synth.rng(5, 100)
+
+    def make_requests(count):
+        tid = g.integers(0, len(texts_h), size=count)
+        ms = synth.loguniform_ints(2, 512, count, g)
+        rep = g.random(count) < 0.05
+        out = []
+        for k in range(count):
+            t = texts_h[tid[k]]
+            p = (synth.substring_pattern(t, int(ms[k]), g)[0] if k % 2 else
+                 synth.random_pattern(alphabets[tid[k]], int(ms[k]), g))
+            out.append((int(tid[k]), p, bool(rep[k])))
+        return out
+
+    # warm-up (kernel attributes, allocator, histograms)
+    srv = Server(ex, hbm_budget=args.hbm_budget, on_done=lambda r: setattr(r, "positions", None))
+    for t, p, r in make_requests(256):
+        srv.submit(t, p, r)
+    srv.drain()
+
+    lines = []
+    last = None
+    for rate in args.rates:
+        nreq = int(min(args.max_requests, max(1000, rate * args.seconds)))
+        reqs = make_requests(nreq)
+        arrivals = np.cumsum(g.exponential(1.0 / rate, size=nreq))
+        checks = []
+
+        def consume(r):  # the client takes the result; position buffers are dropped at once
+            if r.report and len(checks) < 20 and 0 < r.count < (1 << 20):
+                checks.append((r.text_id, r.pattern, r.positions[:64].cpu().numpy()))
+            r.positions = None
+
+        srv = Server(ex, hbm_budget=args.hbm_budget, on_done=consume)
+        clock = srv.clock
+        start = clock()
+        k = 0
+        handles = []
+        while k < nreq or not srv.idle():
+            now = clock() - start
+            while k < nreq and arrivals[k] <= now:
+                t, p, r = reqs[k]
+                handles.append(srv.submit(t, p, r, t_submit=start + arrivals[k]))
+                k += 1
+            srv.step()
+        elapsed = clock() - start
+        st = srv.stats()
+        done = st["completed"]
+        rec = {"metric": "served p50/p99 latency", "value": round(st.get("p99_ms", float("nan")), 3),
+               "unit": "ms (p99)", "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": round(elapsed * 1e3, 1),
+               "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+               "data": "synthetic (8 seeded texts; Poisson arrivals; half substring, half random patterns)",
+               "config": {"workload": f"serve: 8 resident texts of {n} B, m log-uniform [2,512], 5% report",
+                          "offered_req_per_s": rate, "achieved_req_per_s": round(done / elapsed, 1),
+                          "requests": nreq, "p50_ms": round(st.get("p50_ms", float("nan")), 3),
+                          "p99_ms": round(st.get("p99_ms", float("nan")), 3),
+                          "count_p50_ms": round(st.get("count_p50_ms", float("nan")), 3),
+                          "count_p99_ms": round(st.get("count_p99_ms", float("nan")), 3),
+                          "report_p50_ms": round(st.get("report_p50_ms", float("nan")), 3),
+                          "report_p99_ms": round(st.get("report_p99_ms", float("nan")), 3),
+                          "mean_batch": st.get("mean_batch"),
+                          "batches": st["batches"], "rejected": st["rejected"],
+                          "peak_reserved_bytes": st["peak_reserved_bytes"], "hbm_budget_bytes": args.hbm_budget,
+                          "streams": args.streams}}
+        log(f"[bench] serve rate {rate}/s: {json.dumps(rec['config'])}")
+        lines.append(rec)
+        last = handles
+        for tid, p, pos in checks:   # the positions reported in the mix are occurrences of p
+            for q in pos:
+                assert bytes(texts_h[tid][int(q):int(q) + len(p)]) == p
+    # each result in the mix equals the same search alone
+    for r in last[:: max(1, len(last) // 200)]:
+        if r.status == "done":
+            assert r.count == sm.count(ex.texts[r.text_id], r.pattern), ("mix != alone", r.rid)
+    return lines
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="zipf", choices=["zipf", "batched"])
+    ap.add_argument("--workload", default="zipf", choices=["zipf", "batched", "serve"])
+    ap.add_argument("--rates", type=float, nargs="+", default=[200, 1000, 5000, 20000, 50000, 100000],
+                    help="serve: offered loads in requests/s")
+    ap.add_argument("--seconds", type=float, default=2.0, help="serve: seconds of arrivals per load point")
+    ap.add_argument("--max-requests", type=int, default=20000, dest="max_requests")
+    ap.add_argument("--streams", type=int, default=2, help="serve: device streams (in-flight batches)")
+    ap.add_argument("--hbm-budget", type=int, default=1 << 30, dest="hbm_budget",
+                    help="serve: bytes of HBM for report position buffers")
     ap.add_argument("--nq", type=int, default=10_000, help="batched: patterns on the one text")
     ap.add_argument("--ntexts", type=int, default=4096, help="batched: texts with one pattern each")
     ap.add_argument("--oracle-samples", type=int, default=4, dest="oracle_samples")
@@ -354,7 +461,7 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
-    res = {"zipf": run_zipf, "batched": run_batched}[args.workload](args)
+    res = {"zipf": run_zipf, "batched": run_batched, "serve": run_serve}[args.workload](args)
     for r in (res if isinstance(res, list) else [res]):
         print(json.dumps(r), flush=True)
 

@@ -258,20 +258,25 @@ def count_batch(texts: Sequence, queries: Iterable, peel=None, tile_kib=None, wg
     nq = len(qs)
     qarr = np.zeros(max(nq, 1), dtype=_QUERY_DT)
     if nq:
-        pats = [_pat(q[1]) for q in qs]
-        lens = np.fromiter((p.size for p in pats), dtype=np.uint64, count=nq)
-        blob = np.concatenate(pats) if int(lens.sum()) else np.zeros(1, dtype=np.uint8)
+        raw = [q[1] for q in qs]
+        if all(type(p) is bytes for p in raw):       # fast path: one join, no per-pattern arrays
+            blob = np.frombuffer(b"".join(raw) or b"\0", dtype=np.uint8)
+            lens = np.fromiter(map(len, raw), dtype=np.uint64, count=nq)
+        else:
+            pats = [_pat(p) for p in raw]
+            lens = np.fromiter((p.size for p in pats), dtype=np.uint64, count=nq)
+            blob = np.concatenate(pats) if int(lens.sum()) else np.zeros(1, dtype=np.uint8)
         keep.append(blob)
         offs = np.zeros(nq, dtype=np.uint64)
         np.cumsum(lens[:-1], out=offs[1:])
-        qarr["text_id"][:nq] = np.fromiter((int(q[0]) for q in qs), dtype=np.int64, count=nq).astype(np.uint32)
+        qarr["text_id"][:nq] = np.fromiter((q[0] for q in qs), dtype=np.int64, count=nq).astype(np.uint32)
         qarr["p"][:nq] = np.where(lens > 0, np.uint64(blob.ctypes.data) + offs, 0)
         qarr["m"][:nq] = lens
         for i, q in enumerate(qs):
             if len(q) > 2 and q[2] is not None:
                 tid = int(q[0])
                 tx = texts[tid] if 0 <= tid < len(texts) else None
-                o = _resolve_order(q[2], pats[i], tx)
+                o = _resolve_order(q[2], _pat(raw[i]), tx)
                 if o is not None:
                     keep.append(o)
                     qarr["order"][i] = o.ctypes.data

@@ -419,3 +419,32 @@ def test_text_past_allocation_rejected(dev):
     rc = lib.sm_count(p.ctypes.data, 2, td.data_ptr(), 1 << 40, None)
     assert rc == sm._lib.SM_EINVAL
     assert "past the end" in lib.sm_last_error().decode()
+
+
+def test_serving_alone_equals_mix(dev):
+    from paper_1612_01506_amd.serve import GpuExecutor, Server
+    texts_h = [synth.zipf_text(3_000_000, 95, 1.0, config=5, stream=1),
+               rand_text(2_000_003, 4, 77), synth.zipf_text(1_500_000, 20, 1.0, config=5, stream=2)]
+    ex = GpuExecutor([to_dev(t, dev, 3 * i) for i, t in enumerate(texts_h)], nstreams=2)
+    srv = Server(ex, max_batch=96, hbm_budget=1 << 24)
+    g = np.random.default_rng(12)
+    reqs = []
+    for k in range(400):
+        ti = int(g.integers(0, 3))
+        m = int(synth.loguniform_ints(2, 512, 1, g)[0])
+        p = (synth.substring_pattern(texts_h[ti], m, g)[0] if k % 2 else
+             synth.random_pattern(bytes(np.unique(texts_h[ti])), m, g))
+        reqs.append(srv.submit(ti, p, report=(k % 20 == 0)))
+        if g.random() < 0.3:
+            srv.step()
+    srv.drain()
+    assert srv.batches > 2
+    for k, r in enumerate(reqs):
+        assert r.status == "done", (r.status, r.error)
+        alone = sm.count(ex.texts[r.text_id], r.pattern)
+        assert r.count == alone
+        if k % 10 == 0 or r.report:
+            assert r.count == oracle.count(r.pattern, texts_h[r.text_id])
+        if r.report:
+            pos = r.positions.cpu().numpy() if hasattr(r.positions, "cpu") else r.positions
+            assert np.array_equal(pos.astype(np.uint64), oracle.report(r.pattern, texts_h[r.text_id]))

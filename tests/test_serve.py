@@ -1,0 +1,141 @@
+"""Serving scheduler on the CPU: a test-only executor answers with the oracle.
+
+Checks continuous batching (requests arriving while batches are in flight go
+into later batches, never more than max_inflight at once), results equal to
+independent searches, memory-based admission of reporting requests, and that
+failures stay confined to the requests they hit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_1612_01506_amd.serve import Server
+
+
+class FakeExecutor:
+    """Completes a launch after `delay` polls; counts and positions come from the oracle."""
+
+    def __init__(self, texts, nslots=2, delay=3, fail_batches=()):
+        self.texts = texts
+        self.nslots = nslots
+        self.delay = delay
+        self.fail_batches = set(fail_batches)
+        self.launches = 0
+        self.active = 0
+        self.max_active = 0
+
+    def _start(self):
+        self.launches += 1
+        self.active += 1
+        self.max_active = max(self.max_active, self.active)
+
+    def launch_counts(self, slot, reqs):
+        if self.launches in self.fail_batches:
+            self.launches += 1
+            raise RuntimeError("injected launch failure")
+        self._start()
+        counts = np.array([oracle.count(r.pattern, self.texts[r.text_id]) for r in reqs], dtype=np.int64)
+        return {"left": self.delay, "counts": counts}
+
+    def launch_report(self, slot, req, cap):
+        self._start()
+        pos = oracle.report(req.pattern, self.texts[req.text_id])
+        return {"left": self.delay, "total": int(pos.size), "pos": pos[:cap]}
+
+    def ready(self, h):
+        if h["left"] > 0:
+            h["left"] -= 1
+            return False
+        if not h.get("seen"):
+            h["seen"] = True
+            self.active -= 1
+        return True
+
+    def counts(self, h):
+        return h["counts"]
+
+    def report(self, h):
+        return h["total"], h["pos"]
+
+
+def make_texts():
+    return [synth.zipf_text(20_000, 95, 1.0, config=5, stream=i) for i in range(3)] + \
+           [synth.uniform_text(20_000, 4, config=5, stream=9)]
+
+
+def test_results_equal_independent_searches():
+    texts = make_texts()
+    ex = FakeExecutor(texts, nslots=2, delay=2)
+    srv = Server(ex, max_batch=7)
+    g = np.random.default_rng(1)
+    reqs = []
+    for k in range(200):
+        ti = int(g.integers(0, len(texts)))
+        m = int(synth.loguniform_ints(1, 40, 1, g)[0])
+        p = synth.substring_pattern(texts[ti], m, g)[0] if k % 2 else synth.random_pattern(b"ACGT", m, g)
+        reqs.append(srv.submit(ti, p, report=(k % 10 == 0)))
+        if k % 3 == 0:
+            srv.step()
+    srv.drain()
+    assert all(r.status == "done" for r in reqs)
+    for r in reqs:
+        assert r.count == oracle.count(r.pattern, texts[r.text_id])
+        if r.report:
+            assert np.array_equal(np.asarray(r.positions, dtype=np.uint64), oracle.report(r.pattern, texts[r.text_id]))
+    assert ex.max_active <= 2
+    st = srv.stats()
+    assert st["completed"] == 200 and st["rejected"] == 0
+    assert st["batches"] > 3            # arrivals during flight were batched later
+    assert "p50_ms" in st and "p99_ms" in st
+
+
+def test_continuous_batching_admits_while_busy():
+    texts = make_texts()
+    ex = FakeExecutor(texts, nslots=1, delay=5)
+    srv = Server(ex)
+    first = [srv.submit(0, b"ab") for _ in range(3)]
+    srv.step()                          # batch 1 in flight
+    late = [srv.submit(1, b"a") for _ in range(4)]
+    srv.step()                          # no free slot: late requests wait
+    assert all(r.status == "queued" for r in late)
+    srv.drain()
+    assert srv.batch_sizes == [3, 4]
+    assert all(r.status == "done" for r in first + late)
+
+
+def test_report_memory_admission_and_rejection():
+    t = np.frombuffer(b"a" * 1000, dtype=np.uint8)
+    ex = FakeExecutor([t], nslots=2, delay=1)
+    # budget fits one report of "a" (1000 positions = 8000 B) but not two at once
+    srv = Server(ex, hbm_budget=10_000)
+    r1 = srv.submit(0, b"a", report=True)
+    r2 = srv.submit(0, b"a", report=True)
+    r3 = srv.submit(0, b"aa", report=True)  # 999 positions
+    big = Server(FakeExecutor([t], nslots=1, delay=0), hbm_budget=1000)
+    r4 = big.submit(0, b"a", report=True)   # 8000 B > budget: rejected
+    srv.drain()
+    big.drain()
+    for r in (r1, r2, r3):
+        assert r.status == "done"
+        assert np.array_equal(np.asarray(r.positions, dtype=np.uint64), oracle.report(r.pattern, t))
+    assert srv.peak_reserved <= 10_000
+    assert r4.status == "rejected" and "budget" in r4.error
+
+
+def test_failures_stay_confined():
+    texts = make_texts()
+    ex = FakeExecutor(texts, nslots=1, delay=0, fail_batches={0})
+    srv = Server(ex)
+    bad = [srv.submit(0, b"x") for _ in range(2)]
+    srv.step()                          # first launch fails
+    good = [srv.submit(1, b"y") for _ in range(2)]
+    empty = srv.submit(0, b"")
+    srv.drain()
+    assert all(r.status == "error" and "injected" in r.error for r in bad)
+    assert all(r.status == "done" for r in good)
+    assert empty.status == "error"
+    with pytest.raises(TimeoutError):
+        stuck = Server(FakeExecutor(texts, nslots=1, delay=10**9))
+        stuck.submit(0, b"a")
+        stuck.drain(timeout=0.05)
