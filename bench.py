@@ -330,6 +330,172 @@ def run_batched(args):
     return lines
 
 
+# ---------------------------------------------------------------------- single
+def run_single(args):
+    """8 MiB ACGT text, one m=16 substring: plain synchronous search, asynchronous loop and graph
+    replay, in left-to-right and frequency order.  Small enough to stay cache resident, so this is a
+    latency figure, not an HBM figure."""
+    import torch
+
+    import oracle
+    import paper_1612_01506_amd as sm
+    import synth
+
+    n = args.n if args.n != (1 << 30) else (8 << 20)
+    t_host, p = synth.single_count_workload(n=n, m=16)
+    dev = torch.device("cuda:0")
+    t_dev = torch.from_numpy(t_host).to(dev)
+    text = sm.Text(t_dev)
+    want = oracle.count(p, t_host)
+    lines = []
+    reps = args.reps
+    for order in ("ltr", "freq"):
+        # plain form: one synchronous call per search
+        for _ in range(10):
+            assert sm.count(text, p, order=order) == want
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            c = sm.count(text, p, order=order)
+        sync_us = (time.perf_counter() - t0) / reps * 1e6
+        assert c == want
+        # asynchronous loop over a prepared pattern
+        ps = sm.Patterns([p], [sm.order(order, p, text.hist) if order == "freq" else None])
+        out = torch.zeros(reps, dtype=torch.int64, device=dev)
+        for i in range(min(reps, 10)):
+            ps.count_async(0, t_dev, out[i:i + 1])
+        out.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(reps):
+            ps.count_async(0, t_dev, out[i:i + 1])
+        torch.cuda.synchronize()
+        async_us = (time.perf_counter() - t0) / reps * 1e6
+        assert bool((out == want).all())
+        # graph replay: `per_graph` searches captured once, replayed; every replay checked
+        per_graph = 100
+        gout = torch.zeros(per_graph, dtype=torch.int64, device=dev)
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for i in range(per_graph):
+                ps.count_async(0, t_dev, gout[i:i + 1])     # warm-up outside capture
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            gout.zero_()
+            for i in range(per_graph):
+                ps.count_async(0, t_dev, gout[i:i + 1])
+        nrep = max(1, reps // per_graph)
+        for k in range(3):          # replays with eager work in between
+            g.replay()
+            torch.cuda.synchronize()
+            assert bool((gout == want).all()), "graph replay differs from eager"
+            assert sm.count(text, p, order=order) == want
+        t0 = time.perf_counter()
+        for _ in range(nrep):
+            g.replay()
+        torch.cuda.synchronize()
+        graph_us = (time.perf_counter() - t0) / (nrep * per_graph) * 1e6
+        assert bool((gout == want).all())
+        ps.close()
+        lines.append({
+            "metric": "single-search latency", "value": round(graph_us, 2), "unit": "us/search (graph replay)",
+            "n_gpus": 1, "steps": reps, "warmup": 10, "ms_per_step": round(graph_us / 1e3, 5),
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+            "data": "synthetic (seeded uniform ACGT text, substring pattern)",
+            "config": {"workload": f"single: {n}-byte uniform ACGT text, m=16 substring, order={order}",
+                       "count": want, "sync_call_us": round(sync_us, 2), "async_loop_us": round(async_us, 2),
+                       "graph_replay_us": round(graph_us, 2),
+                       "text_GBps_graph": round(n / (graph_us * 1e-6) / 1e9, 1)},
+        })
+    return lines
+
+
+# ----------------------------------------------------------------------- small
+def run_small(args):
+    """Small alphabets (sigma 2 and 4, 1 GiB) with m in {8, 64, 512, 4096}, and periodic a^n texts."""
+    import torch
+
+    import oracle
+    import paper_1612_01506_amd as sm
+    import synth
+
+    dev = torch.device("cuda:0")
+    lines = []
+    n = args.n
+    for sigma in (2, 4):
+        t_host, pats = synth.small_alphabet_workload(n=n, sigma=sigma)
+        t_dev = torch.from_numpy(t_host).to(dev)
+        text = sm.Text(t_dev)
+        res = {}
+        for peel in (2, 5):
+            ps = sm.Patterns(pats, "freq", text.hist)
+            out = torch.zeros(len(pats), dtype=torch.int64, device=dev)
+            for i in range(len(pats)):
+                ps.count_async(i, t_dev, out[i:i + 1], peel=peel)
+            out.zero_()
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in pats]
+            for i in range(len(pats)):
+                ev[i][0].record()
+                ps.count_async(i, t_dev, out[i:i + 1], peel=peel)
+                ev[i][1].record()
+            torch.cuda.synchronize()
+            counts = out.cpu().numpy()
+            per_m = {}
+            for i, p in enumerate(pats):
+                per_m.setdefault(len(p), []).append(ev[i][0].elapsed_time(ev[i][1]))
+            res[f"peel{peel}_GBps_by_m"] = {m: round(n / (np.mean(v) * 1e-3) / 1e9, 1) for m, v in per_m.items()}
+            ps.close()
+        seen = set()
+        for i, p in enumerate(pats):        # oracle on one pattern per length
+            if len(p) not in seen:
+                seen.add(len(p))
+                assert oracle.count(p, t_host) == counts[i], ("oracle", sigma, len(p))
+        res["counts_first_per_m"] = {len(p): int(counts[i]) for i, p in enumerate(pats) if i % 11 == 0}
+        lines.append({
+            "metric": "text GB/s per search (% HBM peak)", "unit": "GB/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+            "value": round(float(np.mean([v for v in res["peel2_GBps_by_m"].values()])), 1),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+            "data": "synthetic (seeded uniform text; 10 substrings + 1 random pattern per m)",
+            "ms_per_step": None,
+            "config": dict({"workload": f"small_alphabet: {n}-byte uniform sigma={sigma} text, "
+                                        "m in {8,64,512,4096}, frequency order"}, **res),
+        })
+        del t_dev, text
+        torch.cuda.empty_cache()
+    # periodic a^n with a^(k-1)b and a^k
+    np_ = min(n, 256 << 20)
+    t_dev = torch.full((np_,), ord("a"), dtype=torch.uint8, device=dev)
+    text = sm.Text(t_dev)
+    per = {}
+    for k in (16, 256):
+        for name, p, want in ((f"a^{k}", b"a" * k, np_ - k + 1), (f"a^{k - 1}b", b"a" * (k - 1) + b"b", 0)):
+            for order in ("ltr", "freq"):
+                ps = sm.Patterns([p], "freq" if order == "freq" else "ltr", text.hist)
+                out = torch.zeros(1, dtype=torch.int64, device=dev)
+                ps.count_async(0, t_dev, out)
+                out.zero_()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                ps.count_async(0, t_dev, out)
+                e1.record()
+                torch.cuda.synchronize()
+                assert int(out.item()) == want, (name, order)
+                per[f"{name}/{order}"] = {"us": round(e0.elapsed_time(e1) * 1e3, 1),
+                                          "GBps": round(np_ / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)}
+                ps.close()
+    lines.append({
+        "metric": "text GB/s per search (% HBM peak)", "unit": "GB/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "value": per["a^256/freq"]["GBps"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic (a^n)", "ms_per_step": None,
+        "config": {"workload": f"periodic: a^n, n={np_}, patterns a^k and a^(k-1)b, k in {{16,256}}; "
+                               "counts equal the closed forms n-k+1 and 0", "results": per},
+    })
+    return lines
+
+
 # ----------------------------------------------------------------------- serve
 def run_serve(args):
     """Open-loop Poisson requests against 8 resident texts, swept offered load."""
@@ -346,9 +512,9 @@ def run_serve(args):
     texts_h = []
     for i, (kind, sigma) in enumerate(mixes):
         if kind == "zipf":
-            texts_h.append(synth.zipf_text(n, sigma, 1.0, config=5, stream=i))
+            texts_h.append(synth.zipf_text(n, sigma, 1.0, family=5, stream=i))
         else:
-            texts_h.append(synth.uniform_text(n, sigma, config=5, stream=i))
+            texts_h.append(synth.uniform_text(n, sigma, family=5, stream=i))
     log(f"[bench] serve: 8 texts of {n} B generated in {time.time() - t0:.1f}s")
     dev = torch.device("cuda:0")
     ex = GpuExecutor([torch.from_numpy(t).to(dev) for t in texts_h], nstreams=args.streams)
@@ -435,7 +601,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="zipf", choices=["zipf", "batched", "serve"])
+    ap.add_argument("--workload", default="zipf", choices=["zipf", "batched", "serve", "single", "small"])
+    ap.add_argument("--reps", type=int, default=1000, help="single: searches timed per form")
     ap.add_argument("--rates", type=float, nargs="+", default=[200, 1000, 5000, 20000, 50000, 100000],
                     help="serve: offered loads in requests/s")
     ap.add_argument("--seconds", type=float, default=2.0, help="serve: seconds of arrivals per load point")
@@ -461,7 +628,8 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
-    res = {"zipf": run_zipf, "batched": run_batched, "serve": run_serve}[args.workload](args)
+    res = {"zipf": run_zipf, "batched": run_batched, "serve": run_serve, "single": run_single,
+           "small": run_small}[args.workload](args)
     for r in (res if isinstance(res, list) else [res]):
         print(json.dumps(r), flush=True)
 

@@ -67,8 +67,15 @@ def _stream(stream) -> int | None:
     return int(stream)
 
 
-def _params(peel=None, tile_kib=None, wgs_per_cu=None):
+def _params(peel=None, tile_kib=None, wgs_per_cu=None, text=None, m=None):
+    """sm_params for a call; with none given and a Text whose histogram is known, the autotuner's
+    table (if one exists for this device) supplies them."""
     if peel is None and tile_kib is None and wgs_per_cu is None:
+        if isinstance(text, Text) and text._hist is not None and m:
+            from . import autotune
+            tp = autotune.params_for(text._hist, int(m), text.n)
+            if tp:
+                return ctypes.byref(sm_params(tp["peel"], tp["tile_kib"], tp["wgs_per_cu"], 0))
         return None
     return ctypes.byref(sm_params(int(peel or 0), int(tile_kib or 0), int(wgs_per_cu or 0), 0))
 
@@ -147,7 +154,7 @@ def count(t, p, order=None, peel=None, tile_kib=None, wgs_per_cu=None, stream=No
     ptr, n = _dev_text(t)
     o = _resolve_order(order, a, t)
     return check(load().sm_count_ex(_ptr(a), a.size, ptr, n, _ptr(o),
-                                    _params(peel, tile_kib, wgs_per_cu), _stream(stream)))
+                                    _params(peel, tile_kib, wgs_per_cu, t, a.size), _stream(stream)))
 
 
 def count_async(t, p, out: torch.Tensor, order=None, peel=None, tile_kib=None, wgs_per_cu=None,
@@ -158,7 +165,7 @@ def count_async(t, p, out: torch.Tensor, order=None, peel=None, tile_kib=None, w
     if out.dtype != torch.int64 or not out.is_cuda:
         raise TypeError("out must be a CUDA int64 tensor")
     o = _resolve_order(order, a, t)
-    check(load().sm_count_async(_ptr(a), a.size, ptr, n, _ptr(o), _params(peel, tile_kib, wgs_per_cu),
+    check(load().sm_count_async(_ptr(a), a.size, ptr, n, _ptr(o), _params(peel, tile_kib, wgs_per_cu, t, a.size),
                                 out.data_ptr(), _stream(stream)))
 
 
@@ -173,7 +180,7 @@ def report(t, p, order=None, cap: int | None = None, peel=None, tile_kib=None, w
     ptr, n = _dev_text(t)
     o = _resolve_order(order, a, t)
     dev = t.t.device if isinstance(t, Text) else t.device
-    params = _params(peel, tile_kib, wgs_per_cu)
+    params = _params(peel, tile_kib, wgs_per_cu, t, a.size)
     if cap is None:
         cap = check(load().sm_count_ex(_ptr(a), a.size, ptr, n, _ptr(o), params, _stream(stream)))
     pos = torch.empty(max(int(cap), 1), dtype=torch.int64, device=dev)
@@ -190,7 +197,7 @@ def report_async(t, p, out: torch.Tensor, total: torch.Tensor, order=None, peel=
     a = _pat(p)
     ptr, n = _dev_text(t)
     o = _resolve_order(order, a, t)
-    check(load().sm_report_async(_ptr(a), a.size, ptr, n, _ptr(o), _params(peel, tile_kib, wgs_per_cu),
+    check(load().sm_report_async(_ptr(a), a.size, ptr, n, _ptr(o), _params(peel, tile_kib, wgs_per_cu, t, a.size),
                                  out.data_ptr(), out.numel(), total.data_ptr(), _stream(stream)))
 
 
@@ -337,7 +344,7 @@ class Patterns:
                     stream=None) -> None:
         """ADD the count of pattern i in t to out[0] (device int64), asynchronously."""
         ptr, n = _dev_text(t)
-        check(load().sm_patterns_count(self._h, i, ptr, n, _params(peel, tile_kib, wgs_per_cu),
+        check(load().sm_patterns_count(self._h, i, ptr, n, _params(peel, tile_kib, wgs_per_cu, t, self.m[i]),
                                        out.data_ptr(), _stream(stream)))
 
     def count(self, i: int, t, **kw) -> int:
@@ -350,12 +357,12 @@ class Patterns:
                stream=None) -> int:
         """Write up to out.numel() increasing positions of pattern i into out; return the full count."""
         ptr, n = _dev_text(t)
-        return check(load().sm_patterns_report(self._h, i, ptr, n, _params(peel, tile_kib, wgs_per_cu),
+        return check(load().sm_patterns_report(self._h, i, ptr, n, _params(peel, tile_kib, wgs_per_cu, t, self.m[i]),
                                                out.data_ptr(), out.numel(), _stream(stream)))
 
     def report_async(self, i: int, t, out: torch.Tensor, total: torch.Tensor, peel=None, tile_kib=None,
                      wgs_per_cu=None, stream=None) -> None:
         """Positions of pattern i into out (up to out.numel()), full count into total[0]; no wait."""
         ptr, n = _dev_text(t)
-        check(load().sm_patterns_report_async(self._h, i, ptr, n, _params(peel, tile_kib, wgs_per_cu),
+        check(load().sm_patterns_report_async(self._h, i, ptr, n, _params(peel, tile_kib, wgs_per_cu, t, self.m[i]),
                                               out.data_ptr(), out.numel(), total.data_ptr(), _stream(stream)))

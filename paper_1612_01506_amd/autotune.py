@@ -1,0 +1,158 @@
+"""Launch-parameter autotuner for single searches.
+
+For every cell (alphabet class, pattern-length bucket, text-size bucket) the
+tuner times count searches of substring patterns on a seeded synthetic text
+over a grid of tile size, workgroups per compute unit and peel factor r, and
+keeps the fastest setting.  None of these parameters changes a result.  The
+paper's observations seed the grid: with frequency order r = 2 is best for
+large alphabets, r = 3 for protein and r = 5 for DNA (Section 3).
+
+The table is a JSON file keyed by GPU architecture and HIP version
+(`tuning/<arch>.json` next to this module).  The binding consults it for
+searches on texts whose histogram it knows (`Text` objects) when the caller
+gives no explicit parameters; with no table for the current device it passes
+nothing and the library's defaults apply.
+
+    python -m paper_1612_01506_amd.autotune --out tuned.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import time
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+TABLE_DIR = os.path.join(_HERE, "tuning")
+
+CLASSES = (2, 4, 20, 95)            # alphabet classes (symbols present)
+M_BUCKETS = (8, 64, 512, 4096)       # upper bounds of pattern-length buckets
+N_BUCKETS = (16 << 20, 1 << 62)      # upper bounds of text-size buckets
+GRID = [(tk, w, r) for tk in (4, 8, 16) for w in (4, 6, 8) for r in (1, 2, 3, 5)]
+
+_table = None
+_table_key = None
+
+
+def alphabet_class(hist) -> int:
+    nsym = int(np.count_nonzero(np.asarray(hist)))
+    return 2 if nsym <= 2 else 4 if nsym <= 4 else 20 if nsym <= 32 else 95
+
+
+def _bucket(v: int, bounds) -> int:
+    for i, b in enumerate(bounds):
+        if v <= b:
+            return i
+    return len(bounds) - 1
+
+
+def _device_key():
+    import torch
+
+    props = torch.cuda.get_device_properties(0)
+    arch = props.gcnArchName.split(":")[0]
+    return arch, torch.version.hip or "unknown"
+
+
+def load_table(path: str | None = None):
+    global _table, _table_key
+    if path is None:
+        try:
+            arch, hip = _device_key()
+        except Exception:  # noqa: BLE001 - no device: no table
+            return None
+        path = os.path.join(TABLE_DIR, f"{arch}.json")
+        key = (arch, hip)
+    else:
+        key = ("file", path)
+    if _table_key == key:
+        return _table
+    _table_key = key
+    _table = None
+    if os.path.exists(path):
+        with open(path) as f:
+            _table = json.load(f)
+    return _table
+
+
+def params_for(hist, m: int, n: int) -> dict | None:
+    """Tuned launch parameters for a pattern of length m in a text of n bytes with this histogram."""
+    tab = load_table()
+    if not tab:
+        return None
+    key = f"{alphabet_class(hist)}/{_bucket(m, M_BUCKETS)}/{_bucket(n, N_BUCKETS)}"
+    e = tab["cells"].get(key)
+    if e is None:
+        return None
+    return {"tile_kib": e["tile_kib"], "wgs_per_cu": e["wgs_per_cu"], "peel": e["peel"]}
+
+
+def tune(sizes=(8 << 20, 256 << 20), patterns_per_cell: int = 4, reps: int = 3, log=print) -> dict:
+    import torch
+
+    from . import Patterns, Text
+    import synth
+
+    dev = torch.device("cuda:0")
+    arch, hip = _device_key()
+    cells = {}
+    timings = {}
+    for ni, n in enumerate(sizes):
+        for sigma in CLASSES:
+            if sigma == 95:
+                t_host = synth.zipf_text(n, 95, 1.0, family=7, stream=ni)
+            else:
+                t_host = synth.uniform_text(n, sigma, family=7, stream=10 * ni + sigma)
+            t = Text(torch.from_numpy(t_host).to(dev))
+            g = synth.rng(7, 100 + sigma + ni)
+            lo = 1
+            for mi, mhi in enumerate(M_BUCKETS):
+                ms = [int(x) for x in np.linspace(lo, mhi, patterns_per_cell).round()]
+                lo = mhi + 1
+                pats = [synth.substring_pattern(t_host, min(m, n), g)[0] for m in ms]
+                ps = Patterns(pats, "freq", t.hist)
+                out = torch.zeros(1, dtype=torch.int64, device=dev)
+                best = None
+                for tk, w, r in GRID:
+                    for i in range(len(pats)):
+                        ps.count_async(i, t.t, out, peel=r, tile_kib=tk, wgs_per_cu=w)
+                    torch.cuda.synchronize()
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    for _ in range(reps):
+                        for i in range(len(pats)):
+                            ps.count_async(i, t.t, out, peel=r, tile_kib=tk, wgs_per_cu=w)
+                    e1.record()
+                    torch.cuda.synchronize()
+                    us = e0.elapsed_time(e1) * 1e3 / (reps * len(pats))
+                    timings[f"{sigma}/{mi}/{ni}/{tk}/{w}/{r}"] = round(us, 2)
+                    if best is None or us < best[0]:
+                        best = (us, tk, w, r)
+                ps.close()
+                key = f"{sigma}/{mi}/{ni}"
+                cells[key] = {"tile_kib": best[1], "wgs_per_cu": best[2], "peel": best[3],
+                              "us": round(best[0], 2), "text_bytes": n, "m": ms}
+                log(f"[autotune] class {sigma} m<={mhi} n={n}: {cells[key]}")
+            del t
+            torch.cuda.empty_cache()
+    return {"arch": arch, "hip": hip, "created": time.strftime("%Y-%m-%d"),
+            "grid": {"tile_kib": [4, 8, 16], "wgs_per_cu": [4, 6, 8], "peel": [1, 2, 3, 5]},
+            "classes": list(CLASSES), "m_buckets": list(M_BUCKETS), "n_buckets": list(N_BUCKETS),
+            "cells": cells, "timings_us": timings}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--reps", type=int, default=3)
+    args = ap.parse_args()
+    tab = tune(reps=args.reps)
+    with open(args.out, "w") as f:
+        json.dump(tab, f, indent=1)
+    print(f"wrote {args.out}: {len(tab['cells'])} cells")
+
+
+if __name__ == "__main__":
+    main()

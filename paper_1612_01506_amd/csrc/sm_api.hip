@@ -394,7 +394,11 @@ int launch_count(Dev &d, const TextView &tv, uint64_t m, const uint64_t *steps_d
         const uint64_t T = 4096ull * cpl;
         a.halo = (uint32_t)halo;
         a.ntiles = ceil_div(a.last + 1, T);
-        a.chunk_log2 = (uint32_t)tu.chunk_log2;
+        // small texts: deal single tiles so that every workgroup gets work
+        uint32_t ck = (uint32_t)tu.chunk_log2;
+        while (ck > 0 && ceil_div(a.ntiles, 1ull << ck) < target)
+            --ck;
+        a.chunk_log2 = ck;
         const uint64_t nchunks = ceil_div(a.ntiles, 1ull << a.chunk_log2);
         const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(nchunks, target));
         HIP_TRY(launch_count_staged(a, cpl, tu.r, (unsigned)grid, s));

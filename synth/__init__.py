@@ -20,7 +20,8 @@ sources with matching alphabet sizes:
 Bytes are produced by a counter-based splitmix64 hash (Steele, Lea and Flood,
 OOPSLA 2014): byte i depends only on (key, i), so a GiB-scale text can be made
 in parallel by the C helper ``synth.c`` and any slice of it recomputed here in
-numpy.  Keys come from ``numpy.random.SeedSequence([SEED, config, stream])``.
+numpy.  Keys come from ``numpy.random.SeedSequence([SEED, family, stream])``, where
+a family number separates the workloads and a stream number the texts and draws within one.
 """
 from __future__ import annotations
 
@@ -48,15 +49,15 @@ _M2 = np.uint64(0x94D049BB133111EB)
 
 
 # ----------------------------------------------------------------------------- seeds
-def stream_key(config: int, stream: int) -> int:
-    """64-bit generator key for (config, stream) under the master seed."""
-    ss = np.random.SeedSequence([SEED, int(config), int(stream)])
+def stream_key(family: int, stream: int) -> int:
+    """64-bit generator key for (family, stream) under the master seed."""
+    ss = np.random.SeedSequence([SEED, int(family), int(stream)])
     return int(ss.generate_state(1, dtype=np.uint64)[0])
 
 
-def rng(config: int, stream: int) -> np.random.Generator:
+def rng(family: int, stream: int) -> np.random.Generator:
     """numpy Generator for the small draws (offsets, lengths, patterns)."""
-    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([SEED, int(config), int(stream)])))
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([SEED, int(family), int(stream)])))
 
 
 # ------------------------------------------------------------------------ symbol laws
@@ -79,9 +80,9 @@ def uniform_thresholds(sigma: int) -> np.ndarray:
     return ((k << np.uint64(32)) // np.uint64(sigma)).astype(np.uint32)
 
 
-def rank_permutation(alphabet: bytes, config: int, stream: int) -> bytes:
+def rank_permutation(alphabet: bytes, family: int, stream: int) -> bytes:
     """Seeded rank -> symbol map (rank 0 is the most probable symbol)."""
-    perm = rng(config, 10_000 + stream).permutation(len(alphabet))
+    perm = rng(family, 10_000 + stream).permutation(len(alphabet))
     return bytes(alphabet[i] for i in perm)
 
 
@@ -131,14 +132,14 @@ def iid_text(n: int, symbols: bytes, thr: np.ndarray, key: int) -> np.ndarray:
     return out
 
 
-def zipf_text(n: int, sigma: int = 95, s: float = 1.0, config: int = 2, stream: int = 0) -> np.ndarray:
+def zipf_text(n: int, sigma: int = 95, s: float = 1.0, family: int = 2, stream: int = 0) -> np.ndarray:
     """Order-0 Zipf(s) text over ALPHABETS[sigma] under a seeded rank permutation."""
-    syms = rank_permutation(ALPHABETS[sigma], config, stream)
-    return iid_text(n, syms, zipf_thresholds(sigma, s), stream_key(config, stream))
+    syms = rank_permutation(ALPHABETS[sigma], family, stream)
+    return iid_text(n, syms, zipf_thresholds(sigma, s), stream_key(family, stream))
 
 
-def uniform_text(n: int, sigma: int = 4, config: int = 1, stream: int = 0) -> np.ndarray:
-    return iid_text(n, ALPHABETS[sigma], uniform_thresholds(sigma), stream_key(config, stream))
+def uniform_text(n: int, sigma: int = 4, family: int = 1, stream: int = 0) -> np.ndarray:
+    return iid_text(n, ALPHABETS[sigma], uniform_thresholds(sigma), stream_key(family, stream))
 
 
 def periodic_text(n: int, unit: bytes) -> np.ndarray:
@@ -176,7 +177,7 @@ class Query:
 
 def single_count_workload(n: int = 8 << 20, m: int = 16):
     """Single count search: uniform ACGT text, one substring pattern at a seeded offset."""
-    t = uniform_text(n, 4, config=1, stream=0)
+    t = uniform_text(n, 4, family=1, stream=0)
     p, _ = substring_pattern(t, m, rng(1, 1))
     return t, p
 
@@ -187,7 +188,7 @@ def zipf_workload(n: int = 1 << 30, per_m: int = 100,
 
     Returns (text, list of (pattern, report_flag)).  Report mode is requested for m >= report_min_m.
     """
-    t = zipf_text(n, 95, 1.0, config=2, stream=0)
+    t = zipf_text(n, 95, 1.0, family=2, stream=0)
     g = rng(2, 1)
     pats = []
     for m in ms:
@@ -199,7 +200,7 @@ def zipf_workload(n: int = 1 << 30, per_m: int = 100,
 
 
 def small_alphabet_workload(n: int = 1 << 30, sigma: int = 2, ms=(8, 64, 512, 4096), per_m: int = 10):
-    t = uniform_text(n, sigma, config=3, stream=sigma)
+    t = uniform_text(n, sigma, family=3, stream=sigma)
     g = rng(3, 100 + sigma)
     pats = []
     for m in ms:
@@ -213,7 +214,7 @@ def small_alphabet_workload(n: int = 1 << 30, sigma: int = 2, ms=(8, 64, 512, 40
 
 def batched_one_text_workload(n: int = 2 << 30, nq: int = 10_000, lo: int = 2, hi: int = 1024):
     """One Zipf sigma=95 text, nq patterns with m log-uniform in [lo, hi]; half substrings, half random."""
-    t = zipf_text(n, 95, 1.0, config=4, stream=0)
+    t = zipf_text(n, 95, 1.0, family=4, stream=0)
     g = rng(4, 1)
     ms = loguniform_ints(lo, hi, nq, g)
     pats = []
@@ -236,9 +237,9 @@ def batched_many_texts_workload(ntexts: int = 4096, lo: int = 4 << 10, hi: int =
     for i in range(ntexts):
         sigma = (4, 20, 95)[i % 3]
         if sigma == 95:
-            t = zipf_text(int(lens[i]), 95, 1.0, config=4, stream=100 + i)
+            t = zipf_text(int(lens[i]), 95, 1.0, family=4, stream=100 + i)
         else:
-            t = uniform_text(int(lens[i]), sigma, config=4, stream=100 + i)
+            t = uniform_text(int(lens[i]), sigma, family=4, stream=100 + i)
         m = int(min(ms[i], len(t)))
         texts.append(t)
         pats.append(substring_pattern(t, m, g)[0])

@@ -356,7 +356,7 @@ def test_batch_bitmap_mode(dev, sigma):
     g = np.random.default_rng(300 + sigma)
     sizes = [5_000, 8_192, 8_193, 70_001, 1_234_567]
     texts_h = [rand_text(n, sigma, 50 + i) if sigma != 95 else
-               synth.zipf_text(n, 95, 1.0, config=9, stream=i) for i, n in enumerate(sizes)]
+               synth.zipf_text(n, 95, 1.0, family=9, stream=i) for i, n in enumerate(sizes)]
     texts = [sm.Text(to_dev(t, dev, (7 * i) % 16)) for i, t in enumerate(texts_h)]
     queries, want = [], []
     for ti, t in enumerate(texts_h):
@@ -423,8 +423,8 @@ def test_text_past_allocation_rejected(dev):
 
 def test_serving_alone_equals_mix(dev):
     from paper_1612_01506_amd.serve import GpuExecutor, Server
-    texts_h = [synth.zipf_text(3_000_000, 95, 1.0, config=5, stream=1),
-               rand_text(2_000_003, 4, 77), synth.zipf_text(1_500_000, 20, 1.0, config=5, stream=2)]
+    texts_h = [synth.zipf_text(3_000_000, 95, 1.0, family=5, stream=1),
+               rand_text(2_000_003, 4, 77), synth.zipf_text(1_500_000, 20, 1.0, family=5, stream=2)]
     ex = GpuExecutor([to_dev(t, dev, 3 * i) for i, t in enumerate(texts_h)], nstreams=2)
     srv = Server(ex, max_batch=96, hbm_budget=1 << 24)
     g = np.random.default_rng(12)

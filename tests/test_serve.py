@@ -60,8 +60,8 @@ class FakeExecutor:
 
 
 def make_texts():
-    return [synth.zipf_text(20_000, 95, 1.0, config=5, stream=i) for i in range(3)] + \
-           [synth.uniform_text(20_000, 4, config=5, stream=9)]
+    return [synth.zipf_text(20_000, 95, 1.0, family=5, stream=i) for i in range(3)] + \
+           [synth.uniform_text(20_000, 4, family=5, stream=9)]
 
 
 def test_results_equal_independent_searches():

@@ -17,17 +17,17 @@ def test_bulk_equals_numpy_definition():
 
 
 def test_deterministic_and_alphabet():
-    a = synth.zipf_text(50_000, 95, 1.0, config=2, stream=0)
-    b = synth.zipf_text(50_000, 95, 1.0, config=2, stream=0)
+    a = synth.zipf_text(50_000, 95, 1.0, family=2, stream=0)
+    b = synth.zipf_text(50_000, 95, 1.0, family=2, stream=0)
     assert np.array_equal(a, b)
     assert set(np.unique(a).tolist()) <= set(synth.ALPHABETS[95])
-    c = synth.uniform_text(50_000, 4, config=1, stream=0)
+    c = synth.uniform_text(50_000, 4, family=1, stream=0)
     assert set(np.unique(c).tolist()) == set(b"ACGT")
 
 
 def test_zipf_frequencies_match_law():
     n = 2_000_000
-    t = synth.zipf_text(n, 95, 1.0, config=2, stream=3)
+    t = synth.zipf_text(n, 95, 1.0, family=2, stream=3)
     ranks = synth.rank_permutation(synth.ALPHABETS[95], 2, 3)
     k = np.arange(1, 96, dtype=np.float64)
     p = (1.0 / k) / (1.0 / k).sum()
