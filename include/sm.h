@@ -196,6 +196,33 @@ typedef struct sm_query {
 int32_t sm_count_batch(const sm_query *q, uint64_t nq, const sm_text *texts, uint64_t nt,
                        uint64_t *counts_dev, const sm_params *params, void *stream);
 
+/* A planned batch (Section 1 problem statement, one count per query, as
+ * sm_count_batch).  sm_batch_create validates and plans the batch exactly as
+ * sm_count_batch does and uploads its tables (step tables, tile and query
+ * lists) into one device buffer owned by the plan, synchronously on the null
+ * stream.  The plan keeps the texts' device addresses and lengths, not their
+ * contents: the texts must stay allocated, and may change contents between
+ * runs.  For a text given with a histogram the plan keeps that histogram's
+ * support (the symbols with a nonzero entry): its counts stay exact only while
+ * the text's symbols stay within that support.  Host inputs (queries,
+ * patterns, orders, histograms) are consumed before return.  nq = 0 gives a plan whose runs do nothing.  On error *out
+ * is NULL.  The plan belongs to the device current at creation. */
+typedef struct sm_batch sm_batch;
+
+int32_t sm_batch_create(const sm_query *q, uint64_t nq, const sm_text *texts, uint64_t nt,
+                        const sm_params *params, sm_batch **out);
+
+/* Runs a plan: counts_dev[i] (device, nq x uint64) is overwritten with the
+ * count of query i.  Launches kernels on `stream` only: no allocation, no
+ * host-device copy and no synchronisation, so the call can be captured in a
+ * HIP graph.  Runs of one plan may overlap on different streams only with
+ * different counts_dev buffers.  SM_EINVAL if the current device is not the
+ * plan's. */
+int32_t sm_batch_run(const sm_batch *b, uint64_t *counts_dev, void *stream);
+
+/* Frees the plan's device buffer (synchronous; no run may be pending). NULL is a no-op. */
+int32_t sm_batch_destroy(sm_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

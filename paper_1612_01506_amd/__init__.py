@@ -25,7 +25,7 @@ from ._lib import (SM_ORDER_FREQ, SM_ORDER_H, SM_ORDER_HS, SM_ORDER_LTR, SmError
                    sm_params, sm_query, sm_text)
 
 __all__ = ["Text", "PackedTexts", "Patterns", "SmError", "histogram", "order", "count", "count_async", "report",
-           "report_async", "count_batch", "version", "device_cus"]
+           "report_async", "count_batch", "BatchPlan", "version", "device_cus"]
 
 ORDER_KINDS = {"ltr": SM_ORDER_LTR, "freq": SM_ORDER_FREQ, "h": SM_ORDER_H, "hs": SM_ORDER_HS}
 
@@ -233,15 +233,8 @@ class PackedTexts:
         return t
 
 
-def count_batch(texts: Sequence, queries: Iterable, peel=None, tile_kib=None, wgs_per_cu=None,
-                stream=None, use_hist: bool = True) -> torch.Tensor:
-    """Counts of many (text_id, pattern[, order]) queries in one persistent launch (asynchronous).
-
-    Returns a device int64 tensor with one count per query.  Queries without an
-    explicit order use the frequency order when the text's histogram is known
-    (texts given as Text objects and use_hist), else left to right.  Texts with
-    a histogram and at least 32 queries run in the bitmap mode.
-    """
+def _marshal_batch(texts, queries, use_hist: bool):
+    """(query array, text array, #texts, #queries, device, objects to keep alive) for the batch calls."""
     assert _TEXT_DT.itemsize == ctypes.sizeof(sm_text) and _QUERY_DT.itemsize == ctypes.sizeof(sm_query)
     keep = []
     dev = None
@@ -287,11 +280,75 @@ def count_batch(texts: Sequence, queries: Iterable, peel=None, tile_kib=None, wg
                 if o is not None:
                     keep.append(o)
                     qarr["order"][i] = o.ctypes.data
+    return qarr, tarr, len(texts), nq, dev, keep
+
+
+def count_batch(texts: Sequence, queries: Iterable, peel=None, tile_kib=None, wgs_per_cu=None,
+                stream=None, use_hist: bool = True) -> torch.Tensor:
+    """Counts of many (text_id, pattern[, order]) queries in one persistent launch (asynchronous).
+
+    Returns a device int64 tensor with one count per query.  Queries without an
+    explicit order use the frequency order when the text's histogram is known
+    (texts given as Text objects and use_hist), else left to right.  Texts with
+    a histogram and at least 32 queries run in the bitmap mode.
+    """
+    qarr, tarr, nt, nq, dev, keep = _marshal_batch(texts, queries, use_hist)
     out = torch.empty(max(nq, 1), dtype=torch.int64, device=dev or "cuda")
     check(load().sm_count_batch(qarr.ctypes.data_as(ctypes.POINTER(sm_query)), nq,
-                                tarr.ctypes.data_as(ctypes.POINTER(sm_text)), len(texts), out.data_ptr(),
+                                tarr.ctypes.data_as(ctypes.POINTER(sm_text)), nt, out.data_ptr(),
                                 _params(peel, tile_kib, wgs_per_cu), _stream(stream)))
+    del keep
     return out[:nq]
+
+
+class BatchPlan:
+    """A batch of (text_id, pattern[, order]) count queries planned and uploaded once (sm_batch_*).
+
+    run() only launches kernels (no allocation, no copy, no synchronisation), so
+    it can be captured in a CUDA/HIP graph and replayed.  The texts must stay
+    allocated while the plan lives; their contents may change between runs.
+    """
+
+    def __init__(self, texts: Sequence, queries: Iterable, peel=None, tile_kib=None, wgs_per_cu=None,
+                 use_hist: bool = True):
+        qarr, tarr, nt, nq, dev, keep = _marshal_batch(texts, queries, use_hist)
+        self.nq = nq
+        self.device = torch.device(dev) if dev is not None else torch.device("cuda", torch.cuda.current_device())
+        self._texts = texts                 # keeps the device texts alive
+        h = ctypes.c_void_p()
+        check(load().sm_batch_create(qarr.ctypes.data_as(ctypes.POINTER(sm_query)), nq,
+                                     tarr.ctypes.data_as(ctypes.POINTER(sm_text)), nt,
+                                     _params(peel, tile_kib, wgs_per_cu), ctypes.byref(h)))
+        del keep
+        self._h = h
+
+    def run(self, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """Overwrites out[:nq] (device int64) with the counts; allocates out when None (not under capture)."""
+        if self._h is None:
+            raise ValueError("plan is closed")
+        if out is None:
+            out = torch.empty(max(self.nq, 1), dtype=torch.int64, device=self.device)
+        if out.dtype != torch.int64 or not out.is_cuda or not out.is_contiguous() or out.numel() < self.nq:
+            raise ValueError("out must be a contiguous device int64 tensor with at least nq entries")
+        check(load().sm_batch_run(self._h, out.data_ptr(), _stream(stream)))
+        return out[:self.nq]
+
+    def close(self) -> None:
+        if self._h is not None:
+            check(load().sm_batch_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 # ------------------------------------------------------------- prepared patterns

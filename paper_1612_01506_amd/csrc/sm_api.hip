@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cstring>
 #include <deque>
+#include <functional>
 #include <memory>
 #include <mutex>
 #include <numeric>
@@ -101,10 +102,13 @@ int get_dev(Dev **out)
         if (e == hipSuccess)
             e = hipHostMalloc(reinterpret_cast<void **>(&d->hpin), 2 * sizeof(unsigned long long),
                               hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = prime_kernel_attrs();
         if (e != hipSuccess) {
             if (d->rh) (void)hipHostFree(d->rh);
             if (d->rd) (void)hipFree(d->rd);
             if (d->u64) (void)hipFree(d->u64);
+            if (d->hpin) (void)hipHostFree(d->hpin);
             delete d;
             return fail(e == hipErrorOutOfMemory ? SM_ENOMEM : SM_EDEVICE,
                         std::string("device init: ") + hipGetErrorString(e));
@@ -576,6 +580,396 @@ constexpr uint64_t kBmMinQueries = 32;
 
 }  // namespace
 
+namespace {
+int validate_batch(const sm_query *q, uint64_t nq, const sm_text *texts, uint64_t nt)
+{
+    g_err.clear();
+    if (!q)
+        return fail(SM_EINVAL, "q is NULL");
+    if (nq >= (1ull << 32))
+        return fail(SM_EINVAL, "too many queries");
+    if (nt > 0 && !texts)
+        return fail(SM_EINVAL, "texts is NULL");
+    AllocCache cache;
+    for (uint64_t i = 0; i < nt; ++i) {
+        int rc = check_text(texts[i].t, texts[i].n, &cache);
+        if (rc < 0)
+            return fail(rc, "text " + std::to_string(i) + ": " + g_err);
+    }
+    for (uint64_t i = 0; i < nq; ++i) {
+        if (q[i].text_id >= nt)
+            return fail(SM_EINVAL, "query " + std::to_string(i) + ": text_id out of range");
+        if (q[i].flags != 0)
+            return fail(SM_EINVAL, "query " + std::to_string(i) + ": unknown flags");
+        int rc = check_pattern(q[i].p, q[i].m, q[i].order);
+        if (rc < 0)
+            return fail(rc, "query " + std::to_string(i) + ": " + g_err);
+    }
+    return SM_OK;
+}
+
+// Launch description of a planned batch.  Tables live in one device buffer
+// (`dev`) laid out at the offsets below; they hold absolute device addresses
+// into that buffer, so a plan is bound to the buffer it was filled for.
+struct LaunchPlan {
+    size_t bytes = 0;
+    size_t o_items = 0, o_tchunk = 0, o_queries = 0, o_steps = 0, o_bitems = 0, o_bq = 0, o_bout = 0,
+           o_smap = 0, o_bsteps = 0;
+    uint64_t nq = 0;
+    // bitmap launch
+    uint64_t n_bitems = 0;
+    uint32_t bm_words = 0;
+    uint64_t bm_grid = 0;
+    // byte-tile launch
+    uint64_t ntiles = 0;
+    uint32_t halo_max = 0;
+    int cpl = 2;
+    uint64_t st_grid = 0;
+    // long patterns: one global-kernel search each
+    struct Long {
+        TextView tv;
+        uint64_t m, steps_off, out;
+        Tune tu;
+    };
+    std::vector<Long> longs;
+};
+
+using AllocFn = std::function<int(size_t, uint8_t **, uint8_t **)>;
+
+// Plans a validated batch: classifies the queries (bitmap / byte tiles /
+// long), builds every table into host memory obtained from `alloc` (which
+// also names the device address the tables will live at) and fills `lp`.
+int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uint64_t nt, const sm_params *params,
+               const AllocFn &alloc, LaunchPlan *lp)
+{
+    lp->nq = nq;
+    const int cpl = (params && (params->tile_kib == 4 || params->tile_kib == 8 || params->tile_kib == 16))
+                        ? params->tile_kib / 4
+                        : 2;
+    const uint64_t T = 4096ull * cpl;
+    const int rdef = (params && params->peel > 0) ? std::min<int>(params->peel, (int)kMaxPeel) : 2;
+    const int wpc = (params && params->wgs_per_cu > 0) ? std::min(params->wgs_per_cu, 32) : 6;
+    const uint64_t target = (uint64_t)std::max(d.cus, 1) * (uint64_t)wpc;
+    // two LDS tile buffers of T + halo and the query counters must fit
+    const uint64_t max_halo = (kMaxLds - kQChunk * sizeof(uint32_t)) / 2 - T;
+
+    // ---- per-text alphabets (bitmap mode needs the histogram)
+    std::vector<std::vector<uint8_t>> smaps(nt);
+    std::vector<uint32_t> nslots(nt, 0);
+    std::vector<uint64_t> nbm(nt, 0);
+    for (uint64_t i = 0; i < nt; ++i) {
+        if (!texts[i].hist)
+            continue;
+        smaps[i].assign(256, 0xFF);
+        for (int b = 0; b < 256; ++b)
+            if (texts[i].hist[b])
+                smaps[i][b] = (uint8_t)nslots[i]++;
+    }
+    auto bm_wps = [](uint64_t m_max) { return (uint32_t)round_up(258 + ceil_div(m_max, 32), 4); };
+    auto bm_lds = [&](uint32_t slots, uint32_t wps) {
+        return (uint64_t)slots * wps * 4 + 256 + kBmQChunk * sizeof(uint32_t);
+    };
+    auto bm_bucket = [](uint64_t m) -> uint32_t { return m <= 256 ? 256 : (m <= 1024 ? 1024 : 4096); };
+    // a text qualifies if its alphabet fits next to the largest bucket it needs
+    std::vector<uint8_t> text_bm(nt, 0);
+    for (uint64_t i = 0; i < nq; ++i) {
+        const uint32_t t = q[i].text_id;
+        if (texts[t].hist && q[i].m <= texts[t].n && q[i].m <= 4096 && nslots[t] > 0 &&
+            bm_lds(nslots[t], bm_wps(bm_bucket(q[i].m))) <= kBmMaxLds)
+            nbm[t]++;
+    }
+    for (uint64_t t = 0; t < nt; ++t)
+        text_bm[t] = nbm[t] >= kBmMinQueries;
+
+    // ---- classify queries
+    std::vector<PlanQuery> staged, longq, bmq;
+    uint64_t total_steps = 0, total_bm_steps = 0;
+    for (uint64_t i = 0; i < nq; ++i) {
+        const uint32_t t = q[i].text_id;
+        const uint64_t n = texts[t].n;
+        if (q[i].m > n)
+            continue;  // count stays 0
+        if (text_bm[t] && q[i].m <= 4096 && bm_lds(nslots[t], bm_wps(bm_bucket(q[i].m))) <= kBmMaxLds) {
+            bool absent = false;
+            for (uint64_t j = 0; j < q[i].m && !absent; ++j)
+                absent = smaps[t][q[i].p[j]] == 0xFF;
+            if (absent)
+                continue;  // a symbol the text lacks: count 0
+            bmq.push_back({i, t, q[i].m, bm_bucket(q[i].m)});
+            total_bm_steps += q[i].m;
+            continue;
+        }
+        PlanQuery pq{i, t, q[i].m, 0};
+        const uint64_t halo = halo_for(q[i].m);
+        uint64_t b = 64;
+        while (b < halo)
+            b <<= 1;
+        pq.bucket = (uint32_t)b;
+        if (halo <= max_halo)
+            staged.push_back(pq);
+        else
+            longq.push_back(pq);
+        total_steps += q[i].m + kStepPad;
+    }
+    auto by_text_bucket = [](const PlanQuery &a, const PlanQuery &b) {
+        return a.text != b.text ? a.text < b.text : a.bucket < b.bucket;
+    };
+    std::stable_sort(staged.begin(), staged.end(), by_text_bucket);
+    std::stable_sort(bmq.begin(), bmq.end(), by_text_bucket);
+
+    struct Chunk {
+        uint32_t text;
+        uint32_t q0, q1;
+        uint64_t m_min, m_max;
+    };
+    auto make_chunks = [](const std::vector<PlanQuery> &v, uint32_t cap) {
+        std::vector<Chunk> out;
+        for (uint32_t i = 0; i < v.size();) {
+            uint32_t j = i;
+            uint64_t mn = v[i].m, mx = v[i].m;
+            while (j < v.size() && j - i < cap && v[j].text == v[i].text && v[j].bucket == v[i].bucket) {
+                mn = std::min(mn, v[j].m);
+                mx = std::max(mx, v[j].m);
+                ++j;
+            }
+            out.push_back({v[i].text, i, j, mn, mx});
+            i = j;
+        }
+        return out;
+    };
+    const std::vector<Chunk> chunks = make_chunks(staged, kQChunk);
+    const std::vector<Chunk> bchunks = make_chunks(bmq, kBmQChunk);
+
+    // ---- byte-tile chunks in one global tile space
+    std::vector<BatchChunk> bchunks_t;
+    std::vector<uint32_t> tile_chunk;
+    uint32_t halo_max = 16;
+    for (auto &c : chunks) {
+        const sm_text &tx = texts[c.text];
+        const TextView tv = make_view(tx.t, tx.n);
+        const uint64_t ntiles = ceil_div(tv.first + tx.n - c.m_min + 1, T);
+        BatchChunk bc{};
+        bc.tv = tv;
+        bc.tile0 = tile_chunk.size();
+        bc.q_begin = c.q0;
+        bc.q_end = c.q1;
+        bc.halo = halo_for(c.m_max);
+        halo_max = std::max(halo_max, bc.halo);
+        tile_chunk.insert(tile_chunk.end(), ntiles, (uint32_t)bchunks_t.size());
+        bchunks_t.push_back(bc);
+    }
+
+    // ---- bitmap items
+    const uint64_t bm_per_cu_guess = 1;
+    const uint64_t bm_grid_target = (uint64_t)std::max(d.cus, 1) * bm_per_cu_guess;
+    uint64_t bm_work = 0;
+    for (auto &c : bchunks) {
+        const uint64_t first = reinterpret_cast<uintptr_t>(texts[c.text].t) & 15u;
+        bm_work += ceil_div(first + texts[c.text].n - c.m_min + 1, kBmT);
+    }
+    const uint64_t bspan = std::max<uint64_t>(1, bm_work / (bm_grid_target * 4));
+    std::vector<BmItem> bitems;
+    uint32_t bm_words = 0;
+    for (auto &c : bchunks) {
+        const sm_text &tx = texts[c.text];
+        const TextView tv = make_view(tx.t, tx.n);
+        const uint64_t ntiles = ceil_div(tv.first + tx.n - c.m_min + 1, kBmT);
+        const uint32_t wps = bm_wps(c.m_max);
+        bm_words = std::max(bm_words, nslots[c.text] * wps);
+        for (uint64_t t0 = 0; t0 < ntiles; t0 += bspan) {
+            BmItem it{};
+            it.tv = tv;
+            it.tile_begin = t0;
+            it.tile_end = std::min(ntiles, t0 + bspan);
+            it.q_begin = c.q0;
+            it.q_end = c.q1;
+            it.wps = wps;
+            it.nslots = nslots[c.text];
+            it.smap = nullptr;  // set after upload layout is known
+            bitems.push_back(it);
+        }
+    }
+
+    // ---- one upload: [chunks | tile->chunk | queries | steps | bitmap items | bitmap queries | outs |
+    //                   smaps | bitmap steps]
+    const size_t o_items = 0;
+    const size_t o_tchunk = o_items + round_up(bchunks_t.size() * sizeof(BatchChunk), 256);
+    const size_t o_queries = o_tchunk + round_up(tile_chunk.size() * sizeof(uint32_t), 256);
+    const size_t o_steps = o_queries + round_up(std::max<size_t>(staged.size(), 1) * sizeof(BatchQuery), 256);
+    const size_t o_bitems = o_steps + round_up(total_steps * sizeof(uint64_t), 256);
+    const size_t o_bq = o_bitems + round_up(bitems.size() * sizeof(BmItem), 256);
+    const size_t o_bout = o_bq + round_up(bmq.size() * sizeof(BmQuery), 256);
+    const size_t o_smap = o_bout + round_up(bmq.size() * sizeof(uint32_t), 256);
+    const size_t o_bsteps = o_smap + round_up(nt * 256, 256);
+    if (total_bm_steps >= (1ull << 32))
+        return fail(SM_EINVAL, "batch too large: pattern bytes in bitmap mode exceed 2^32");
+    const size_t bytes = o_bsteps + round_up(total_bm_steps * sizeof(uint32_t), 256);
+    uint8_t *uhost = nullptr, *udev = nullptr;
+    SM_TRY(alloc(bytes, &uhost, &udev));
+    lp->bytes = bytes;
+    std::copy(bchunks_t.begin(), bchunks_t.end(), reinterpret_cast<BatchChunk *>(uhost + o_items));
+    std::copy(tile_chunk.begin(), tile_chunk.end(), reinterpret_cast<uint32_t *>(uhost + o_tchunk));
+    BatchQuery *hq = reinterpret_cast<BatchQuery *>(uhost + o_queries);
+    uint64_t *hs = reinterpret_cast<uint64_t *>(uhost + o_steps);
+    uint64_t soff = 0;
+    std::vector<int32_t> ord;
+    std::vector<uint32_t> cnt;
+    std::vector<std::unique_ptr<FreqRanks>> ranks(nt);
+    auto order_of = [&](uint64_t qi) -> const int32_t * {
+        const sm_query &Q = q[qi];
+        if (Q.order)
+            return Q.order;
+        ord.resize(Q.m);
+        if (texts[Q.text_id].hist) {
+            if (!ranks[Q.text_id])
+                ranks[Q.text_id].reset(new FreqRanks(texts[Q.text_id].hist));
+            ranks[Q.text_id]->order(Q.p, Q.m, ord.data(), cnt);
+        } else {
+            order_ltr(Q.m, ord.data());
+        }
+        return ord.data();
+    };
+    auto emit_steps = [&](uint64_t qi) -> uint64_t {
+        const sm_query &Q = q[qi];
+        build_steps(Q.p, Q.m, order_of(qi), hs + soff);
+        const uint64_t at = soff;
+        soff += Q.m + kStepPad;
+        return at;
+    };
+    for (size_t i = 0; i < staged.size(); ++i) {
+        const PlanQuery &pq = staged[i];
+        const sm_text &tx = texts[pq.text];
+        BatchQuery bq{};
+        bq.steps_off = emit_steps(pq.idx);
+        bq.last = (reinterpret_cast<uintptr_t>(tx.t) & 15u) + tx.n - pq.m;
+        bq.m = (uint32_t)pq.m;
+        bq.r = (uint32_t)std::min<uint64_t>((uint64_t)rdef, pq.m);
+        bq.out = (uint32_t)pq.idx;
+        hq[i] = bq;
+    }
+    std::vector<uint64_t> long_steps_off;
+    for (auto &pq : longq)
+        long_steps_off.push_back(emit_steps(pq.idx));
+    // bitmap part
+    BmItem *hbi = reinterpret_cast<BmItem *>(uhost + o_bitems);
+    BmQuery *hbq = reinterpret_cast<BmQuery *>(uhost + o_bq);
+    uint32_t *hbout = reinterpret_cast<uint32_t *>(uhost + o_bout);
+    uint8_t *hsm = uhost + o_smap;
+    uint32_t *hbs = reinterpret_cast<uint32_t *>(uhost + o_bsteps);
+    for (uint64_t t = 0; t < nt; ++t)
+        if (!smaps[t].empty())
+            std::copy(smaps[t].begin(), smaps[t].end(), hsm + 256 * t);
+    uint64_t bsoff = 0;
+    for (auto &c : bchunks) {
+        const uint32_t wps = bm_wps(c.m_max);
+        for (uint32_t i = c.q0; i < c.q1; ++i) {
+            const PlanQuery &pq = bmq[i];
+            const sm_query &Q = q[pq.idx];
+            const int32_t *o = order_of(pq.idx);
+            for (uint64_t l = 0; l < Q.m; ++l) {
+                const uint32_t j = (uint32_t)o[l];
+                const uint32_t slot = smaps[pq.text][Q.p[j]];
+                hbs[bsoff + l] = ((slot * wps + (j >> 5)) << 5) | (j & 31u);
+            }
+            BmQuery bq{};
+            bq.e0 = hbs[bsoff];
+            bq.e1 = Q.m > 1 ? hbs[bsoff + 1] : hbs[bsoff];
+            bq.steps_off = (uint32_t)bsoff;
+            bq.mr = (uint32_t)pq.m | ((uint32_t)std::min<uint64_t>((uint64_t)rdef, pq.m) << 24);
+            hbq[i] = bq;
+            hbout[i] = (uint32_t)pq.idx;
+            bsoff += Q.m;
+        }
+    }
+    {
+        size_t k = 0;
+        for (auto &c : bchunks) {
+            const uint64_t first = reinterpret_cast<uintptr_t>(texts[c.text].t) & 15u;
+            const uint64_t ntiles = ceil_div(first + texts[c.text].n - c.m_min + 1, kBmT);
+            for (uint64_t t0 = 0; t0 < ntiles; t0 += bspan) {
+                bitems[k].smap = udev + o_smap + 256 * c.text;
+                ++k;
+            }
+        }
+        std::copy(bitems.begin(), bitems.end(), hbi);
+    }
+    lp->o_items = o_items;
+    lp->o_tchunk = o_tchunk;
+    lp->o_queries = o_queries;
+    lp->o_steps = o_steps;
+    lp->o_bitems = o_bitems;
+    lp->o_bq = o_bq;
+    lp->o_bout = o_bout;
+    lp->o_smap = o_smap;
+    lp->o_bsteps = o_bsteps;
+    lp->n_bitems = bitems.size();
+    lp->bm_words = (uint32_t)round_up(bm_words, 4);
+    {
+        const uint32_t lds = lp->bm_words * 4 + 256 + kBmQChunk * sizeof(uint32_t);
+        const uint64_t per_cu = std::max<uint64_t>(1, kBmMaxLds / lds);
+        lp->bm_grid = std::min<uint64_t>(bitems.size(), (uint64_t)std::max(d.cus, 1) * std::min<uint64_t>(per_cu, 2));
+    }
+    lp->ntiles = tile_chunk.size();
+    lp->halo_max = halo_max;
+    lp->cpl = cpl;
+    lp->st_grid = std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(tile_chunk.size(), 1ull << kChunkLog2), target));
+    for (size_t i = 0; i < longq.size(); ++i) {
+        const PlanQuery &pq = longq[i];
+        LaunchPlan::Long L;
+        L.tv = make_view(texts[pq.text].t, texts[pq.text].n);
+        L.m = pq.m;
+        L.steps_off = long_steps_off[i];
+        L.out = pq.idx;
+        L.tu = Tune{(int)std::min<uint64_t>((uint64_t)rdef, pq.m), 1, wpc, (int)kChunkLog2};
+        lp->longs.push_back(L);
+    }
+    return SM_OK;
+}
+
+// Zeroes the counts and launches the planned kernels; no host-device copy
+// and no allocation, so it can be captured in a graph.
+int launch_plan(Dev &d, const LaunchPlan &lp, const uint8_t *dev, unsigned long long *counts, hipStream_t s)
+{
+    HIP_TRY(launch_fill_u64(counts, lp.nq, 0ull, s));
+    if (lp.n_bitems) {
+        BmArgs a{};
+        a.items = reinterpret_cast<const BmItem *>(dev + lp.o_bitems);
+        a.nitems = lp.n_bitems;
+        a.queries = reinterpret_cast<const BmQuery *>(dev + lp.o_bq);
+        a.outs = reinterpret_cast<const uint32_t *>(dev + lp.o_bout);
+        a.steps = reinterpret_cast<const uint32_t *>(dev + lp.o_bsteps);
+        a.counts = counts;
+        a.bm_words = lp.bm_words;
+        const uint32_t lds = a.bm_words * 4 + 256 + kBmQChunk * sizeof(uint32_t);
+        HIP_TRY(launch_batch_bitmap(a, (unsigned)lp.bm_grid, lds, s));
+    }
+    if (lp.ntiles) {
+        BatchArgs a{};
+        a.chunks = reinterpret_cast<const BatchChunk *>(dev + lp.o_items);
+        a.tile_chunk = reinterpret_cast<const uint32_t *>(dev + lp.o_tchunk);
+        a.ntiles = lp.ntiles;
+        a.queries = reinterpret_cast<const BatchQuery *>(dev + lp.o_queries);
+        a.steps = reinterpret_cast<const uint64_t *>(dev + lp.o_steps);
+        a.counts = counts;
+        a.halo_max = lp.halo_max;
+        a.chunk_log2 = kChunkLog2;
+        HIP_TRY(launch_batch_staged(a, lp.cpl, (unsigned)lp.st_grid, s));
+    }
+    for (const auto &L : lp.longs)
+        SM_TRY(launch_count(d, L.tv, L.m, reinterpret_cast<const uint64_t *>(dev + lp.o_steps) + L.steps_off, L.tu,
+                            counts + L.out, nullptr, nullptr, s));
+    return SM_OK;
+}
+
+}  // namespace
+
+// A planned batch: tables in one plan-owned device buffer.
+struct sm_batch {
+    int dev = -1;
+    uint8_t *buf = nullptr;
+    LaunchPlan lp;
+};
+
 // A prepared pattern set: step tables of all patterns in one device buffer.
 struct sm_patterns {
     int dev = -1;
@@ -897,332 +1291,100 @@ int32_t sm_count_batch(const sm_query *q, uint64_t nq, const sm_text *texts, uin
     g_err.clear();
     if (nq == 0)
         return SM_OK;
-    if (!q || !counts_dev)
-        return fail(SM_EINVAL, "q or counts_dev is NULL");
-    if (nq >= (1ull << 32))
-        return fail(SM_EINVAL, "too many queries");
-    if (nt > 0 && !texts)
-        return fail(SM_EINVAL, "texts is NULL");
-    AllocCache cache;
-    for (uint64_t i = 0; i < nt; ++i) {
-        int rc = check_text(texts[i].t, texts[i].n, &cache);
-        if (rc < 0)
-            return fail(rc, "text " + std::to_string(i) + ": " + g_err);
-    }
-    for (uint64_t i = 0; i < nq; ++i) {
-        if (q[i].text_id >= nt)
-            return fail(SM_EINVAL, "query " + std::to_string(i) + ": text_id out of range");
-        if (q[i].flags != 0)
-            return fail(SM_EINVAL, "query " + std::to_string(i) + ": unknown flags");
-        int rc = check_pattern(q[i].p, q[i].m, q[i].order);
-        if (rc < 0)
-            return fail(rc, "query " + std::to_string(i) + ": " + g_err);
-    }
+    if (!counts_dev)
+        return fail(SM_EINVAL, "counts_dev is NULL");
+    SM_TRY(validate_batch(q, nq, texts, nt));
     Dev *d;
     SM_TRY(get_dev(&d));
     std::lock_guard<std::mutex> lk(d->mu);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    unsigned long long *counts = reinterpret_cast<unsigned long long *>(counts_dev);
-    HIP_TRY(launch_fill_u64(counts, nq, 0ull, s));
-
-    const int cpl = (params && (params->tile_kib == 4 || params->tile_kib == 8 || params->tile_kib == 16))
-                        ? params->tile_kib / 4
-                        : 2;
-    const uint64_t T = 4096ull * cpl;
-    const int rdef = (params && params->peel > 0) ? std::min<int>(params->peel, (int)kMaxPeel) : 2;
-    const int wpc = (params && params->wgs_per_cu > 0) ? std::min(params->wgs_per_cu, 32) : 6;
-    const uint64_t target = (uint64_t)std::max(d->cus, 1) * (uint64_t)wpc;
-    // two LDS tile buffers of T + halo and the query counters must fit
-    const uint64_t max_halo = (kMaxLds - kQChunk * sizeof(uint32_t)) / 2 - T;
-
-    // ---- per-text alphabets (bitmap mode needs the histogram)
-    std::vector<std::vector<uint8_t>> smaps(nt);
-    std::vector<uint32_t> nslots(nt, 0);
-    std::vector<uint64_t> nbm(nt, 0);
-    for (uint64_t i = 0; i < nt; ++i) {
-        if (!texts[i].hist)
-            continue;
-        smaps[i].assign(256, 0xFF);
-        for (int b = 0; b < 256; ++b)
-            if (texts[i].hist[b])
-                smaps[i][b] = (uint8_t)nslots[i]++;
-    }
-    auto bm_wps = [](uint64_t m_max) { return (uint32_t)round_up(258 + ceil_div(m_max, 32), 4); };
-    auto bm_lds = [&](uint32_t slots, uint32_t wps) {
-        return (uint64_t)slots * wps * 4 + 256 + kBmQChunk * sizeof(uint32_t);
-    };
-    auto bm_bucket = [](uint64_t m) -> uint32_t { return m <= 256 ? 256 : (m <= 1024 ? 1024 : 4096); };
-    // a text qualifies if its alphabet fits next to the largest bucket it needs
-    std::vector<uint8_t> text_bm(nt, 0);
-    for (uint64_t i = 0; i < nq; ++i) {
-        const uint32_t t = q[i].text_id;
-        if (texts[t].hist && q[i].m <= texts[t].n && q[i].m <= 4096 && nslots[t] > 0 &&
-            bm_lds(nslots[t], bm_wps(bm_bucket(q[i].m))) <= kBmMaxLds)
-            nbm[t]++;
-    }
-    for (uint64_t t = 0; t < nt; ++t)
-        text_bm[t] = nbm[t] >= kBmMinQueries;
-
-    // ---- classify queries
-    std::vector<PlanQuery> staged, longq, bmq;
-    uint64_t total_steps = 0, total_bm_steps = 0;
-    for (uint64_t i = 0; i < nq; ++i) {
-        const uint32_t t = q[i].text_id;
-        const uint64_t n = texts[t].n;
-        if (q[i].m > n)
-            continue;  // count stays 0
-        if (text_bm[t] && q[i].m <= 4096 && bm_lds(nslots[t], bm_wps(bm_bucket(q[i].m))) <= kBmMaxLds) {
-            bool absent = false;
-            for (uint64_t j = 0; j < q[i].m && !absent; ++j)
-                absent = smaps[t][q[i].p[j]] == 0xFF;
-            if (absent)
-                continue;  // a symbol the text lacks: count 0
-            bmq.push_back({i, t, q[i].m, bm_bucket(q[i].m)});
-            total_bm_steps += q[i].m;
-            continue;
-        }
-        PlanQuery pq{i, t, q[i].m, 0};
-        const uint64_t halo = halo_for(q[i].m);
-        uint64_t b = 64;
-        while (b < halo)
-            b <<= 1;
-        pq.bucket = (uint32_t)b;
-        if (halo <= max_halo)
-            staged.push_back(pq);
-        else
-            longq.push_back(pq);
-        total_steps += q[i].m + kStepPad;
-    }
-    auto by_text_bucket = [](const PlanQuery &a, const PlanQuery &b) {
-        return a.text != b.text ? a.text < b.text : a.bucket < b.bucket;
-    };
-    std::stable_sort(staged.begin(), staged.end(), by_text_bucket);
-    std::stable_sort(bmq.begin(), bmq.end(), by_text_bucket);
-
-    struct Chunk {
-        uint32_t text;
-        uint32_t q0, q1;
-        uint64_t m_min, m_max;
-    };
-    auto make_chunks = [](const std::vector<PlanQuery> &v, uint32_t cap) {
-        std::vector<Chunk> out;
-        for (uint32_t i = 0; i < v.size();) {
-            uint32_t j = i;
-            uint64_t mn = v[i].m, mx = v[i].m;
-            while (j < v.size() && j - i < cap && v[j].text == v[i].text && v[j].bucket == v[i].bucket) {
-                mn = std::min(mn, v[j].m);
-                mx = std::max(mx, v[j].m);
-                ++j;
-            }
-            out.push_back({v[i].text, i, j, mn, mx});
-            i = j;
-        }
-        return out;
-    };
-    const std::vector<Chunk> chunks = make_chunks(staged, kQChunk);
-    const std::vector<Chunk> bchunks = make_chunks(bmq, kBmQChunk);
-
-    // ---- byte-tile chunks in one global tile space
-    std::vector<BatchChunk> bchunks_t;
-    std::vector<uint32_t> tile_chunk;
-    uint32_t halo_max = 16;
-    for (auto &c : chunks) {
-        const sm_text &tx = texts[c.text];
-        const TextView tv = make_view(tx.t, tx.n);
-        const uint64_t ntiles = ceil_div(tv.first + tx.n - c.m_min + 1, T);
-        BatchChunk bc{};
-        bc.tv = tv;
-        bc.tile0 = tile_chunk.size();
-        bc.q_begin = c.q0;
-        bc.q_end = c.q1;
-        bc.halo = halo_for(c.m_max);
-        halo_max = std::max(halo_max, bc.halo);
-        tile_chunk.insert(tile_chunk.end(), ntiles, (uint32_t)bchunks_t.size());
-        bchunks_t.push_back(bc);
-    }
-
-    // ---- bitmap items
-    const uint64_t bm_per_cu_guess = 1;
-    const uint64_t bm_grid_target = (uint64_t)std::max(d->cus, 1) * bm_per_cu_guess;
-    uint64_t bm_work = 0;
-    for (auto &c : bchunks) {
-        const uint64_t first = reinterpret_cast<uintptr_t>(texts[c.text].t) & 15u;
-        bm_work += ceil_div(first + texts[c.text].n - c.m_min + 1, kBmT);
-    }
-    const uint64_t bspan = std::max<uint64_t>(1, bm_work / (bm_grid_target * 4));
-    std::vector<BmItem> bitems;
-    uint32_t bm_words = 0;
-    for (auto &c : bchunks) {
-        const sm_text &tx = texts[c.text];
-        const TextView tv = make_view(tx.t, tx.n);
-        const uint64_t ntiles = ceil_div(tv.first + tx.n - c.m_min + 1, kBmT);
-        const uint32_t wps = bm_wps(c.m_max);
-        bm_words = std::max(bm_words, nslots[c.text] * wps);
-        for (uint64_t t0 = 0; t0 < ntiles; t0 += bspan) {
-            BmItem it{};
-            it.tv = tv;
-            it.tile_begin = t0;
-            it.tile_end = std::min(ntiles, t0 + bspan);
-            it.q_begin = c.q0;
-            it.q_end = c.q1;
-            it.wps = wps;
-            it.nslots = nslots[c.text];
-            it.smap = nullptr;  // set after upload layout is known
-            bitems.push_back(it);
-        }
-    }
-
-    // ---- one upload: [chunks | tile->chunk | queries | steps | bitmap items | bitmap queries | outs |
-    //                   smaps | bitmap steps]
-    const size_t o_items = 0;
-    const size_t o_tchunk = o_items + round_up(bchunks_t.size() * sizeof(BatchChunk), 256);
-    const size_t o_queries = o_tchunk + round_up(tile_chunk.size() * sizeof(uint32_t), 256);
-    const size_t o_steps = o_queries + round_up(std::max<size_t>(staged.size(), 1) * sizeof(BatchQuery), 256);
-    const size_t o_bitems = o_steps + round_up(total_steps * sizeof(uint64_t), 256);
-    const size_t o_bq = o_bitems + round_up(bitems.size() * sizeof(BmItem), 256);
-    const size_t o_bout = o_bq + round_up(bmq.size() * sizeof(BmQuery), 256);
-    const size_t o_smap = o_bout + round_up(bmq.size() * sizeof(uint32_t), 256);
-    const size_t o_bsteps = o_smap + round_up(nt * 256, 256);
-    if (total_bm_steps >= (1ull << 32))
-        return fail(SM_EINVAL, "batch too large: pattern bytes in bitmap mode exceed 2^32");
-    const size_t bytes = o_bsteps + round_up(total_bm_steps * sizeof(uint32_t), 256);
     Upload u;
-    SM_TRY(ring_reserve(*d, bytes, &u));
-    std::copy(bchunks_t.begin(), bchunks_t.end(), reinterpret_cast<BatchChunk *>(u.host + o_items));
-    std::copy(tile_chunk.begin(), tile_chunk.end(), reinterpret_cast<uint32_t *>(u.host + o_tchunk));
-    BatchQuery *hq = reinterpret_cast<BatchQuery *>(u.host + o_queries);
-    uint64_t *hs = reinterpret_cast<uint64_t *>(u.host + o_steps);
-    uint64_t soff = 0;
-    std::vector<int32_t> ord;
-    std::vector<uint32_t> cnt;
-    std::vector<std::unique_ptr<FreqRanks>> ranks(nt);
-    auto order_of = [&](uint64_t qi) -> const int32_t * {
-        const sm_query &Q = q[qi];
-        if (Q.order)
-            return Q.order;
-        ord.resize(Q.m);
-        if (texts[Q.text_id].hist) {
-            if (!ranks[Q.text_id])
-                ranks[Q.text_id].reset(new FreqRanks(texts[Q.text_id].hist));
-            ranks[Q.text_id]->order(Q.p, Q.m, ord.data(), cnt);
-        } else {
-            order_ltr(Q.m, ord.data());
-        }
-        return ord.data();
+    LaunchPlan lp;
+    AllocFn alloc = [&](size_t bytes, uint8_t **h, uint8_t **dv) {
+        SM_TRY(ring_reserve(*d, bytes, &u));
+        *h = u.host;
+        *dv = u.dev;
+        return (int)SM_OK;
     };
-    auto emit_steps = [&](uint64_t qi) -> uint64_t {
-        const sm_query &Q = q[qi];
-        build_steps(Q.p, Q.m, order_of(qi), hs + soff);
-        const uint64_t at = soff;
-        soff += Q.m + kStepPad;
-        return at;
-    };
-    for (size_t i = 0; i < staged.size(); ++i) {
-        const PlanQuery &pq = staged[i];
-        const sm_text &tx = texts[pq.text];
-        BatchQuery bq{};
-        bq.steps_off = emit_steps(pq.idx);
-        bq.last = (reinterpret_cast<uintptr_t>(tx.t) & 15u) + tx.n - pq.m;
-        bq.m = (uint32_t)pq.m;
-        bq.r = (uint32_t)std::min<uint64_t>((uint64_t)rdef, pq.m);
-        bq.out = (uint32_t)pq.idx;
-        hq[i] = bq;
-    }
-    std::vector<uint64_t> long_steps_off;
-    for (auto &pq : longq)
-        long_steps_off.push_back(emit_steps(pq.idx));
-    // bitmap part
-    BmItem *hbi = reinterpret_cast<BmItem *>(u.host + o_bitems);
-    BmQuery *hbq = reinterpret_cast<BmQuery *>(u.host + o_bq);
-    uint32_t *hbout = reinterpret_cast<uint32_t *>(u.host + o_bout);
-    uint8_t *hsm = u.host + o_smap;
-    uint32_t *hbs = reinterpret_cast<uint32_t *>(u.host + o_bsteps);
-    for (uint64_t t = 0; t < nt; ++t)
-        if (!smaps[t].empty())
-            std::copy(smaps[t].begin(), smaps[t].end(), hsm + 256 * t);
-    uint64_t bsoff = 0;
-    for (auto &c : bchunks) {
-        const uint32_t wps = bm_wps(c.m_max);
-        for (uint32_t i = c.q0; i < c.q1; ++i) {
-            const PlanQuery &pq = bmq[i];
-            const sm_query &Q = q[pq.idx];
-            const int32_t *o = order_of(pq.idx);
-            for (uint64_t l = 0; l < Q.m; ++l) {
-                const uint32_t j = (uint32_t)o[l];
-                const uint32_t slot = smaps[pq.text][Q.p[j]];
-                hbs[bsoff + l] = ((slot * wps + (j >> 5)) << 5) | (j & 31u);
-            }
-            BmQuery bq{};
-            bq.e0 = hbs[bsoff];
-            bq.e1 = Q.m > 1 ? hbs[bsoff + 1] : hbs[bsoff];
-            bq.steps_off = (uint32_t)bsoff;
-            bq.mr = (uint32_t)pq.m | ((uint32_t)std::min<uint64_t>((uint64_t)rdef, pq.m) << 24);
-            hbq[i] = bq;
-            hbout[i] = (uint32_t)pq.idx;
-            bsoff += Q.m;
-        }
-    }
-    {
-        size_t k = 0;
-        for (auto &c : bchunks) {
-            const uint64_t first = reinterpret_cast<uintptr_t>(texts[c.text].t) & 15u;
-            const uint64_t ntiles = ceil_div(first + texts[c.text].n - c.m_min + 1, kBmT);
-            for (uint64_t t0 = 0; t0 < ntiles; t0 += bspan) {
-                bitems[k].smap = u.dev + o_smap + 256 * c.text;
-                ++k;
-            }
-        }
-        std::copy(bitems.begin(), bitems.end(), hbi);
-    }
-    SM_TRY(ring_copy(u, bytes, s));
-
-    auto bail = [&](int rc, const std::string &msg) {
-        (void)ring_commit(*d, u, s);
+    SM_TRY(plan_batch(*d, q, nq, texts, nt, params, alloc, &lp));
+    int rc = ring_copy(u, lp.bytes, s);
+    if (rc == SM_OK)
+        rc = launch_plan(*d, lp, u.dev, reinterpret_cast<unsigned long long *>(counts_dev), s);
+    const std::string msg = g_err;
+    const int rc2 = ring_commit(*d, u, s);
+    if (rc < 0)
         return fail(rc, msg);
+    return rc2;
+}
+
+int32_t sm_batch_create(const sm_query *q, uint64_t nq, const sm_text *texts, uint64_t nt, const sm_params *params,
+                        sm_batch **out)
+{
+    g_err.clear();
+    if (!out)
+        return fail(SM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (nq > 0)
+        SM_TRY(validate_batch(q, nq, texts, nt));
+    Dev *d;
+    SM_TRY(get_dev(&d));
+    sm_batch *b = new sm_batch();
+    b->dev = d->id;
+    std::vector<uint8_t> host;
+    AllocFn alloc = [&](size_t bytes, uint8_t **h, uint8_t **dv) {
+        host.assign(bytes, 0);
+        hipError_t e = hipMalloc(reinterpret_cast<void **>(&b->buf), bytes);
+        if (e != hipSuccess)
+            return fail(e == hipErrorOutOfMemory ? SM_ENOMEM : SM_EDEVICE,
+                        std::string("batch plan buffer: ") + hipGetErrorString(e));
+        *h = host.data();
+        *dv = b->buf;
+        return (int)SM_OK;
     };
-    if (!bitems.empty()) {
-        BmArgs a{};
-        a.items = reinterpret_cast<const BmItem *>(u.dev + o_bitems);
-        a.nitems = bitems.size();
-        a.queries = reinterpret_cast<const BmQuery *>(u.dev + o_bq);
-        a.outs = reinterpret_cast<const uint32_t *>(u.dev + o_bout);
-        a.steps = reinterpret_cast<const uint32_t *>(u.dev + o_bsteps);
-        a.counts = counts;
-        a.bm_words = (uint32_t)round_up(bm_words, 4);
-        const uint32_t lds = a.bm_words * 4 + 256 + kBmQChunk * sizeof(uint32_t);
-        const uint64_t per_cu = std::max<uint64_t>(1, kBmMaxLds / lds);
-        const uint64_t grid = std::min<uint64_t>(bitems.size(), (uint64_t)std::max(d->cus, 1) * std::min<uint64_t>(per_cu, 2));
-        hipError_t e = launch_batch_bitmap(a, (unsigned)grid, lds, s);
+    int rc = nq > 0 ? plan_batch(*d, q, nq, texts, nt, params, alloc, &b->lp) : SM_OK;
+    if (rc == SM_OK && b->buf) {
+        hipError_t e = hipMemcpy(b->buf, host.data(), b->lp.bytes, hipMemcpyHostToDevice);
         if (e != hipSuccess)
-            return bail(SM_EDEVICE, std::string("bitmap batch launch: ") + hipGetErrorString(e));
+            rc = fail(SM_EDEVICE, std::string("batch plan upload: ") + hipGetErrorString(e));
     }
-    if (!tile_chunk.empty()) {
-        BatchArgs a{};
-        a.chunks = reinterpret_cast<const BatchChunk *>(u.dev + o_items);
-        a.tile_chunk = reinterpret_cast<const uint32_t *>(u.dev + o_tchunk);
-        a.ntiles = tile_chunk.size();
-        a.queries = reinterpret_cast<const BatchQuery *>(u.dev + o_queries);
-        a.steps = reinterpret_cast<const uint64_t *>(u.dev + o_steps);
-        a.counts = counts;
-        a.halo_max = halo_max;
-        a.chunk_log2 = kChunkLog2;
-        const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(a.ntiles, 1ull << kChunkLog2), target));
-        hipError_t e = launch_batch_staged(a, cpl, (unsigned)grid, s);
-        if (e != hipSuccess)
-            return bail(SM_EDEVICE, std::string("batch launch: ") + hipGetErrorString(e));
+    if (rc < 0) {
+        if (b->buf)
+            (void)hipFree(b->buf);
+        delete b;
+        return rc;
     }
-    for (size_t i = 0; i < longq.size(); ++i) {
-        const PlanQuery &pq = longq[i];
-        Tune tu{(int)std::min<uint64_t>((uint64_t)rdef, pq.m), 1, wpc, (int)kChunkLog2};
-        int rc = launch_count(*d, make_view(texts[pq.text].t, texts[pq.text].n), pq.m,
-                              reinterpret_cast<const uint64_t *>(u.dev + o_steps) + long_steps_off[i], tu,
-                              counts + pq.idx, nullptr, nullptr, s);
-        if (rc < 0) {
-            std::string msg = g_err;
-            return bail(rc, msg);
-        }
-    }
-    return ring_commit(*d, u, s);
+    *out = b;
+    return SM_OK;
+}
+
+int32_t sm_batch_run(const sm_batch *b, uint64_t *counts_dev, void *stream)
+{
+    g_err.clear();
+    if (!b)
+        return fail(SM_EINVAL, "batch plan is NULL");
+    if (b->lp.nq == 0)
+        return SM_OK;
+    if (!counts_dev)
+        return fail(SM_EINVAL, "counts_dev is NULL");
+    int cur = -1;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != b->dev)
+        return fail(SM_EINVAL, "batch plan belongs to another device");
+    Dev *d;
+    SM_TRY(get_dev(&d));
+    return launch_plan(*d, b->lp, b->buf, reinterpret_cast<unsigned long long *>(counts_dev),
+                       reinterpret_cast<hipStream_t>(stream));
+}
+
+int32_t sm_batch_destroy(sm_batch *b)
+{
+    g_err.clear();
+    if (!b)
+        return SM_OK;
+    if (b->buf)
+        HIP_TRY(hipFree(b->buf));
+    delete b;
+    return SM_OK;
 }
 
 }  // extern "C"

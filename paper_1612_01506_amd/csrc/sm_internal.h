@@ -125,5 +125,7 @@ hipError_t launch_hist(const TextView &tv, unsigned long long *hist, unsigned gr
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_batch_staged(const BatchArgs &a, int cpl, unsigned grid, hipStream_t s);
 hipError_t launch_batch_bitmap(const BmArgs &a, unsigned grid, uint32_t lds_bytes, hipStream_t s);
+// Sets the dynamic-LDS limits of all kernels on the current device.
+hipError_t prime_kernel_attrs();
 
 }  // namespace smk

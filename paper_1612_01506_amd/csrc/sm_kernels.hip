@@ -1070,3 +1070,45 @@ hipError_t launch_batch_bitmap(const BmArgs &a, unsigned grid, uint32_t lds_byte
     return hipGetLastError();
 }
 }  // namespace smk
+
+namespace smk {
+// Raises the dynamic-LDS limit of every kernel that takes more than the
+// default.  Called once per device at initialisation, so that later launches
+// (possibly under stream capture) make no attribute calls.
+template <typename K>
+static hipError_t lds_attr(K *k, int bytes)
+{
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+template <int CPL>
+static hipError_t prime_cpl()
+{
+    const void *ks[] = {reinterpret_cast<const void *>(&k_count_staged<CPL, 1>),
+                        reinterpret_cast<const void *>(&k_count_staged<CPL, 2>),
+                        reinterpret_cast<const void *>(&k_count_staged<CPL, 3>),
+                        reinterpret_cast<const void *>(&k_count_staged<CPL, 4>),
+                        reinterpret_cast<const void *>(&k_count_staged<CPL, 5>),
+                        reinterpret_cast<const void *>(&k_count_staged<CPL, 6>),
+                        reinterpret_cast<const void *>(&k_count_staged<CPL, 7>),
+                        reinterpret_cast<const void *>(&k_count_staged<CPL, 8>),
+                        reinterpret_cast<const void *>(&k_batch_staged<CPL>)};
+    for (const void *k : ks) {
+        hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t prime_kernel_attrs()
+{
+    hipError_t e;
+    if ((e = prime_cpl<1>()) != hipSuccess || (e = prime_cpl<2>()) != hipSuccess ||
+        (e = prime_cpl<4>()) != hipSuccess)
+        return e;
+    if ((e = lds_attr(&k_report_write, (int)kMaxLds)) != hipSuccess)
+        return e;
+    return lds_attr(&k_batch_bitmap, (int)kBmMaxLds);
+}
+}  // namespace smk

@@ -59,6 +59,13 @@ def test_validation_before_any_device_call():
     assert lib.sm_report(p.ctypes.data, 3, None, 0, None, None, 5) == _lib.SM_EINVAL
     # batch: NULL arrays
     assert lib.sm_count_batch(None, 1, None, 0, None, None, None) == _lib.SM_EINVAL
+    # batch plans: NULL arrays, NULL output handle, NULL plan
+    h = ctypes.c_void_p(1)
+    assert lib.sm_batch_create(None, 1, None, 0, None, ctypes.byref(h)) == _lib.SM_EINVAL
+    assert h.value is None
+    assert lib.sm_batch_create(None, 0, None, 0, None, None) == _lib.SM_EINVAL
+    assert "NULL" in _err(lib.sm_batch_run(None, None, None))
+    assert lib.sm_batch_destroy(None) == _lib.SM_OK
     # histogram: NULL output
     assert lib.sm_histogram(None, 0, None, None) == _lib.SM_EINVAL
 

@@ -448,3 +448,73 @@ def test_serving_alone_equals_mix(dev):
         if r.report:
             pos = r.positions.cpu().numpy() if hasattr(r.positions, "cpu") else r.positions
             assert np.array_equal(pos.astype(np.uint64), oracle.report(r.pattern, texts_h[r.text_id]))
+
+
+def test_batch_plan_graph_replay(dev):
+    """A planned batch equals the one-shot batch and the oracle, eagerly and replayed from a graph.
+
+    Between replays the program runs its own eager searches and rewrites the
+    texts (same lengths, same alphabets); every replay is checked against the
+    oracle on the texts as they are then.
+    """
+    g = np.random.default_rng(4242)
+    spec = [(60_000, 4, True), (700_001, 95, True), (33, 2, False), (250_000, 256, False), (90_001, 20, True)]
+    texts_h = [rand_text(n, s, 10 + i) for i, (n, s, _) in enumerate(spec)]
+    bufs = [to_dev(t, dev, (5 * i) % 16) for i, t in enumerate(texts_h)]
+    texts = [sm.Text(b) if hist else b for b, (_, _, hist) in zip(bufs, spec)]
+    queries = []
+    for k in range(500):
+        ti = int(g.integers(0, len(spec)))
+        m = int(synth.loguniform_ints(1, 3000, 1, g)[0])
+        queries.append((ti, pick_pattern(texts_h[ti], m, g, planted=g.random() < 0.7)))
+    queries.append((3, bytes(texts_h[3][100:100 + 40_000])))   # long: global kernel
+    queries.append((2, b"0" * 40))                              # m > n
+    want = [oracle.count(p, texts_h[ti]) for ti, p in queries]
+
+    plan = sm.BatchPlan(texts, queries)
+    out = torch.full((len(queries) + 3,), -7, dtype=torch.int64, device=dev)
+    assert plan.run(out).cpu().tolist() == want
+    assert out[len(queries):].cpu().tolist() == [-7] * 3      # only nq entries written
+    assert sm.count_batch(texts, queries).cpu().tolist() == want
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.run(out)                                           # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.run(out)
+    for rep in range(4):
+        if rep >= 2:                                            # new contents, same lengths and alphabets
+            for i, (n, sg, _) in enumerate(spec):
+                texts_h[i] = rand_text(n, sg, 1000 * rep + i)
+                bufs[i].copy_(torch.from_numpy(texts_h[i]))
+            want = [oracle.count(p, texts_h[ti]) for ti, p in queries]
+        out.fill_(-1)
+        graph.replay()
+        torch.cuda.synchronize()
+        assert out[:len(queries)].cpu().tolist() == want, f"replay {rep}"
+        # the program's own eager work between replays
+        ti, p = queries[rep]
+        assert sm.count(bufs[ti], p) == want[rep]
+        assert sm.count_batch(texts, queries[:40]).cpu().tolist() == want[:40]
+    plan.close()
+    plan.close()
+    with pytest.raises(ValueError):
+        plan.run(out)
+
+
+def test_batch_plan_empty_and_errors(dev):
+    td = to_dev(np.frombuffer(b"abcabc", dtype=np.uint8), dev)
+    plan = sm.BatchPlan([td], [])
+    out = torch.zeros(1, dtype=torch.int64, device=dev)
+    assert plan.run(out).numel() == 0
+    plan.close()
+    with pytest.raises(sm.SmError, match="query 1"):
+        sm.BatchPlan([td], [(0, b"a"), (2, b"b")])
+    with sm.BatchPlan([td], [(0, b"abc"), (0, b"c"), (0, b"abcabcx")]) as plan:
+        assert plan.run().cpu().tolist() == [2, 2, 0]
+        with pytest.raises(ValueError):
+            plan.run(torch.zeros(2, dtype=torch.int64, device=dev))
