@@ -97,8 +97,13 @@ def run_zipf(args):
 
     state = {}
 
+    hev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+
     def step(timed: bool):
-        hist = sm.histogram(t_dev).cpu().numpy().view(np.uint64)                  # symbol frequencies
+        hev[0].record(stream)
+        hd = sm.histogram(t_dev)
+        hev[1].record(stream)
+        hist = hd.cpu().numpy().view(np.uint64)                                    # symbol frequencies
         ps = sm.Patterns(patterns, "freq", hist)                  # compare orders pi + step tables -> HBM
         counts = torch.zeros(len(patterns), dtype=torch.int64, device=dev)
         for i in range(len(patterns)):
@@ -114,6 +119,7 @@ def run_zipf(args):
         state["plist"] = [posbuf[k, :min(int(tot), cap)] for k, tot in enumerate(state["totals"])]
         if timed:
             state.setdefault("kern_ms", []).extend(a.elapsed_time(b) for a, b in ev)
+            state.setdefault("hist_ms", []).append(hev[0].elapsed_time(hev[1]))
 
     for _ in range(args.warmup):
         step(False)
@@ -192,6 +198,9 @@ def run_zipf(args):
             "kernel": "k_count_staged<2,2> (8 KiB tiles, peel 2)", "avg_launch_us": round(avg_ms * 1e3, 2),
             "algorithmic_bytes_per_launch": n,
         },
+        "histogram": {"avg_us": round(float(np.mean(state["hist_ms"])) * 1e3, 1),
+                      "GBps": round(n / (float(np.mean(state["hist_ms"])) * 1e-3) / 1e9, 1),
+                      "kernel": "k_hist (per-lane LDS bin copies)"},
         "cpu_baseline": {
             "value": round(cpu_bytes / cpu_t / 1e9, 3) if cpu_t else None, "unit": "GB/s",
             "cores": ncores, "kind": "oracle",
@@ -210,6 +219,34 @@ def _timed(fn, reps=1):
         out = fn()
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / reps, out
+
+
+def _plan_times(sm, texts, queries, out_len, reps, want):
+    """(create seconds, eager run seconds, graph replay seconds) of a BatchPlan; counts checked."""
+    import torch
+
+    t0 = time.perf_counter()
+    plan = sm.BatchPlan(texts, queries)
+    t_create = time.perf_counter() - t0
+    out = torch.empty(out_len, dtype=torch.int64, device=want.device)
+    plan.run(out)
+    torch.cuda.synchronize()
+    assert torch.equal(out[:len(queries)], want), "plan counts differ from the one-shot batch"
+    t_run, _ = _timed(lambda: plan.run(out), reps)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.run(out)
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.run(out)
+    out.fill_(-1)
+    t_graph, _ = _timed(g.replay, reps)
+    assert torch.equal(out[:len(queries)], want), "graph replay counts differ"
+    del g
+    plan.close()
+    return t_create, t_run, t_graph
 
 
 def run_batched(args):
@@ -259,6 +296,7 @@ def run_batched(args):
     g = synth.rng(4, 99)
     for i in g.choice(len(pats), size=args.oracle_samples, replace=False):
         assert oracle.count(pats[i], t_host) == cb[i], ("oracle", i)
+    pc, pr, pg = _plan_times(sm, [text], queries, len(pats), max(args.steps, 3), torch.from_numpy(cb).to(dev))
     mean_m = float(np.mean([len(p) for p in pats]))
     lines.append({
         "metric": "batched searches/s", "value": round(len(pats) / tb, 1), "unit": "searches/s",
@@ -269,6 +307,7 @@ def run_batched(args):
                                f"(mean {mean_m:.0f}), {n}-byte Zipf(1.0) sigma=95 text",
                    "sequential_s": round(ts, 4), "batched_s": round(tb, 4),
                    "batched_host_enqueue_s": round(min(enq), 4),
+                   "plan_create_s": round(pc, 4), "plan_run_s": round(pr, 4), "plan_graph_replay_s": round(pg, 4),
                    "speedup_vs_sequential": round(ts / tb, 2),
                    "sequential_text_GBps": round(len(pats) * n / ts / 1e9, 1),
                    "logical_text_GBps_batched": round(len(pats) * n / tb / 1e9, 1),
@@ -288,7 +327,11 @@ def run_batched(args):
         views.append(v)
         off += th.size
     q2 = [(i, p) for i, p in enumerate(pats2)]
-    packed = sm.PackedTexts(big, [v.data_ptr() - big.data_ptr() for v in views], [v.numel() for v in views])
+    # resident texts keep their symbol histograms (computed once, outside the timed region)
+    t_h = time.perf_counter()
+    hists = torch.stack([sm.histogram(v) for v in views]).cpu().numpy().view(np.uint64)
+    hist_s = time.perf_counter() - t_h
+    packed = sm.PackedTexts(big, [v.data_ptr() - big.data_ptr() for v in views], [v.numel() for v in views], hists)
 
     def sequential2():
         ps = sm.Patterns(pats2)
@@ -315,6 +358,7 @@ def run_batched(args):
     cb2 = cb2.cpu().numpy()
     for i in range(0, len(pats2), max(1, len(pats2) // 64)):
         assert oracle.count(pats2[i], texts_h[i]) == cb2[i], ("oracle many", i)
+    pc2, pr2, pg2 = _plan_times(sm, packed, q2, len(pats2), max(args.steps, 10), torch.from_numpy(cb2).to(dev))
     lines.append({
         "metric": "batched searches/s", "value": round(len(pats2) / tb2, 1), "unit": "searches/s",
         "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": round(tb2 * 1e3, 3),
@@ -324,6 +368,10 @@ def run_batched(args):
                                "lengths log-uniform [4 KiB, 4 MiB], m log-uniform [4,256]",
                    "sequential_s": round(ts2, 4), "batched_s": round(tb2, 4),
                    "batched_host_enqueue_s": round(min(enq2), 4),
+                   "plan_create_s": round(pc2, 4), "plan_run_s": round(pr2, 5),
+                   "plan_graph_replay_s": round(pg2, 5),
+                   "text_GBps_plan_replay": round(total / pg2 / 1e9, 1),
+                   "histograms_once_s": round(hist_s, 4),
                    "speedup_vs_sequential": round(ts2 / tb2, 2),
                    "text_GBps_batched": round(total / tb2 / 1e9, 1)},
     })

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <deque>
 #include <functional>
+#include <thread>
 #include <memory>
 #include <mutex>
 #include <numeric>
@@ -95,6 +96,8 @@ int get_dev(Dev **out)
             d->rsize = kRingBytes;
             e = hipHostMalloc(reinterpret_cast<void **>(&d->rh), d->rsize, hipHostMallocDefault);
         }
+        if (e == hipSuccess)  // touch every page once now: first writes to fresh pinned pages are slow
+            std::memset(d->rh, 0, d->rsize);
         if (e == hipSuccess)
             e = hipMalloc(reinterpret_cast<void **>(&d->rd), d->rsize);
         if (e == hipSuccess)
@@ -297,6 +300,53 @@ struct FreqRanks {
             o[cnt[rank[p[j]]]++] = (int32_t)j;
     }
 };
+
+// The same order computed from the pattern's own symbols only: rank the
+// distinct symbols of p by frequency (equal frequencies share a rank), then
+// the same stable counting sort.  O(m + k log k) for k distinct symbols, so
+// it is the cheaper choice when only a few patterns use a histogram.
+void order_freq_sparse(const uint64_t *hist, const uint8_t *p, uint64_t m, int32_t *o)
+{
+    uint16_t rank[256];
+    std::fill(rank, rank + 256, (uint16_t)0xFFFF);
+    uint64_t key[256];  // frequency in the high bits, symbol in the low 8 when it fits
+    uint8_t sym[256];
+    uint32_t k = 0;
+    uint64_t hmax = 0;
+    for (uint64_t j = 0; j < m; ++j)
+        if (rank[p[j]] == 0xFFFF) {
+            rank[p[j]] = 0;
+            sym[k++] = p[j];
+            hmax = std::max(hmax, hist[p[j]]);
+        }
+    if (hmax < (1ull << 56)) {
+        for (uint32_t i = 0; i < k; ++i)
+            key[i] = (hist[sym[i]] << 8) | sym[i];
+        std::sort(key, key + k);
+        for (uint32_t i = 0; i < k; ++i)
+            sym[i] = (uint8_t)(key[i] & 0xFFu);
+    } else {
+        std::sort(sym, sym + k, [&](uint8_t a, uint8_t b) { return hist[a] < hist[b]; });
+    }
+    uint32_t r = 0;
+    for (uint32_t i = 0; i < k; ++i) {
+        if (i > 0 && hist[sym[i]] != hist[sym[i - 1]])
+            ++r;
+        rank[sym[i]] = (uint16_t)r;
+    }
+    const uint32_t nr = k ? r + 1 : 0;
+    uint32_t cnt[257];
+    std::fill(cnt, cnt + nr + 1, 0u);
+    for (uint64_t j = 0; j < m; ++j)
+        cnt[rank[p[j]] + 1]++;
+    for (uint32_t i = 0; i < nr; ++i)
+        cnt[i + 1] += cnt[i];
+    for (uint64_t j = 0; j < m; ++j)
+        o[cnt[rank[p[j]]]++] = (int32_t)j;
+}
+
+// Patterns of at least this total length against one histogram share a FreqRanks.
+constexpr uint64_t kRanksMinBytes = 1024;
 
 // Section 2.4, 1-based listing 1, m, 4, 7, ..., 3, 6, ..., 2, 5, ...: position 1,
 // position m, then the residue chains 1, 0, 2 (mod 3) upward from 4, 3, 2,
@@ -634,6 +684,49 @@ struct LaunchPlan {
     std::vector<Long> longs;
 };
 
+// Runs body(begin, end) over [0, n) split into contiguous ranges, on up to
+// kPlanThreads threads when n is large enough to pay for them.
+constexpr size_t kPlanThreads = 8, kPlanPerThread = 1024;
+template <typename F>
+void parallel_for(size_t n, const F &body)
+{
+    const size_t hw = std::max<size_t>(1, std::thread::hardware_concurrency());
+    const size_t nth = std::min({kPlanThreads, hw, std::max<size_t>(1, n / kPlanPerThread)});
+    if (nth <= 1) {
+        body(0, n);
+        return;
+    }
+    std::vector<std::thread> pool;
+    const size_t per = (n + nth - 1) / nth;
+    for (size_t t = 1; t < nth; ++t) {
+        const size_t k0 = std::min(n, t * per), k1 = std::min(n, k0 + per);
+        pool.emplace_back([&body, k0, k1] { body(k0, k1); });
+    }
+    body(0, std::min(n, per));
+    for (auto &th : pool)
+        th.join();
+}
+
+// Peel factor from the text's symbol frequencies.  Section 3 finds r = 2
+// best for English, 3 for protein and 5 for DNA; this picks the smallest r
+// after which the expected number of the W starts of a vector still alive
+// (W times the product of the first r compared symbols' frequencies, in the
+// query's compare order) is at most one, capped at 5 and at m.  That gives
+// 2, 3 and 5 for large, protein-sized and DNA alphabets.  Speed only.
+constexpr uint32_t kModelPeelMax = 5;
+uint32_t model_peel(const uint8_t *p, uint64_t m, const int32_t *order, const uint64_t *hist, double hsum, double W)
+{
+    const uint32_t cap = (uint32_t)std::min<uint64_t>(m, kModelPeelMax);
+    double e = W;
+    for (uint32_t k = 1; k <= cap; ++k) {
+        const uint64_t j = order ? (uint64_t)order[k - 1] : k - 1;
+        e *= hsum > 0 ? (double)hist[p[j]] / hsum : 0.0;
+        if (e <= 1.0)
+            return k;
+    }
+    return cap;
+}
+
 using AllocFn = std::function<int(size_t, uint8_t **, uint8_t **)>;
 
 // Plans a validated batch: classifies the queries (bitmap / byte tiles /
@@ -647,39 +740,51 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
                         ? params->tile_kib / 4
                         : 2;
     const uint64_t T = 4096ull * cpl;
-    const int rdef = (params && params->peel > 0) ? std::min<int>(params->peel, (int)kMaxPeel) : 2;
+    const bool peel_given = params && params->peel > 0;
+    const int rdef = peel_given ? std::min<int>(params->peel, (int)kMaxPeel) : 2;
     const int wpc = (params && params->wgs_per_cu > 0) ? std::min(params->wgs_per_cu, 32) : 6;
     const uint64_t target = (uint64_t)std::max(d.cus, 1) * (uint64_t)wpc;
     // two LDS tile buffers of T + halo and the query counters must fit
     const uint64_t max_halo = (kMaxLds - kQChunk * sizeof(uint32_t)) / 2 - T;
 
-    // ---- per-text alphabets (bitmap mode needs the histogram)
-    std::vector<std::vector<uint8_t>> smaps(nt);
-    std::vector<uint32_t> nslots(nt, 0);
-    std::vector<uint64_t> nbm(nt, 0);
-    for (uint64_t i = 0; i < nt; ++i) {
-        if (!texts[i].hist)
-            continue;
-        smaps[i].assign(256, 0xFF);
-        for (int b = 0; b < 256; ++b)
-            if (texts[i].hist[b])
-                smaps[i][b] = (uint8_t)nslots[i]++;
-    }
+    // ---- per-text alphabets (bitmap mode needs the histogram and kBmMinQueries queries)
     auto bm_wps = [](uint64_t m_max) { return (uint32_t)round_up(258 + ceil_div(m_max, 32), 4); };
     auto bm_lds = [&](uint32_t slots, uint32_t wps) {
         return (uint64_t)slots * wps * 4 + 256 + kBmQChunk * sizeof(uint32_t);
     };
     auto bm_bucket = [](uint64_t m) -> uint32_t { return m <= 256 ? 256 : (m <= 1024 ? 1024 : 4096); };
-    // a text qualifies if its alphabet fits next to the largest bucket it needs
-    std::vector<uint8_t> text_bm(nt, 0);
+    std::vector<uint64_t> nbm(nt, 0);
     for (uint64_t i = 0; i < nq; ++i) {
         const uint32_t t = q[i].text_id;
-        if (texts[t].hist && q[i].m <= texts[t].n && q[i].m <= 4096 && nslots[t] > 0 &&
+        if (texts[t].hist && q[i].m <= texts[t].n && q[i].m <= 4096)
+            nbm[t]++;
+    }
+    std::vector<std::vector<uint8_t>> smaps(nt);  // symbol -> bitmap slot, texts with enough queries only
+    std::vector<uint32_t> nslots(nt, 0);
+    for (uint64_t t = 0; t < nt; ++t) {
+        if (nbm[t] < kBmMinQueries)
+            continue;
+        smaps[t].assign(256, 0xFF);
+        for (int b = 0; b < 256; ++b)
+            if (texts[t].hist[b])
+                smaps[t][b] = (uint8_t)nslots[t]++;
+        nbm[t] = 0;
+    }
+    // a text qualifies if enough of its queries fit the LDS next to their bucket's bitmaps
+    for (uint64_t i = 0; i < nq; ++i) {
+        const uint32_t t = q[i].text_id;
+        if (!smaps[t].empty() && q[i].m <= texts[t].n && q[i].m <= 4096 && nslots[t] > 0 &&
             bm_lds(nslots[t], bm_wps(bm_bucket(q[i].m))) <= kBmMaxLds)
             nbm[t]++;
     }
-    for (uint64_t t = 0; t < nt; ++t)
-        text_bm[t] = nbm[t] >= kBmMinQueries;
+    std::vector<uint8_t> text_bm(nt, 0);
+    std::vector<uint32_t> smap_slot(nt, 0);
+    uint32_t n_smaps = 0;
+    for (uint64_t t = 0; t < nt; ++t) {
+        text_bm[t] = !smaps[t].empty() && nbm[t] >= kBmMinQueries;
+        if (text_bm[t])
+            smap_slot[t] = n_smaps++;
+    }
 
     // ---- classify queries
     std::vector<PlanQuery> staged, longq, bmq;
@@ -800,7 +905,7 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
     const size_t o_bq = o_bitems + round_up(bitems.size() * sizeof(BmItem), 256);
     const size_t o_bout = o_bq + round_up(bmq.size() * sizeof(BmQuery), 256);
     const size_t o_smap = o_bout + round_up(bmq.size() * sizeof(uint32_t), 256);
-    const size_t o_bsteps = o_smap + round_up(nt * 256, 256);
+    const size_t o_bsteps = o_smap + round_up((uint64_t)n_smaps * 256, 256);
     if (total_bm_steps >= (1ull << 32))
         return fail(SM_EINVAL, "batch too large: pattern bytes in bitmap mode exceed 2^32");
     const size_t bytes = o_bsteps + round_up(total_bm_steps * sizeof(uint32_t), 256);
@@ -811,83 +916,135 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
     std::copy(tile_chunk.begin(), tile_chunk.end(), reinterpret_cast<uint32_t *>(uhost + o_tchunk));
     BatchQuery *hq = reinterpret_cast<BatchQuery *>(uhost + o_queries);
     uint64_t *hs = reinterpret_cast<uint64_t *>(uhost + o_steps);
-    uint64_t soff = 0;
-    std::vector<int32_t> ord;
-    std::vector<uint32_t> cnt;
-    std::vector<std::unique_ptr<FreqRanks>> ranks(nt);
-    auto order_of = [&](uint64_t qi) -> const int32_t * {
-        const sm_query &Q = q[qi];
-        if (Q.order)
-            return Q.order;
-        ord.resize(Q.m);
-        if (texts[Q.text_id].hist) {
-            if (!ranks[Q.text_id])
-                ranks[Q.text_id].reset(new FreqRanks(texts[Q.text_id].hist));
-            ranks[Q.text_id]->order(Q.p, Q.m, ord.data(), cnt);
-        } else {
-            order_ltr(Q.m, ord.data());
-        }
-        return ord.data();
-    };
-    auto emit_steps = [&](uint64_t qi) -> uint64_t {
-        const sm_query &Q = q[qi];
-        build_steps(Q.p, Q.m, order_of(qi), hs + soff);
-        const uint64_t at = soff;
-        soff += Q.m + kStepPad;
-        return at;
-    };
-    for (size_t i = 0; i < staged.size(); ++i) {
-        const PlanQuery &pq = staged[i];
-        const sm_text &tx = texts[pq.text];
-        BatchQuery bq{};
-        bq.steps_off = emit_steps(pq.idx);
-        bq.last = (reinterpret_cast<uintptr_t>(tx.t) & 15u) + tx.n - pq.m;
-        bq.m = (uint32_t)pq.m;
-        bq.r = (uint32_t)std::min<uint64_t>((uint64_t)rdef, pq.m);
-        bq.out = (uint32_t)pq.idx;
-        hq[i] = bq;
-    }
-    std::vector<uint64_t> long_steps_off;
-    for (auto &pq : longq)
-        long_steps_off.push_back(emit_steps(pq.idx));
-    // bitmap part
     BmItem *hbi = reinterpret_cast<BmItem *>(uhost + o_bitems);
     BmQuery *hbq = reinterpret_cast<BmQuery *>(uhost + o_bq);
     uint32_t *hbout = reinterpret_cast<uint32_t *>(uhost + o_bout);
     uint8_t *hsm = uhost + o_smap;
     uint32_t *hbs = reinterpret_cast<uint32_t *>(uhost + o_bsteps);
     for (uint64_t t = 0; t < nt; ++t)
-        if (!smaps[t].empty())
-            std::copy(smaps[t].begin(), smaps[t].end(), hsm + 256 * t);
-    uint64_t bsoff = 0;
-    for (auto &c : bchunks) {
-        const uint32_t wps = bm_wps(c.m_max);
-        for (uint32_t i = c.q0; i < c.q1; ++i) {
-            const PlanQuery &pq = bmq[i];
-            const sm_query &Q = q[pq.idx];
-            const int32_t *o = order_of(pq.idx);
-            for (uint64_t l = 0; l < Q.m; ++l) {
-                const uint32_t j = (uint32_t)o[l];
-                const uint32_t slot = smaps[pq.text][Q.p[j]];
-                hbs[bsoff + l] = ((slot * wps + (j >> 5)) << 5) | (j & 31u);
-            }
-            BmQuery bq{};
-            bq.e0 = hbs[bsoff];
-            bq.e1 = Q.m > 1 ? hbs[bsoff + 1] : hbs[bsoff];
-            bq.steps_off = (uint32_t)bsoff;
-            bq.mr = (uint32_t)pq.m | ((uint32_t)std::min<uint64_t>((uint64_t)rdef, pq.m) << 24);
-            hbq[i] = bq;
-            hbout[i] = (uint32_t)pq.idx;
-            bsoff += Q.m;
+        if (text_bm[t])
+            std::copy(smaps[t].begin(), smaps[t].end(), hsm + 256 * smap_slot[t]);
+
+    // ---- shared per-text state, prepared before the per-query work is split over threads
+    std::vector<std::unique_ptr<FreqRanks>> ranks(nt);
+    std::vector<uint64_t> text_bytes(nt, 0);  // pattern bytes per text needing a frequency order
+    for (uint64_t i = 0; i < nq; ++i)
+        if (!q[i].order && texts[q[i].text_id].hist)
+            text_bytes[q[i].text_id] += q[i].m;
+    std::vector<double> hsum(nt, 0.0);  // histogram totals for the peel model
+    for (uint64_t t = 0; t < nt; ++t) {
+        if (!texts[t].hist)
+            continue;
+        if (text_bytes[t] >= kRanksMinBytes)
+            ranks[t].reset(new FreqRanks(texts[t].hist));
+        if (!peel_given) {
+            uint64_t sum = 0;
+            for (int b = 0; b < 256; ++b)
+                sum += texts[t].hist[b];
+            hsum[t] = (double)sum;
         }
     }
+    // step-table offsets: staged queries, then long ones; bitmap steps separately
+    const size_t n_st = staged.size(), n_lg = longq.size(), n_bm = bmq.size();
+    std::vector<uint64_t> st_off(n_st + n_lg), bm_off(n_bm);
+    std::vector<uint32_t> bm_wps_of(n_bm);
+    {
+        uint64_t acc = 0;
+        for (size_t i = 0; i < n_st + n_lg; ++i) {
+            st_off[i] = acc;
+            acc += (i < n_st ? staged[i].m : longq[i - n_st].m) + kStepPad;
+        }
+        acc = 0;
+        for (size_t i = 0; i < n_bm; ++i) {
+            bm_off[i] = acc;
+            acc += bmq[i].m;
+        }
+        for (auto &c : bchunks)
+            for (uint32_t i = c.q0; i < c.q1; ++i)
+                bm_wps_of[i] = bm_wps(c.m_max);
+    }
+    std::vector<uint32_t> long_peel(n_lg);
+
+    // ---- per-query tables: compare order, step entries, peel (independent per query)
+    struct Scratch {
+        std::vector<int32_t> ord;
+        std::vector<uint32_t> cnt;
+    };
+    auto order_of = [&](uint64_t qi, Scratch &w) -> const int32_t * {
+        const sm_query &Q = q[qi];
+        if (Q.order)
+            return Q.order;
+        w.ord.resize(Q.m);
+        const uint64_t *h = texts[Q.text_id].hist;
+        if (!h)
+            order_ltr(Q.m, w.ord.data());
+        else if (ranks[Q.text_id])
+            ranks[Q.text_id]->order(Q.p, Q.m, w.ord.data(), w.cnt);
+        else
+            order_freq_sparse(h, Q.p, Q.m, w.ord.data());
+        return w.ord.data();
+    };
+    // peel of a query: the caller's, else the frequency model when the text has a histogram, else 2
+    auto peel_of = [&](uint64_t qi, const int32_t *o, double W) -> uint32_t {
+        const sm_query &Q = q[qi];
+        const uint64_t *h = texts[Q.text_id].hist;
+        if (peel_given || !h)
+            return (uint32_t)std::min<uint64_t>((uint64_t)rdef, Q.m);
+        return model_peel(Q.p, Q.m, o, h, hsum[Q.text_id], W);
+    };
+    auto fill = [&](size_t k, Scratch &w) {
+        if (k < n_st + n_lg) {
+            const PlanQuery &pq = k < n_st ? staged[k] : longq[k - n_st];
+            const sm_query &Q = q[pq.idx];
+            const int32_t *o = order_of(pq.idx, w);
+            build_steps(Q.p, Q.m, o, hs + st_off[k]);
+            const uint32_t r = peel_of(pq.idx, o, (double)kBlock);
+            if (k >= n_st) {
+                long_peel[k - n_st] = r;
+                return;
+            }
+            const sm_text &tx = texts[pq.text];
+            BatchQuery bq{};
+            bq.steps_off = st_off[k];
+            bq.last = (reinterpret_cast<uintptr_t>(tx.t) & 15u) + tx.n - pq.m;
+            bq.m = (uint32_t)pq.m;
+            bq.r = r;
+            bq.out = (uint32_t)pq.idx;
+            hq[k] = bq;
+            return;
+        }
+        const size_t i = k - n_st - n_lg;
+        const PlanQuery &pq = bmq[i];
+        const sm_query &Q = q[pq.idx];
+        const int32_t *o = order_of(pq.idx, w);
+        const uint32_t wps = bm_wps_of[i];
+        uint32_t *e = hbs + bm_off[i];
+        for (uint64_t l = 0; l < Q.m; ++l) {
+            const uint32_t j = (uint32_t)o[l];
+            const uint32_t slot = smaps[pq.text][Q.p[j]];
+            e[l] = ((slot * wps + (j >> 5)) << 5) | (j & 31u);
+        }
+        BmQuery bq{};
+        bq.e0 = e[0];
+        bq.e1 = Q.m > 1 ? e[1] : e[0];
+        bq.steps_off = (uint32_t)bm_off[i];
+        bq.mr = (uint32_t)pq.m | (peel_of(pq.idx, o, (double)kBmT) << 24);
+        hbq[i] = bq;
+        hbout[i] = (uint32_t)pq.idx;
+    };
+    parallel_for(n_st + n_lg + n_bm, [&](size_t k0, size_t k1) {
+        Scratch w;
+        for (size_t k = k0; k < k1; ++k)
+            fill(k, w);
+    });
+    std::vector<uint64_t> long_steps_off(st_off.begin() + n_st, st_off.end());
     {
         size_t k = 0;
         for (auto &c : bchunks) {
             const uint64_t first = reinterpret_cast<uintptr_t>(texts[c.text].t) & 15u;
             const uint64_t ntiles = ceil_div(first + texts[c.text].n - c.m_min + 1, kBmT);
             for (uint64_t t0 = 0; t0 < ntiles; t0 += bspan) {
-                bitems[k].smap = udev + o_smap + 256 * c.text;
+                bitems[k].smap = udev + o_smap + 256 * smap_slot[c.text];
                 ++k;
             }
         }
@@ -920,7 +1077,7 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
         L.m = pq.m;
         L.steps_off = long_steps_off[i];
         L.out = pq.idx;
-        L.tu = Tune{(int)std::min<uint64_t>((uint64_t)rdef, pq.m), 1, wpc, (int)kChunkLog2};
+        L.tu = Tune{(int)long_peel[i], 1, wpc, (int)kChunkLog2};
         lp->longs.push_back(L);
     }
     return SM_OK;
@@ -1054,7 +1211,9 @@ int32_t sm_histogram(const uint8_t *t, uint64_t n, uint64_t *hist_dev, void *str
         return SM_OK;
     const TextView tv = make_view(t, n);
     const uint64_t nchunks = tv.end16 / 16;
-    const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(nchunks, kWG), (uint64_t)d->cus * 4));
+    // two 64 KiB workgroups fit a compute unit's LDS
+    const uint64_t grid =
+        std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(nchunks, kHistWG), (uint64_t)std::max(d->cus, 1) * 2));
     HIP_TRY(launch_hist(tv, h, (unsigned)grid, s));
     return SM_OK;
 }
@@ -1073,8 +1232,12 @@ int32_t sm_order(int32_t kind, const uint8_t *p, uint64_t m, const uint64_t *his
     case SM_ORDER_FREQ: {
         if (!hist_host)
             return fail(SM_EINVAL, "SM_ORDER_FREQ needs hist_host");
-        std::vector<uint32_t> cnt;
-        FreqRanks(hist_host).order(p, m, order_out, cnt);
+        if (m >= kRanksMinBytes) {
+            std::vector<uint32_t> cnt;
+            FreqRanks(hist_host).order(p, m, order_out, cnt);
+        } else {
+            order_freq_sparse(hist_host, p, m, order_out);
+        }
         return SM_OK;
     }
     case SM_ORDER_H: order_fixed_h(m, order_out); return SM_OK;

@@ -9,6 +9,8 @@ namespace smk {
 
 constexpr uint32_t kWG = 256;            // threads per workgroup: four wave64
 constexpr uint32_t kWaves = kWG / 64;
+constexpr uint32_t kHistWG = 1024;        // histogram workgroup: 16 waves sharing 64 lane copies
+constexpr uint32_t kHistLds = 256 * 64 * 4;
 constexpr uint32_t kBlock = 1024;        // starts per wave vector: 64 lanes x 4 dwords x 4 bytes
 constexpr uint32_t kMaxPeel = 8;         // largest peel factor r compiled in
 constexpr uint32_t kStepPad = 8;         // zero entries after every step table (one-ahead loads)

@@ -657,41 +657,75 @@ __global__ __launch_bounds__(kWG) void k_report_write(CountArgs a, uint32_t r, c
 
 // ------------------------------------------------------------- histogram
 
-// Symbol frequencies (Section 2.2): per-wave LDS histograms over 16-byte
-// chunks, then one 64-bit atomicAdd per nonzero bin and workgroup.
-__global__ __launch_bounds__(kWG) void k_hist(TextView tv, unsigned long long *hist)
+// Symbol frequencies (Section 2.2).  Every lane of a wave owns a private copy
+// of the 256 bins, laid out bin-major ([bin][lane], 64 KiB per workgroup), so
+// the 64 lanes of an LDS atomic never share an address and consecutive lanes
+// hit consecutive banks whatever the byte values: a skewed text costs the same
+// as a uniform one.  The 16 waves of the workgroup share the 64 copies.  At
+// the end each bin's 64 copies are summed and added to the global histogram
+// with one 64-bit atomic per nonzero bin and workgroup.
+__device__ __forceinline__ void hist_add16(uint8_t *hb, uint32_t lane4, uint4 v)
 {
-    __shared__ uint32_t h[kWaves][256];
-    const uint32_t tid = threadIdx.x, wave = wave_id();
-    for (uint32_t i = tid; i < kWaves * 256u; i += kWG)
-        (&h[0][0])[i] = 0u;
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const uint32_t bin = (w[i >> 2] >> (8 * (i & 3))) & 0xFFu;
+        atomicAdd(reinterpret_cast<uint32_t *>(hb + (bin << 8) + lane4), 1u);
+    }
+}
+
+__global__ __launch_bounds__(kHistWG) void k_hist(TextView tv, unsigned long long *hist)
+{
+    extern __shared__ __align__(16) uint32_t h[];  // [256][64]
+    const uint32_t tid = threadIdx.x, lane = tid & 63u;
+    for (uint32_t i = tid; i < 256u * 64u / 4u; i += kHistWG)
+        reinterpret_cast<uint4 *>(h)[i] = make_uint4(0, 0, 0, 0);
     __syncthreads();
-    uint32_t *hw = h[wave];
-    const uint64_t lo = tv.first, hi = tv.first + tv.n, nchunks = tv.end16 / 16u;
-    for (uint64_t c = (uint64_t)blockIdx.x * kWG + tid; c < nchunks; c += (uint64_t)gridDim.x * kWG) {
-        const uint64_t u = 16u * c;
-        const uint4 v = *reinterpret_cast<const uint4 *>(tv.base + u);
-        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-        if (u >= lo && u + 16u <= hi) {
-#pragma unroll
-            for (int i = 0; i < 16; ++i)
-                atomicAdd(&hw[(w[i >> 2] >> (8 * (i & 3))) & 0xFFu], 1u);
-        } else {
-#pragma unroll
-            for (int i = 0; i < 16; ++i)
-                if (u + i >= lo && u + i < hi)
-                    atomicAdd(&hw[(w[i >> 2] >> (8 * (i & 3))) & 0xFFu], 1u);
+    uint8_t *hb = reinterpret_cast<uint8_t *>(h);
+    const uint32_t lane4 = lane * 4u;
+    const uint64_t lo = tv.first, hi = tv.first + tv.n;
+    // interior chunks [c_lo, c_hi) hold text bytes only; the (at most two) edge chunks are masked
+    const uint64_t c_lo = (lo + 15u) / 16u, c_hi = hi / 16u;
+    const uint64_t stride = (uint64_t)gridDim.x * kHistWG;
+    uint64_t c = c_lo + (uint64_t)blockIdx.x * kHistWG + tid;
+    for (; c + stride < c_hi; c += 2 * stride) {
+        const uint4 v0 = *reinterpret_cast<const uint4 *>(tv.base + 16u * c);
+        const uint4 v1 = *reinterpret_cast<const uint4 *>(tv.base + 16u * (c + stride));
+        hist_add16(hb, lane4, v0);
+        hist_add16(hb, lane4, v1);
+    }
+    if (c < c_hi)
+        hist_add16(hb, lane4, *reinterpret_cast<const uint4 *>(tv.base + 16u * c));
+    if (blockIdx.x == 0 && tid < 2u) {
+        // edge chunks: the one holding the first bytes (if the text starts mid-chunk) and the one
+        // holding the last bytes (if it ends mid-chunk and is not that same chunk)
+        const uint64_t e_first = lo / 16u, e_last = hi / 16u;
+        const bool has_first = lo % 16u != 0u;
+        const bool has_last = hi % 16u != 0u && !(has_first && e_last == e_first);
+        const uint64_t e = tid == 0u ? e_first : e_last;
+        if (tid == 0u ? has_first : has_last) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(tv.base + 16u * e);
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+            for (int i = 0; i < 16; ++i) {
+                const uint64_t u = 16u * e + (uint64_t)i;
+                if (u >= lo && u < hi) {
+                    const uint32_t bin = (w[i >> 2] >> (8 * (i & 3))) & 0xFFu;
+                    atomicAdd(reinterpret_cast<uint32_t *>(hb + (bin << 8) + lane4), 1u);
+                }
+            }
         }
     }
     __syncthreads();
-    for (uint32_t bin = tid; bin < 256u; bin += kWG) {
-        unsigned long long s = 0;
+    // four threads per bin, 16 copies each (rotated start spreads the banks), then a quad reduction
+    const uint32_t bin = tid >> 2, part = tid & 3u;
+    uint32_t sum = 0;
 #pragma unroll
-        for (uint32_t i = 0; i < kWaves; ++i)
-            s += h[i][bin];
-        if (s)
-            atomicAdd(&hist[bin], s);
-    }
+    for (uint32_t k = 0; k < 16u; ++k)
+        sum += h[bin * 64u + part * 16u + ((k + bin) & 15u)];
+    sum += dpp_mov<0xb1, 0xf>(sum, 0u);  // quad_perm [1,0,3,2]
+    sum += dpp_mov<0x4e, 0xf>(sum, 0u);  // quad_perm [2,3,0,1]
+    if (part == 0u && sum)
+        atomicAdd(&hist[bin], (unsigned long long)sum);
 }
 
 // Zeroes the per-vector counts (16-byte stores; bc is 16-byte aligned) and the group sums.
@@ -1015,7 +1049,7 @@ hipError_t launch_fill_report(uint32_t *bc, uint64_t nblocks, unsigned long long
 
 hipError_t launch_hist(const TextView &tv, unsigned long long *hist, unsigned grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_hist, dim3(grid), dim3(kWG), 0, s, tv, hist);
+    hipLaunchKernelGGL(k_hist, dim3(grid), dim3(kHistWG), kHistLds, s, tv, hist);
     return hipGetLastError();
 }
 
@@ -1108,6 +1142,8 @@ hipError_t prime_kernel_attrs()
         (e = prime_cpl<4>()) != hipSuccess)
         return e;
     if ((e = lds_attr(&k_report_write, (int)kMaxLds)) != hipSuccess)
+        return e;
+    if ((e = lds_attr(&k_hist, (int)kHistLds)) != hipSuccess)
         return e;
     return lds_attr(&k_batch_bitmap, (int)kBmMaxLds);
 }

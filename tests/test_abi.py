@@ -79,8 +79,9 @@ def test_text_must_be_device_memory():
     assert rc in (_lib.SM_EINVAL, _lib.SM_EDEVICE)
 
 
-@pytest.mark.parametrize("m", [1, 2, 3, 7, 64, 1000])
+@pytest.mark.parametrize("m", [1, 2, 3, 7, 64, 1000, 1023, 1024, 5000])
 def test_library_orders_match_oracle(m):
+    """Below 1024 bytes the library ranks the pattern's own symbols, from 1024 on the whole histogram."""
     g = np.random.default_rng(m)
     p = g.integers(0, 256, size=m, dtype=np.uint8).tobytes()
     p = bytes(b if g.random() > 0.2 else 0x20 for b in p)
@@ -105,5 +106,12 @@ def test_freq_order_ties_and_skew():
     h[ord("b")] = 5
     h[ord("c")] = 1
     h[ord("d")] = 9
-    for p in (b"abcdab", b"ddddc", b"babab", b"c", bytes(range(256)), b"dcba" * 50):
+    for p in (b"abcdab", b"ddddc", b"babab", b"c", bytes(range(256)), b"dcba" * 50, b"dcba" * 300,
+              bytes(range(256)) * 5):
         assert sm.order("freq", p, h).tolist() == oracle.order_freq(p, h).tolist()
+    # frequencies too large to pack next to a symbol in 64 bits
+    big = np.full(256, 1 << 60, dtype=np.uint64)
+    big[ord("x")] = (1 << 60) - 1
+    big[ord("y")] = 3
+    for p in (b"axbyxa", b"yyxxaa" * 200):
+        assert sm.order("freq", p, big).tolist() == oracle.order_freq(p, big).tolist()

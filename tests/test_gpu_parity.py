@@ -211,12 +211,22 @@ def test_report_long_pattern(dev):
 
 
 # --------------------------------------------------------------------- histogram
-@pytest.mark.parametrize("n", [0, 1, 15, 16, 17, 4096, 100_001, 5_000_000])
-def test_histogram(dev, n):
+@pytest.mark.parametrize("n", [0, 1, 2, 15, 16, 17, 31, 33, 4096, 100_001, 5_000_000])
+@pytest.mark.parametrize("offset", [0, 1, 7, 15])
+def test_histogram(dev, n, offset):
     t = rand_text(n, 256, n)
-    td = to_dev(t, dev, n % 16)
+    td = to_dev(t, dev, offset)
     h = sm.histogram(td).cpu().numpy()
     assert h.tolist() == np.bincount(t, minlength=256).tolist()
+
+
+def test_histogram_skewed_and_large(dev):
+    """One symbol only (every lane hits the same bin), a Zipf text, and a text spanning many workgroups."""
+    for t in (np.full(3_000_017, 0xFF, dtype=np.uint8),
+              synth.zipf_text(40_000_001, 95, 1.0, family=9, stream=77),
+              rand_text(70_000_003, 4, 5)):
+        td = to_dev(t, dev, 9)
+        assert sm.histogram(td).cpu().numpy().tolist() == np.bincount(t, minlength=256).tolist()
 
 
 # ------------------------------------------------------------------------ batch
