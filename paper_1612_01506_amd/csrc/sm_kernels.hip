@@ -227,6 +227,9 @@ template <typename Text>
 __device__ __forceinline__ void verify_candidates(const uint64_t *steps, uint32_t l, uint32_t m, uint32_t lane,
                                                   uint32_t (&d)[4], const Text &tx)
 {
+    // the first 64 remaining compares, one per lane, serve every candidate
+    const uint32_t idx0 = l + lane;
+    const uint64_t st0 = idx0 < m ? steps[idx0] : 0ull;
     uint32_t cursor = 0;
     while (true) {
         uint32_t best = 0xFFFFFFFFu;
@@ -242,18 +245,15 @@ __device__ __forceinline__ void verify_candidates(const uint64_t *steps, uint32_
         best = wave_min32(best);
         if (best == 0xFFFFFFFFu)
             break;
-        bool ok = true;
-        for (uint32_t b0 = l; b0 < m; b0 += 64u) {
+        bool ok = !__any(idx0 < m && tx.byte(best + step_pos(st0)) != (step_rep(st0) & 0xFFu));
+        for (uint32_t b0 = l + 64u; ok && b0 < m; b0 += 64u) {
             const uint32_t idx = b0 + lane;
             bool bad = false;
             if (idx < m) {
                 const uint64_t st = steps[idx];
                 bad = tx.byte(best + step_pos(st)) != (step_rep(st) & 0xFFu);
             }
-            if (__any(bad)) {
-                ok = false;
-                break;
-            }
+            ok = !__any(bad);
         }
         if (!ok && lane == ((best & 255u) >> 2)) {
             const uint32_t k = best >> 8, dead = 0xFFu << (8 * (best & 3u));
@@ -269,7 +269,8 @@ __device__ __forceinline__ void verify_candidates(const uint64_t *steps, uint32_
 // Compares l..m-1 for a vector still alive after the peel.  The first
 // kTestEach are each followed by the zero test of Algorithm 4; later ones go
 // in groups of kGroup per test, so a lone long survivor does not serialise on
-// one load-compare-test round trip per compare.  Returns false if the vector
+// one load-compare-test round trip per compare; after a group, a handful of
+// survivors facing many more compares are verified one at a time.  Returns false if the vector
 // died; otherwise d is final (byte == 0 exactly at the matching starts).
 template <typename Text>
 __device__ __forceinline__ bool search_tail(const uint64_t *steps, uint32_t l, uint32_t m, uint32_t lane,
@@ -281,8 +282,12 @@ __device__ __forceinline__ bool search_tail(const uint64_t *steps, uint32_t l, u
         if (!any_alive(d))
             return false;
     }
+    // candidates are verified one by one only once a group of compares has
+    // left a few alive: earlier, few survivors are common and mostly die
+    // within the next group, which costs less than the verification loop
+    bool grouped = false;
     while (l < m) {
-        if (m - l >= kVerifyMin) {
+        if (grouped && m - l >= kVerifyMin) {
             const uint32_t alive = wave_sum32(count_alive(d));
             if (alive <= kVerifyMax) {
                 verify_candidates(steps, l, m, lane, d, tx);
@@ -294,6 +299,7 @@ __device__ __forceinline__ bool search_tail(const uint64_t *steps, uint32_t l, u
         for (uint32_t u = 0; u < g; ++u)
             tx.step(ldc(&steps[l + u]), d);
         l += g;
+        grouped = true;
         if (!any_alive(d))
             return false;
     }
