@@ -806,7 +806,9 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
         }
         PlanQuery pq{i, t, q[i].m, 0};
         const uint64_t halo = halo_for(q[i].m);
-        uint64_t b = 64;
+        // queries whose halo is at most T/8 share one chunk per text (one pass over the text, at
+        // most 12.5% extra tile reads); longer ones are bucketed by power-of-two halo
+        uint64_t b = T / 8;
         while (b < halo)
             b <<= 1;
         pq.bucket = (uint32_t)b;
