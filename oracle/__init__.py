@@ -9,6 +9,8 @@ marshals arguments.  Functions and the passages they follow:
 
 * ``count``      -- Algorithm 1 (Section 2.1): starts s in [0, n-m] with t[s:s+m] == p.
 * ``report``     -- the reporting version of Algorithm 1 (Section 2.1).
+* ``count_nonoverlap`` / ``report_nonoverlap`` -- disjoint occurrences by greedy leftmost selection
+  (not defined in the paper; the reading taken for the optional non-overlapping mode).
 * ``hist``       -- symbol frequencies (Section 2.2).
 * ``order_freq`` -- compare order by increasing symbol frequency (Section 2.2), ties by position.
 * ``order_h`` / ``order_hs`` -- the fixed orders pi_h and pi_hs (Section 2.4).
@@ -61,6 +63,8 @@ def _load():
         lib.oracle_order_h.restype = ctypes.c_int
         lib.oracle_order_hs.argtypes = [u8p, u64, u8p]
         lib.oracle_order_hs.restype = ctypes.c_int
+        lib.oracle_report_nonoverlap.argtypes = [u8p, u64, u8p, u64, u8p, u64]
+        lib.oracle_report_nonoverlap.restype = i64
         lib.oracle_alg4_count.argtypes = [u8p, u64, u8p, u64, u8p, u64]
         lib.oracle_alg4_count.restype = i64
         _lib = lib
@@ -110,6 +114,26 @@ def report_full(p, t, cap: int) -> tuple[int, np.ndarray]:
     if r < 0:
         raise ValueError("pattern length must be >= 1")
     return int(r), out[:min(r, cap)]
+
+
+def report_nonoverlap_full(p, t, cap: int) -> tuple[int, np.ndarray]:
+    """(count of disjoint occurrences taken greedily from the left, first min(count, cap) of their starts)."""
+    p, t = _u8(p), _u8(t)
+    out = np.zeros(max(cap, 1), dtype=np.uint64)
+    r = _load().oracle_report_nonoverlap(_ptr(p), p.size, _ptr(t), t.size, out.ctypes.data, cap)
+    if r < 0:
+        raise ValueError("pattern length must be >= 1")
+    return int(r), out[:min(r, cap)]
+
+
+def count_nonoverlap(p, t) -> int:
+    return report_nonoverlap_full(p, t, 0)[0]
+
+
+def report_nonoverlap(p, t, cap: int | None = None) -> np.ndarray:
+    if cap is None:
+        cap = count_nonoverlap(p, t)
+    return report_nonoverlap_full(p, t, cap)[1]
 
 
 def hist(t) -> np.ndarray:

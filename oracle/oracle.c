@@ -72,6 +72,34 @@ int64_t oracle_report(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n
     return (int64_t)count;
 }
 
+/* Non-overlapping occurrences.  The paper counts every start (Algorithm 1
+ * tests each s); a mode that counts only disjoint occurrences is not defined
+ * there.  The reading taken: the greedy leftmost selection.  The scan starts
+ * at s = 0; an occurrence at s is taken and the scan resumes at s + m,
+ * otherwise at s + 1.  Writes the first min(count, cap) taken starts in
+ * increasing order and returns the full count. */
+int64_t oracle_report_nonoverlap(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n,
+                                 uint64_t *pos, uint64_t cap)
+{
+    if (m == 0)
+        return -1;
+    if (m > n)
+        return 0;
+    uint64_t count = 0;
+    uint64_t s = 0;
+    while (s + m <= n) {
+        if (occurs_at(p, m, t, s)) {
+            if (count < cap)
+                pos[count] = s;
+            ++count;
+            s += m;
+        } else {
+            ++s;
+        }
+    }
+    return (int64_t)count;
+}
+
 /* Symbol frequencies (Section 2.2): hist[b] = number of s with t[s] == b. */
 void oracle_hist(const uint8_t *t, uint64_t n, uint64_t *hist)
 {

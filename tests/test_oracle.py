@@ -1,8 +1,8 @@
 """Pins for the CPU oracle: brute force, the Figure 1 worked example, closed forms, invariants.
 
 None of these checks retypes the oracle's own loop: the references are Python
-slicing, the stdlib ``re`` engine (lookahead finds overlapping matches),
-numpy's bincount, closed-form counts of periodic texts and algebraic
+slicing, the stdlib ``re`` engine (lookahead finds overlapping matches, plain
+``finditer`` disjoint ones), ``bytes.count`` (disjoint, leftmost first), numpy's bincount, closed-form counts of periodic texts and algebraic
 invariants (reversal, thread split, compare order and peel factor).
 """
 import itertools
@@ -245,3 +245,52 @@ def test_alg4_block_boundaries():
         t = b"a" * n
         for k in (1, 2, 5):
             assert oracle.alg4_count(b"a" * k, t, None, 3) == max(0, n - k + 1)
+
+
+# ------------------------------------------------------------ non-overlapping mode
+# Pinned against two independent definitions of "disjoint occurrences, leftmost first":
+# Python's bytes.count (documented as non-overlapping) and re.finditer without lookahead.
+def test_nonoverlap_exhaustive_binary_small():
+    pats = [bytes(x) for m in range(1, 5) for x in itertools.product(b"ab", repeat=m)]
+    for n in range(0, 10):
+        for tx in itertools.product(b"ab", repeat=n):
+            t = bytes(tx)
+            for p in pats:
+                want = [mt.start() for mt in re.finditer(re.escape(p), t)]
+                assert oracle.count_nonoverlap(p, t) == t.count(p) == len(want), (p, t)
+                assert oracle.report_nonoverlap(p, t).tolist() == want, (p, t)
+
+
+@settings(max_examples=300, deadline=None)
+@given(t=st.binary(min_size=0, max_size=600), m=st.integers(1, 8), data=st.data())
+def test_nonoverlap_random_vs_bytes_count(t, m, data):
+    alpha = data.draw(st.sampled_from([b"a", b"ab", b"abc", bytes(range(256))]))
+    t = bytes(alpha[b % len(alpha)] for b in t)
+    p = bytes(alpha[b % len(alpha)] for b in data.draw(st.binary(min_size=m, max_size=m)))
+    assert oracle.count_nonoverlap(p, t) == t.count(p)
+    assert oracle.report_nonoverlap(p, t).tolist() == [mt.start() for mt in re.finditer(re.escape(p), t)]
+    # disjoint occurrences are a subset of all occurrences
+    assert set(oracle.report_nonoverlap(p, t).tolist()) <= set(oracle.report(p, t).tolist())
+
+
+@pytest.mark.parametrize("n,k", [(1, 1), (100, 1), (100, 7), (4096, 16), (5000, 256), (300, 300), (299, 300)])
+def test_nonoverlap_unary_closed_form(n, k):
+    """a^n with p = a^k: the greedy takes starts 0, k, 2k, ..., floor(n/k) of them."""
+    t, p = b"a" * n, b"a" * k
+    assert oracle.count_nonoverlap(p, t) == n // k
+    assert oracle.report_nonoverlap(p, t).tolist() == list(range(0, (n // k) * k, k))
+
+
+def test_nonoverlap_periodic_and_cap():
+    # (ab)^q with p = (ab)^j: disjoint occurrences every 2j bytes
+    for q in (1, 5, 64, 1001):
+        for j in (1, 2, 3):
+            t, p = b"ab" * q, b"ab" * j
+            assert oracle.count_nonoverlap(p, t) == q // j
+    # "aaa" in "aaaaaaa": starts 0 and 3 (not 0, 1, ..., 4)
+    assert oracle.report_nonoverlap(b"aaa", b"aaaaaaa").tolist() == [0, 3]
+    total, first = oracle.report_nonoverlap_full(b"a", b"a" * 50, 7)
+    assert total == 50 and first.tolist() == list(range(7))
+    assert oracle.count_nonoverlap(b"abc", b"ab") == 0
+    with pytest.raises(ValueError):
+        oracle.count_nonoverlap(b"", b"abc")

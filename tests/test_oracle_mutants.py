@@ -25,6 +25,7 @@ MUTANTS = {
                                "            found |= simd_compare(t, i, nvalid, p, j);\n            if (found == 0)"),
     "alg4_inverted_exit": ("        if (found == 0)\n            continue;", "        if (found != 0)\n            continue;"),
     "alg4_window_off_by_one": ("if (t[i + k + j] == p[j])", "if (t[i + k + j] == p[j ? j - 1 : 0])"),
+    "nonoverlap_resume_early": ("            s += m;\n", "            s += m - 1 + (m == 1);\n"),
 }
 
 
