@@ -546,6 +546,62 @@ def run_small(args):
     return lines
 
 
+# ------------------------------------------------------------------ nonoverlap
+def run_nonoverlap(args):
+    """Disjoint-occurrence counts (greedy leftmost) beside the all-starts counts: the 1 GiB Zipf text
+    with short substrings (many overlapping occurrences), and a^n (every start an occurrence)."""
+    import torch
+
+    import oracle
+    import paper_1612_01506_amd as sm
+    import synth
+
+    dev = torch.device("cuda:0")
+    n = args.n
+    t_host = synth.zipf_text(n, 95, 1.0, family=2, stream=0)
+    t_dev = torch.from_numpy(t_host).to(dev)
+    text = sm.Text(t_dev)
+    g = synth.rng(6, 1)
+    res = {}
+
+    def wall(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        return (time.perf_counter() - t0) / reps, r
+
+    for m in (2, 4, 8, 64):
+        p = synth.substring_pattern(t_host, m, g)[0]
+        t_all, c_all = wall(lambda: sm.count(text, p, order="freq"))
+        t_no, c_no = wall(lambda: sm.count(text, p, order="freq", overlap=False))
+        assert c_no == oracle.count_nonoverlap(p, t_host), ("oracle nonoverlap", m)
+        assert c_all == oracle.count(p, t_host), ("oracle", m)
+        res[f"zipf m={m}"] = {"occurrences": c_all, "disjoint": c_no, "all_ms": round(t_all * 1e3, 3),
+                              "disjoint_ms": round(t_no * 1e3, 3),
+                              "disjoint_GBps": round(n / t_no / 1e9, 1)}
+    del t_dev, text
+    torch.cuda.empty_cache()
+    na = min(n, 256 << 20)
+    a_dev = torch.full((na,), ord("a"), dtype=torch.uint8, device=dev)
+    for k in (16, 256):
+        t_no, c_no = wall(lambda: sm.count(a_dev, b"a" * k, overlap=False), reps=1)
+        assert c_no == na // k, ("closed form", k)
+        res[f"a^n a^{k}"] = {"occurrences": na - k + 1, "disjoint": c_no, "disjoint_ms": round(t_no * 1e3, 3)}
+    del a_dev
+    torch.cuda.empty_cache()
+    head = res["zipf m=8"]
+    return [{
+        "metric": "text GB/s per search (% HBM peak)", "unit": "GB/s", "n_gpus": 1, "steps": 3, "warmup": 1,
+        "value": head["disjoint_GBps"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u8", "data": "synthetic (seeded Zipf text, substring patterns; a^n)", "ms_per_step": head["disjoint_ms"],
+        "config": {"workload": f"nonoverlap: disjoint-occurrence counts (synchronous calls, wall clock) on a "
+                               f"{n}-byte Zipf(1.0) sigma=95 text and a^n (n={na}); value = the m=8 search",
+                   "results": res},
+    }]
+
+
 # ----------------------------------------------------------------------- serve
 def run_serve(args):
     """Open-loop Poisson requests against 8 resident texts, swept offered load."""
@@ -651,7 +707,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="zipf", choices=["zipf", "batched", "serve", "single", "small"])
+    ap.add_argument("--workload", default="zipf", choices=["zipf", "batched", "serve", "single", "small", "nonoverlap"])
     ap.add_argument("--reps", type=int, default=1000, help="single: searches timed per form")
     ap.add_argument("--rates", type=float, nargs="+", default=[200, 1000, 5000, 20000, 50000, 100000],
                     help="serve: offered loads in requests/s")
@@ -679,7 +735,7 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     res = {"zipf": run_zipf, "batched": run_batched, "serve": run_serve, "single": run_single,
-           "small": run_small}[args.workload](args)
+           "small": run_small, "nonoverlap": run_nonoverlap}[args.workload](args)
     for r in (res if isinstance(res, list) else [res]):
         print(json.dumps(r), flush=True)
 

@@ -56,13 +56,24 @@ extern "C" {
 #define SM_ORDER_H 2    /* fixed heuristic order pi_h (Section 2.4)                      */
 #define SM_ORDER_HS 3   /* pi_h with space (0x20) positions moved last: pi_hs (Section 2.4) */
 
-/* Launch tuning.  Any field 0 selects the library default.  None of them
- * changes a result. */
+/* sm_params.flags: count and report only disjoint occurrences.  The paper
+ * counts every start (Section 1, Algorithm 1); this optional mode is not
+ * defined there and takes the greedy leftmost selection: the first
+ * occurrence, then the first one starting at or after the previous taken
+ * start + m, and so on (the convention of Python's bytes.count).  Supported by
+ * the synchronous calls sm_count_ex, sm_report_ex and sm_patterns_report;
+ * every other call rejects it with SM_EINVAL.  The occurrences are listed in
+ * library scratch (about 17 bytes each), so a text with 2^32 - 1 or more
+ * occurrences is rejected (SM_EINVAL) and scratch exhaustion gives SM_ENOMEM. */
+#define SM_NONOVERLAP 1
+
+/* Launch tuning and mode.  Any tuning field 0 selects the library default;
+ * none of them changes a result. */
 typedef struct sm_params {
     int32_t peel;       /* r: compares done before the first zero test, 1..8 (Section 2.3); default 2 */
     int32_t tile_kib;   /* text bytes staged per workgroup tile: 4, 8 or 16 KiB; default by n      */
     int32_t wgs_per_cu; /* workgroups per compute unit the grid is sized for, 1..32; default 6     */
-    int32_t flags;      /* reserved, must be 0                                                     */
+    int32_t flags;      /* 0 or SM_NONOVERLAP; other bits are rejected (SM_EINVAL)                 */
 } sm_params;
 
 /* ---------------------------------------------------------------- info */
@@ -104,7 +115,8 @@ int32_t sm_order(int32_t kind, const uint8_t *p, uint64_t m, const uint64_t *his
  * Returns the count (>= 0) or an error code. */
 int64_t sm_count(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n, const int32_t *order);
 
-/* sm_count with tuning (params may be NULL) on `stream`; synchronous. */
+/* sm_count with tuning (params may be NULL) on `stream`; synchronous.  With
+ * SM_NONOVERLAP in params->flags: the number of disjoint occurrences. */
 int64_t sm_count_ex(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n, const int32_t *order,
                     const sm_params *params, void *stream);
 
@@ -121,7 +133,8 @@ int32_t sm_count_async(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t 
 int64_t sm_report(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n, const int32_t *order,
                   uint64_t *pos_dev, uint64_t cap);
 
-/* sm_report with tuning (params may be NULL) on `stream`; synchronous. */
+/* sm_report with tuning (params may be NULL) on `stream`; synchronous.  With
+ * SM_NONOVERLAP: the starts of the disjoint occurrences, and their number. */
 int64_t sm_report_ex(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n, const int32_t *order,
                      const sm_params *params, uint64_t *pos_dev, uint64_t cap, void *stream);
 

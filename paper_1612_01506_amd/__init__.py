@@ -21,7 +21,7 @@ from typing import Iterable, Sequence
 import numpy as np
 import torch
 
-from ._lib import (SM_ORDER_FREQ, SM_ORDER_H, SM_ORDER_HS, SM_ORDER_LTR, SmError, check, load,
+from ._lib import (SM_NONOVERLAP, SM_ORDER_FREQ, SM_ORDER_H, SM_ORDER_HS, SM_ORDER_LTR, SmError, check, load,
                    sm_params, sm_query, sm_text)
 
 __all__ = ["Text", "PackedTexts", "Patterns", "SmError", "histogram", "order", "count", "count_async", "report",
@@ -67,17 +67,19 @@ def _stream(stream) -> int | None:
     return int(stream)
 
 
-def _params(peel=None, tile_kib=None, wgs_per_cu=None, text=None, m=None):
-    """sm_params for a call; with none given and a Text whose histogram is known, the autotuner's
-    table (if one exists for this device) supplies them."""
+def _params(peel=None, tile_kib=None, wgs_per_cu=None, text=None, m=None, overlap: bool = True):
+    """sm_params for a call; with no tuning given and a Text whose histogram is known, the
+    autotuner's table (if one exists for this device) supplies it.  overlap=False selects the
+    non-overlapping mode (SM_NONOVERLAP)."""
+    flags = 0 if overlap else SM_NONOVERLAP
     if peel is None and tile_kib is None and wgs_per_cu is None:
         if isinstance(text, Text) and text._hist is not None and m:
             from . import autotune
             tp = autotune.params_for(text._hist, int(m), text.n)
             if tp:
-                return ctypes.byref(sm_params(tp["peel"], tp["tile_kib"], tp["wgs_per_cu"], 0))
-        return None
-    return ctypes.byref(sm_params(int(peel or 0), int(tile_kib or 0), int(wgs_per_cu or 0), 0))
+                return ctypes.byref(sm_params(tp["peel"], tp["tile_kib"], tp["wgs_per_cu"], flags))
+        return ctypes.byref(sm_params(0, 0, 0, flags)) if flags else None
+    return ctypes.byref(sm_params(int(peel or 0), int(tile_kib or 0), int(wgs_per_cu or 0), flags))
 
 
 # ---------------------------------------------------------------------- texts
@@ -148,13 +150,14 @@ def _resolve_order(order_arg, p: np.ndarray, text) -> np.ndarray | None:
 
 
 # -------------------------------------------------------------------- searches
-def count(t, p, order=None, peel=None, tile_kib=None, wgs_per_cu=None, stream=None) -> int:
-    """Number of (overlapping) occurrences of p in t; synchronous."""
+def count(t, p, order=None, peel=None, tile_kib=None, wgs_per_cu=None, stream=None, overlap: bool = True) -> int:
+    """Number of occurrences of p in t; synchronous.  All starts are counted (overlapping
+    occurrences included); overlap=False counts disjoint occurrences taken greedily from the left."""
     a = _pat(p)
     ptr, n = _dev_text(t)
     o = _resolve_order(order, a, t)
     return check(load().sm_count_ex(_ptr(a), a.size, ptr, n, _ptr(o),
-                                    _params(peel, tile_kib, wgs_per_cu, t, a.size), _stream(stream)))
+                                    _params(peel, tile_kib, wgs_per_cu, t, a.size, overlap), _stream(stream)))
 
 
 def count_async(t, p, out: torch.Tensor, order=None, peel=None, tile_kib=None, wgs_per_cu=None,
@@ -170,17 +173,18 @@ def count_async(t, p, out: torch.Tensor, order=None, peel=None, tile_kib=None, w
 
 
 def report(t, p, order=None, cap: int | None = None, peel=None, tile_kib=None, wgs_per_cu=None,
-           stream=None, return_count: bool = False):
+           stream=None, return_count: bool = False, overlap: bool = True):
     """Increasing 0-based start positions of p in t (device int64 tensor); synchronous.
 
     With cap given, at most cap positions are written; return_count=True also
-    returns the full count (> cap means truncated).
+    returns the full count (> cap means truncated).  overlap=False reports the
+    disjoint occurrences taken greedily from the left.
     """
     a = _pat(p)
     ptr, n = _dev_text(t)
     o = _resolve_order(order, a, t)
     dev = t.t.device if isinstance(t, Text) else t.device
-    params = _params(peel, tile_kib, wgs_per_cu, t, a.size)
+    params = _params(peel, tile_kib, wgs_per_cu, t, a.size, overlap)
     if cap is None:
         cap = check(load().sm_count_ex(_ptr(a), a.size, ptr, n, _ptr(o), params, _stream(stream)))
     pos = torch.empty(max(int(cap), 1), dtype=torch.int64, device=dev)
@@ -411,10 +415,12 @@ class Patterns:
         return int(out.item())
 
     def report(self, i: int, t, out: torch.Tensor, peel=None, tile_kib=None, wgs_per_cu=None,
-               stream=None) -> int:
-        """Write up to out.numel() increasing positions of pattern i into out; return the full count."""
+               stream=None, overlap: bool = True) -> int:
+        """Write up to out.numel() increasing positions of pattern i into out; return the full count
+        (overlap=False: disjoint occurrences taken greedily from the left)."""
         ptr, n = _dev_text(t)
-        return check(load().sm_patterns_report(self._h, i, ptr, n, _params(peel, tile_kib, wgs_per_cu, t, self.m[i]),
+        return check(load().sm_patterns_report(self._h, i, ptr, n,
+                                               _params(peel, tile_kib, wgs_per_cu, t, self.m[i], overlap),
                                                out.data_ptr(), out.numel(), _stream(stream)))
 
     def report_async(self, i: int, t, out: torch.Tensor, total: torch.Tensor, peel=None, tile_kib=None,

@@ -72,6 +72,10 @@ struct Dev {
     size_t g_cap = 0;
     hipEvent_t rep_ev = nullptr;  // recorded after each report's last kernel
     bool rep_pending = false;
+    // non-overlapping mode (synchronous calls only): occurrence list, successor
+    // indices, marks and chunk sums in one buffer
+    uint8_t *no_buf = nullptr;
+    size_t no_cap = 0;
 };
 
 constexpr int kMaxDev = 64;
@@ -503,12 +507,18 @@ int ensure_report_scratch(Dev &d, uint64_t nblocks, uint64_t ngroups)
     return SM_OK;
 }
 
+int check_flags(const sm_params *params, bool nonoverlap_ok);
+bool nonoverlap(const sm_params *params);
+int64_t nonoverlap_core(Dev &d, const TextView &tv, uint64_t m, const uint64_t *steps_dev, const Tune &tu,
+                        uint64_t *pos, uint64_t cap, hipStream_t s);
+
 int64_t count_sync(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n, const int32_t *order,
                    const sm_params *params, hipStream_t s)
 {
     g_err.clear();
     SM_TRY(check_pattern(p, m, order));
     SM_TRY(check_text(t, n));
+    SM_TRY(check_flags(params, true));
     if (m > n)
         return 0;
     Dev *d;
@@ -517,6 +527,13 @@ int64_t count_sync(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n, c
     const Tune tu = resolve(params, m, n);
     Upload u;
     SM_TRY(upload_steps(*d, p, m, order, s, &u));
+    if (nonoverlap(params)) {
+        const int64_t r = nonoverlap_core(*d, make_view(t, n), m, reinterpret_cast<const uint64_t *>(u.dev), tu,
+                                          nullptr, 0, s);
+        const std::string msg = g_err;
+        SM_TRY(ring_commit(*d, u, s));
+        return r < 0 ? fail((int)r, msg) : r;
+    }
     HIP_TRY(hipMemsetAsync(d->u64, 0, sizeof(unsigned long long), s));
     SM_TRY(launch_count(*d, make_view(t, n), m, reinterpret_cast<const uint64_t *>(u.dev), tu, d->u64, nullptr, nullptr, s));
     HIP_TRY(hipMemcpyAsync(d->hpin, d->u64, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
@@ -525,11 +542,14 @@ int64_t count_sync(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n, c
     return (int64_t)d->hpin[0];
 }
 
-// Report with a device step table already in place: count pass with
-// per-vector counts, group sums, exclusive scan, ordered write pass.  The
-// caller holds d.mu, commits any upload afterwards and synchronises `s`.
-int report_core(Dev &d, const TextView &tv, uint64_t m, const uint64_t *steps_dev, const Tune &tu, uint64_t *pos,
-                uint64_t cap, unsigned long long *total_dev, hipStream_t s)
+// Report with a device step table already in place, in two halves.  The
+// count pass writes nonzero per-vector counts and their group sums, then the
+// exclusive scan gives group offsets and the total (on the device); the write
+// pass searches the vectors with matches again and writes their starts in
+// increasing order.  The caller holds d.mu, commits any upload afterwards and
+// synchronises `s`.
+int report_count_pass(Dev &d, const TextView &tv, uint64_t m, const uint64_t *steps_dev, const Tune &tu,
+                      unsigned long long *total_dev, hipStream_t s)
 {
     const uint64_t last = tv.first + tv.n - m;
     const uint64_t nblocks = ceil_div(last + 1, kBlock);
@@ -539,14 +559,20 @@ int report_core(Dev &d, const TextView &tv, uint64_t m, const uint64_t *steps_de
         HIP_TRY(hipEventCreateWithFlags(&d.rep_ev, hipEventDisableTiming));
     if (d.rep_pending)
         HIP_TRY(hipStreamWaitEvent(s, d.rep_ev, 0));  // scratch is shared by all reports
-    // pass 1: nonzero per-vector counts into a zeroed array, and their group sums
     HIP_TRY(launch_fill_report(d.bc, nblocks, d.gs, ngroups, s));
     SM_TRY(launch_count(d, tv, m, steps_dev, tu, nullptr, d.bc, d.gs, s));
-    // offsets: exclusive scan of the group sums, total
+    HIP_TRY(launch_scan_groups(d.gs, ngroups, d.go, total_dev, s));
+    return SM_OK;
+}
+
+int report_write_pass(Dev &d, const TextView &tv, uint64_t m, const uint64_t *steps_dev, const Tune &tu,
+                      uint64_t *pos, uint64_t cap, hipStream_t s)
+{
+    const uint64_t last = tv.first + tv.n - m;
+    const uint64_t nblocks = ceil_div(last + 1, kBlock);
+    const uint64_t ngroups = ceil_div(nblocks, kGroupBlocks);
     const uint64_t target = (uint64_t)std::max(d.cus, 1) * (uint64_t)tu.wpc;
     const unsigned ggrid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(ngroups, target));
-    HIP_TRY(launch_scan_groups(d.gs, ngroups, d.go, total_dev, s));
-    // pass 2: ordered write of the vectors with matches
     CountArgs a{};
     a.tv = tv;
     a.last = last;
@@ -563,12 +589,94 @@ int report_core(Dev &d, const TextView &tv, uint64_t m, const uint64_t *steps_de
     return SM_OK;
 }
 
+int report_core(Dev &d, const TextView &tv, uint64_t m, const uint64_t *steps_dev, const Tune &tu, uint64_t *pos,
+                uint64_t cap, unsigned long long *total_dev, hipStream_t s)
+{
+    SM_TRY(report_count_pass(d, tv, m, steps_dev, tu, total_dev, s));
+    return report_write_pass(d, tv, m, steps_dev, tu, pos, cap, s);
+}
+
+// Non-overlapping mode (greedy leftmost disjoint occurrences, see the
+// selection kernels): all occurrences are listed in library scratch, the
+// taken ones are selected on the device, and the first cap of them are
+// written to pos.  Returns the number taken.  Synchronous; the caller holds
+// d.mu and commits any upload afterwards.
+int64_t nonoverlap_core(Dev &d, const TextView &tv, uint64_t m, const uint64_t *steps_dev, const Tune &tu,
+                        uint64_t *pos, uint64_t cap, hipStream_t s)
+{
+    unsigned long long *tot = d.u64 + 1;
+    SM_TRY(report_count_pass(d, tv, m, steps_dev, tu, tot, s));
+    HIP_TRY(hipMemcpyAsync(d.hpin + 1, tot, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const uint64_t c = d.hpin[1];
+    if (c == 0)
+        return 0;
+    if (c >= 0xFFFFFFFFull)
+        return fail(SM_EINVAL, "non-overlapping mode supports fewer than 2^32 - 1 occurrences");
+    const uint64_t ng = ceil_div(c, kNoChunkEntries);
+    const size_t o_pos = 0, o_na = round_up(c * 8, 256), o_nb = o_na + round_up(c * 4, 256),
+                 o_mark = o_nb + round_up(c * 4, 256), o_gs = o_mark + round_up(c * 4, 256),
+                 o_go = o_gs + round_up(ng * 8, 256), bytes = o_go + round_up(ng * 8, 256);
+    if (d.no_cap < bytes) {
+        if (d.no_buf)
+            HIP_TRY(hipFree(d.no_buf));
+        d.no_buf = nullptr;
+        d.no_cap = 0;
+        hipError_t e = hipMalloc(reinterpret_cast<void **>(&d.no_buf), bytes);
+        if (e != hipSuccess)
+            return fail(SM_ENOMEM, std::string("non-overlapping scratch: ") + hipGetErrorString(e));
+        d.no_cap = bytes;
+    }
+    unsigned long long *all = reinterpret_cast<unsigned long long *>(d.no_buf + o_pos);
+    uint32_t *na = reinterpret_cast<uint32_t *>(d.no_buf + o_na), *nb = reinterpret_cast<uint32_t *>(d.no_buf + o_nb);
+    uint32_t *mark = reinterpret_cast<uint32_t *>(d.no_buf + o_mark);
+    unsigned long long *gs = reinterpret_cast<unsigned long long *>(d.no_buf + o_gs);
+    unsigned long long *go = reinterpret_cast<unsigned long long *>(d.no_buf + o_go);
+    SM_TRY(report_write_pass(d, tv, m, steps_dev, tu, reinterpret_cast<uint64_t *>(all), c, s));
+    // successors and cluster starts; the longest cluster bounds the doubling rounds
+    HIP_TRY(launch_fill_u64(d.u64, 1, 0ull, s));
+    HIP_TRY(launch_no_next(all, c, (uint32_t)m, na, mark, d.u64, s));
+    HIP_TRY(hipMemcpyAsync(d.hpin, d.u64, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const uint64_t longest = d.hpin[0] + 1;  // a cluster holds at most every non-start entry plus its start
+    for (uint64_t span = 1; span < longest; span <<= 1) {
+        HIP_TRY(launch_no_round(na, nb, mark, c, s));
+        std::swap(na, nb);
+    }
+    HIP_TRY(launch_no_chunk_counts(mark, c, gs, ng, s));
+    HIP_TRY(launch_scan_groups(gs, ng, go, tot, s));
+    if (cap > 0)
+        HIP_TRY(launch_no_compact(all, mark, c, go, ng, reinterpret_cast<unsigned long long *>(pos), cap, s));
+    HIP_TRY(hipMemcpyAsync(d.hpin + 1, tot, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return (int64_t)d.hpin[1];
+}
+
+// Flags of sm_params: SM_NONOVERLAP only where `nonoverlap_ok`.
+int check_flags(const sm_params *params, bool nonoverlap_ok)
+{
+    if (!params || params->flags == 0)
+        return SM_OK;
+    if (params->flags & ~(int32_t)SM_NONOVERLAP)
+        return fail(SM_EINVAL, "unknown sm_params flags");
+    if (!nonoverlap_ok)
+        return fail(SM_EINVAL, "SM_NONOVERLAP is supported by the synchronous calls only "
+                               "(sm_count_ex, sm_report_ex, sm_patterns_report)");
+    return SM_OK;
+}
+
+bool nonoverlap(const sm_params *params)
+{
+    return params && (params->flags & SM_NONOVERLAP);
+}
+
 int64_t report_sync(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n, const int32_t *order,
                     const sm_params *params, uint64_t *pos, uint64_t cap, hipStream_t s)
 {
     g_err.clear();
     SM_TRY(check_pattern(p, m, order));
     SM_TRY(check_text(t, n));
+    SM_TRY(check_flags(params, true));
     if (cap > 0 && !pos)
         return fail(SM_EINVAL, "pos is NULL with cap > 0");
     if (m > n)
@@ -581,6 +689,13 @@ int64_t report_sync(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n, 
     const Tune tu = resolve(params, m, n);
     Upload u;
     SM_TRY(upload_steps(*d, p, m, order, s, &u));
+    if (nonoverlap(params)) {
+        const int64_t r = nonoverlap_core(*d, make_view(t, n), m, reinterpret_cast<const uint64_t *>(u.dev), tu,
+                                          pos, cap, s);
+        const std::string msg = g_err;
+        SM_TRY(ring_commit(*d, u, s));
+        return r < 0 ? fail((int)r, msg) : r;
+    }
     const int rc = report_core(*d, make_view(t, n), m, reinterpret_cast<const uint64_t *>(u.dev), tu, pos, cap,
                                d->u64 + 1, s);
     SM_TRY(ring_commit(*d, u, s));
@@ -596,6 +711,7 @@ int report_async(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n, con
     g_err.clear();
     SM_TRY(check_pattern(p, m, order));
     SM_TRY(check_text(t, n));
+    SM_TRY(check_flags(params, false));
     if (cap > 0 && !pos)
         return fail(SM_EINVAL, "pos is NULL with cap > 0");
     if (!total_dev)
@@ -1191,6 +1307,7 @@ int32_t sm_shutdown(void)
         if (d->gs) (void)hipFree(d->gs);
         if (d->go) (void)hipFree(d->go);
         if (d->rep_ev) (void)hipEventDestroy(d->rep_ev);
+        if (d->no_buf) (void)hipFree(d->no_buf);
         delete d;
         g_devs[i] = nullptr;
     }
@@ -1265,6 +1382,7 @@ int32_t sm_count_async(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t 
     g_err.clear();
     SM_TRY(check_pattern(p, m, order));
     SM_TRY(check_text(t, n));
+    SM_TRY(check_flags(params, false));
     if (!count_dev)
         return fail(SM_EINVAL, "count_dev is NULL");
     if (m > n)
@@ -1390,6 +1508,7 @@ int32_t sm_patterns_count(const sm_patterns *ps, uint64_t i, const uint8_t *t, u
     g_err.clear();
     SM_TRY(check_set(ps, i));
     SM_TRY(check_text(t, n));
+    SM_TRY(check_flags(params, false));
     if (!count_dev)
         return fail(SM_EINVAL, "count_dev is NULL");
     const uint64_t m = ps->m[i];
@@ -1409,6 +1528,7 @@ int64_t sm_patterns_report(const sm_patterns *ps, uint64_t i, const uint8_t *t, 
     g_err.clear();
     SM_TRY(check_set(ps, i));
     SM_TRY(check_text(t, n));
+    SM_TRY(check_flags(params, true));
     if (cap > 0 && !pos_dev)
         return fail(SM_EINVAL, "pos is NULL with cap > 0");
     const uint64_t m = ps->m[i];
@@ -1419,6 +1539,8 @@ int64_t sm_patterns_report(const sm_patterns *ps, uint64_t i, const uint8_t *t, 
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     std::lock_guard<std::mutex> lk(d->mu);
     const Tune tu = resolve(params, m, n);
+    if (nonoverlap(params))
+        return nonoverlap_core(*d, make_view(t, n), m, ps->steps + ps->off[i], tu, pos_dev, cap, s);
     SM_TRY(report_core(*d, make_view(t, n), m, ps->steps + ps->off[i], tu, cap ? pos_dev : nullptr, cap, d->u64 + 1, s));
     HIP_TRY(hipMemcpyAsync(d->hpin + 1, d->u64 + 1, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -1432,6 +1554,7 @@ int32_t sm_patterns_report_async(const sm_patterns *ps, uint64_t i, const uint8_
     g_err.clear();
     SM_TRY(check_set(ps, i));
     SM_TRY(check_text(t, n));
+    SM_TRY(check_flags(params, false));
     if (cap > 0 && !pos_dev)
         return fail(SM_EINVAL, "pos is NULL with cap > 0");
     if (!total_dev)
@@ -1458,6 +1581,7 @@ int32_t sm_count_batch(const sm_query *q, uint64_t nq, const sm_text *texts, uin
         return SM_OK;
     if (!counts_dev)
         return fail(SM_EINVAL, "counts_dev is NULL");
+    SM_TRY(check_flags(params, false));
     SM_TRY(validate_batch(q, nq, texts, nt));
     Dev *d;
     SM_TRY(get_dev(&d));
@@ -1489,6 +1613,7 @@ int32_t sm_batch_create(const sm_query *q, uint64_t nq, const sm_text *texts, ui
     if (!out)
         return fail(SM_EINVAL, "out is NULL");
     *out = nullptr;
+    SM_TRY(check_flags(params, false));
     if (nq > 0)
         SM_TRY(validate_batch(q, nq, texts, nt));
     Dev *d;

@@ -127,6 +127,16 @@ hipError_t launch_hist(const TextView &tv, unsigned long long *hist, unsigned gr
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_batch_staged(const BatchArgs &a, int cpl, unsigned grid, hipStream_t s);
 hipError_t launch_batch_bitmap(const BmArgs &a, unsigned grid, uint32_t lds_bytes, hipStream_t s);
+// Non-overlapping selection over the ascending occurrence list (c entries).
+constexpr uint64_t kNoChunkEntries = 4 * kWG;  // list entries per compaction chunk
+hipError_t launch_no_next(const unsigned long long *pos, uint64_t c, uint32_t m, uint32_t *nxt, uint32_t *mark,
+                          unsigned long long *overlapped, hipStream_t s);
+hipError_t launch_no_round(const uint32_t *nxt, uint32_t *nxt_out, uint32_t *mark, uint64_t c, hipStream_t s);
+hipError_t launch_no_chunk_counts(const uint32_t *mark, uint64_t c, unsigned long long *gs, uint64_t ng,
+                                  hipStream_t s);
+hipError_t launch_no_compact(const unsigned long long *pos, const uint32_t *mark, uint64_t c,
+                             const unsigned long long *go, uint64_t ng, unsigned long long *out, uint64_t cap,
+                             hipStream_t s);
 // Sets the dynamic-LDS limits of all kernels on the current device.
 hipError_t prime_kernel_attrs();
 

@@ -839,6 +839,139 @@ __global__ __launch_bounds__(kWG) void k_batch_staged(BatchArgs a)
         flush(cur);
 }
 
+// ----------------------------------------------------- non-overlapping mode
+//
+// Disjoint occurrences by greedy leftmost selection over the ascending list of
+// all occurrences pos[0..c): take pos[0]; after taking pos[i], take the first
+// occurrence at or after pos[i] + m.  nxt[i] is that successor of i (c if
+// none), so the taken set is the chain 0, nxt[0], nxt[nxt[0]], ...
+// An occurrence at least m after its predecessor in the list starts a cluster
+// and is always taken (the last start taken before it is at most its
+// predecessor, and every occurrence in between lies within m of that start),
+// so the chain is found cluster by cluster.  Pointer doubling marks it: the
+// cluster starts are marked first; round k marks nxt^(2^k)(i) of every marked
+// i and squares the jump, so ceil(log2 L) rounds cover clusters of up to L
+// occurrences.  A mark set early in a round is still on the chain, so the
+// order within a round does not matter.
+
+__device__ __forceinline__ bool no_taken(const uint32_t *mark, uint64_t i)
+{
+    return mark[i] != 0u;
+}
+
+// Successors, cluster-start marks, and the number of entries that are not
+// cluster starts (added to *overlapped).
+__global__ __launch_bounds__(kWG) void k_no_next(const unsigned long long *pos, uint64_t c, uint32_t m, uint32_t *nxt,
+                                                 uint32_t *mark, unsigned long long *overlapped)
+{
+    uint32_t ov = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * kWG + threadIdx.x; i < c; i += (uint64_t)gridDim.x * kWG) {
+        const unsigned long long target = pos[i] + m;
+        uint64_t lo = i + 1, hi = c;  // first index in [lo, hi) with pos >= target
+        while (lo < hi) {
+            const uint64_t mid = lo + (hi - lo) / 2;
+            if (pos[mid] < target)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        nxt[i] = (uint32_t)lo;
+        const bool start = i == 0 || pos[i] - pos[i - 1] >= m;
+        mark[i] = start ? 1u : 0u;
+        ov += start ? 0u : 1u;
+    }
+    const uint32_t s = wave_sum32(ov);
+    if ((threadIdx.x & 63u) == 0 && s)
+        atomicAdd(overlapped, (unsigned long long)s);
+}
+
+__global__ __launch_bounds__(kWG) void k_no_mark(const uint32_t *nxt, uint32_t *mark, uint64_t c)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * kWG + threadIdx.x; i < c; i += (uint64_t)gridDim.x * kWG) {
+        if (no_taken(mark, i)) {
+            const uint32_t j = nxt[i];
+            if (j < c)
+                mark[j] = 1u;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_no_jump(const uint32_t *in, uint32_t *out, uint64_t c)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * kWG + threadIdx.x; i < c; i += (uint64_t)gridDim.x * kWG) {
+        const uint32_t j = in[i];
+        out[i] = j < c ? in[j] : (uint32_t)c;
+    }
+}
+
+// Taken elements per chunk of kNoChunkEntries list entries (four consecutive per thread).
+
+__global__ __launch_bounds__(kWG) void k_no_chunk_counts(const uint32_t *mark, uint64_t c, unsigned long long *gs,
+                                                         uint64_t ng)
+{
+    __shared__ uint32_t ws[kWaves];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = wave_id();
+    for (uint64_t g = blockIdx.x; g < ng; g += gridDim.x) {
+        const uint64_t i0 = g * kNoChunkEntries + 4u * tid;
+        uint32_t k = 0;
+#pragma unroll
+        for (uint32_t e = 0; e < 4u; ++e)
+            k += (i0 + e < c && no_taken(mark, i0 + e)) ? 1u : 0u;
+        const uint32_t s = wave_sum32(k);
+        if (lane == 0)
+            ws[wave] = s;
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t t = 0;
+            for (uint32_t w = 0; w < kWaves; ++w)
+                t += ws[w];
+            gs[g] = t;
+        }
+        __syncthreads();
+    }
+}
+
+// Writes the taken starts of each chunk at its exclusive offset go[g], in list
+// order (thread-major, four entries per thread), keeping the first cap.
+__global__ __launch_bounds__(kWG) void k_no_compact(const unsigned long long *pos, const uint32_t *mark, uint64_t c,
+                                                    const unsigned long long *go, uint64_t ng,
+                                                    unsigned long long *out, uint64_t cap)
+{
+    __shared__ uint32_t ws[kWaves];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = wave_id();
+    for (uint64_t g = blockIdx.x; g < ng; g += gridDim.x) {
+        const uint64_t i0 = g * kNoChunkEntries + 4u * tid;
+        uint32_t take = 0;  // bit e: entry i0 + e is taken
+#pragma unroll
+        for (uint32_t e = 0; e < 4u; ++e)
+            if (i0 + e < c && no_taken(mark, i0 + e))
+                take |= 1u << e;
+        const uint32_t k = (uint32_t)__popc(take);
+        uint32_t inc = k;  // inclusive prefix over the wave's lanes
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t v = __shfl_up(inc, o, 64);
+            if (lane >= (uint32_t)o)
+                inc += v;
+        }
+        if (lane == 63u)
+            ws[wave] = inc;
+        __syncthreads();
+        uint64_t off = go[g] + (inc - k);
+        for (uint32_t w = 0; w < wave; ++w)
+            off += ws[w];
+#pragma unroll
+        for (uint32_t e = 0; e < 4u; ++e) {
+            if (take & (1u << e)) {
+                if (off < cap)
+                    out[off] = pos[i0 + e];
+                ++off;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // ----------------------------------------------------- batch bitmap kernel
 
 // Valid-start bits of the 32 starts p0 .. p0 + 31: first <= p <= last.
@@ -1107,6 +1240,48 @@ hipError_t launch_batch_bitmap(const BmArgs &a, unsigned grid, uint32_t lds_byte
         attr_set = true;
     }
     hipLaunchKernelGGL(k_batch_bitmap, dim3(grid), dim3(kBmWG), lds_bytes, s, a);
+    return hipGetLastError();
+}
+}  // namespace smk
+
+namespace smk {
+static unsigned no_grid(uint64_t items)
+{
+    const uint64_t g = (items + kWG - 1) / kWG;
+    return (unsigned)(g < 8192 ? (g ? g : 1) : 8192);
+}
+
+hipError_t launch_no_next(const unsigned long long *pos, uint64_t c, uint32_t m, uint32_t *nxt, uint32_t *mark,
+                          unsigned long long *overlapped, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_no_next, dim3(no_grid(c)), dim3(kWG), 0, s, pos, c, m, nxt, mark, overlapped);
+    return hipGetLastError();
+}
+
+hipError_t launch_no_round(const uint32_t *nxt, uint32_t *nxt_out, uint32_t *mark, uint64_t c, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_no_mark, dim3(no_grid(c)), dim3(kWG), 0, s, nxt, mark, c);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_no_jump, dim3(no_grid(c)), dim3(kWG), 0, s, nxt, nxt_out, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_no_chunk_counts(const uint32_t *mark, uint64_t c, unsigned long long *gs, uint64_t ng,
+                                  hipStream_t s)
+{
+    const unsigned grid = (unsigned)(ng < 4096 ? (ng ? ng : 1) : 4096);
+    hipLaunchKernelGGL(k_no_chunk_counts, dim3(grid), dim3(kWG), 0, s, mark, c, gs, ng);
+    return hipGetLastError();
+}
+
+hipError_t launch_no_compact(const unsigned long long *pos, const uint32_t *mark, uint64_t c,
+                             const unsigned long long *go, uint64_t ng, unsigned long long *out, uint64_t cap,
+                             hipStream_t s)
+{
+    const unsigned grid = (unsigned)(ng < 4096 ? (ng ? ng : 1) : 4096);
+    hipLaunchKernelGGL(k_no_compact, dim3(grid), dim3(kWG), 0, s, pos, mark, c, go, ng, out, cap);
     return hipGetLastError();
 }
 }  // namespace smk

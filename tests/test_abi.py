@@ -66,6 +66,17 @@ def test_validation_before_any_device_call():
     assert lib.sm_batch_create(None, 0, None, 0, None, None) == _lib.SM_EINVAL
     assert "NULL" in _err(lib.sm_batch_run(None, None, None))
     assert lib.sm_batch_destroy(None) == _lib.SM_OK
+    # sm_params.flags: unknown bits everywhere, SM_NONOVERLAP outside the synchronous calls
+    bad_flags = _lib.sm_params(0, 0, 0, 2)
+    assert "flags" in _err(lib.sm_count_ex(p.ctypes.data, 3, None, 0, None, ctypes.byref(bad_flags), None))
+    no = _lib.sm_params(0, 0, 0, _lib.SM_NONOVERLAP)
+    assert lib.sm_count_ex(p.ctypes.data, 3, None, 0, None, ctypes.byref(no), None) == 0   # m > n: no device work
+    assert "synchronous" in _err(lib.sm_count_async(p.ctypes.data, 3, None, 0, None, ctypes.byref(no), 8, None))
+    assert "synchronous" in _err(lib.sm_report_async(p.ctypes.data, 3, None, 0, None, ctypes.byref(no), None, 0, 8,
+                                                     None))
+    q = np.zeros(1, dtype=sm._QUERY_DT)
+    assert "synchronous" in _err(lib.sm_count_batch(q.ctypes.data_as(ctypes.POINTER(_lib.sm_query)), 1, None, 0, 8,
+                                                    ctypes.byref(no), None))
     # histogram: NULL output
     assert lib.sm_histogram(None, 0, None, None) == _lib.SM_EINVAL
 

@@ -528,3 +528,67 @@ def test_batch_plan_empty_and_errors(dev):
         assert plan.run().cpu().tolist() == [2, 2, 0]
         with pytest.raises(ValueError):
             plan.run(torch.zeros(2, dtype=torch.int64, device=dev))
+
+
+# ------------------------------------------------------------ non-overlapping mode
+@pytest.mark.parametrize("sigma", [1, 2, 4, 256])
+def test_nonoverlap_parity(dev, sigma):
+    """Disjoint occurrences (greedy leftmost) against the oracle: counts, positions, cap, misalignment."""
+    g = np.random.default_rng(700 + sigma)
+    for n in (1, 17, 1023, 1024, 4097, 65_537, 1_000_003):
+        t = (np.full(n, ord("a"), dtype=np.uint8) if sigma == 1 else rand_text(n, min(sigma, 256), n + sigma))
+        td = to_dev(t, dev, n % 16)
+        for m in (1, 2, 3, 5, 8, 31, 100):
+            if sigma == 1:
+                p = b"a" * m
+            else:
+                p = pick_pattern(t, m, g, planted=g.random() < 0.8)
+            want = oracle.report_nonoverlap(p, t)
+            want_n = int(want.size)
+            assert sm.count(td, p, overlap=False) == want_n, (n, m)
+            pos, total = sm.report(td, p, overlap=False, return_count=True)
+            assert total == want_n
+            assert pos.cpu().numpy().astype(np.uint64).tolist() == want.tolist(), (n, m)
+            if want_n > 3:
+                pos, total = sm.report(td, p, overlap=False, cap=3, return_count=True)
+                assert total == want_n and pos.cpu().tolist() == want[:3].tolist()
+            # the overlapping count is unchanged by the mode of earlier calls
+            assert sm.count(td, p) == oracle.count(p, t)
+
+
+def test_nonoverlap_closed_forms_large(dev):
+    """a^n with p = a^k takes floor(n/k) starts 0, k, 2k, ...; (ab)^q with (ab)^j: floor(q/j)."""
+    n = 48_000_011
+    td = torch.full((n,), ord("a"), dtype=torch.uint8, device=dev)
+    for k in (1, 2, 3, 16, 255):
+        assert sm.count(td, b"a" * k, overlap=False) == n // k
+    pos, total = sm.report(td, b"a" * 7, overlap=False, cap=1000, return_count=True)
+    assert total == n // 7 and pos.cpu().tolist() == list(range(0, 7000, 7))
+    q = 3_000_001
+    t2 = to_dev(np.frombuffer(b"ab" * q, dtype=np.uint8), dev, 5)
+    for j in (1, 2, 5):
+        assert sm.count(t2, b"ab" * j, overlap=False) == q // j
+    assert sm.count(t2, b"ba", overlap=False) == q - 1
+
+
+def test_nonoverlap_patterns_and_rejections(dev):
+    t = rand_text(300_000, 2, 9)
+    td = to_dev(t, dev, 3)
+    pats = [b"0", b"01", b"0101", b"11011", bytes(t[1000:1040])]
+    ps = sm.Patterns(pats)
+    out = torch.empty(200_000, dtype=torch.int64, device=dev)
+    for i, p in enumerate(pats):
+        want_n, want = oracle.report_nonoverlap_full(p, t, out.numel())
+        got = ps.report(i, td, out, overlap=False)
+        assert got == want_n
+        assert out[:min(got, out.numel())].cpu().numpy().astype(np.uint64).tolist() == want.tolist()
+    ps.close()
+    c = torch.zeros(1, dtype=torch.int64, device=dev)
+    lib = sm._lib.load()
+    no = sm._lib.sm_params(0, 0, 0, sm._lib.SM_NONOVERLAP)
+    import ctypes
+    p = np.frombuffer(b"01", dtype=np.uint8)
+    rc = lib.sm_count_async(p.ctypes.data, 2, td.data_ptr(), td.numel(), None, ctypes.byref(no), c.data_ptr(), None)
+    assert rc == sm._lib.SM_EINVAL and "synchronous" in lib.sm_last_error().decode()
+    torch.cuda.synchronize()
+    assert int(c.item()) == 0
