@@ -5,6 +5,7 @@
 #include "sm_internal.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <deque>
 #include <functional>
@@ -72,6 +73,9 @@ struct Dev {
     size_t g_cap = 0;
     hipEvent_t rep_ev = nullptr;  // recorded after each report's last kernel
     bool rep_pending = false;
+    // bc and gs must be zero when a report's count pass starts; the write pass
+    // leaves them zero, so only fresh scratch or an unfinished report needs a fill
+    bool rep_dirty = true;
     // non-overlapping mode (synchronous calls only): occurrence list, successor
     // indices, marks and chunk sums in one buffer
     uint8_t *no_buf = nullptr;
@@ -489,6 +493,7 @@ int ensure_report_scratch(Dev &d, uint64_t nblocks, uint64_t ngroups)
         if (e != hipSuccess)
             return fail(SM_ENOMEM, std::string("report scratch: ") + hipGetErrorString(e));
         d.bc_cap = nblocks;
+        d.rep_dirty = true;
     }
     if (d.g_cap < ngroups) {
         if (d.gs)
@@ -503,6 +508,7 @@ int ensure_report_scratch(Dev &d, uint64_t nblocks, uint64_t ngroups)
         if (e != hipSuccess)
             return fail(SM_ENOMEM, std::string("report scratch: ") + hipGetErrorString(e));
         d.g_cap = ngroups;
+        d.rep_dirty = true;
     }
     return SM_OK;
 }
@@ -559,7 +565,9 @@ int report_count_pass(Dev &d, const TextView &tv, uint64_t m, const uint64_t *st
         HIP_TRY(hipEventCreateWithFlags(&d.rep_ev, hipEventDisableTiming));
     if (d.rep_pending)
         HIP_TRY(hipStreamWaitEvent(s, d.rep_ev, 0));  // scratch is shared by all reports
-    HIP_TRY(launch_fill_report(d.bc, nblocks, d.gs, ngroups, s));
+    if (d.rep_dirty)
+        HIP_TRY(launch_fill_report(d.bc, d.bc_cap, d.gs, d.g_cap, s));
+    d.rep_dirty = true;  // until a write pass has cleaned up after this count pass
     SM_TRY(launch_count(d, tv, m, steps_dev, tu, nullptr, d.bc, d.gs, s));
     HIP_TRY(launch_scan_groups(d.gs, ngroups, d.go, total_dev, s));
     return SM_OK;
@@ -586,6 +594,7 @@ int report_write_pass(Dev &d, const TextView &tv, uint64_t m, const uint64_t *st
                                 reinterpret_cast<unsigned long long *>(pos), cap, (uint32_t)win, ggrid, s));
     HIP_TRY(hipEventRecord(d.rep_ev, s));
     d.rep_pending = true;
+    d.rep_dirty = false;
     return SM_OK;
 }
 
@@ -609,8 +618,10 @@ int64_t nonoverlap_core(Dev &d, const TextView &tv, uint64_t m, const uint64_t *
     HIP_TRY(hipMemcpyAsync(d.hpin + 1, tot, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     const uint64_t c = d.hpin[1];
-    if (c == 0)
+    if (c == 0) {
+        d.rep_dirty = false;  // no vector had a match: the count pass wrote nothing
         return 0;
+    }
     if (c >= 0xFFFFFFFFull)
         return fail(SM_EINVAL, "non-overlapping mode supports fewer than 2^32 - 1 occurrences");
     const uint64_t ng = ceil_div(c, kNoChunkEntries);
@@ -801,26 +812,39 @@ struct LaunchPlan {
 };
 
 // Runs body(begin, end) over [0, n) split into contiguous ranges, on up to
-// kPlanThreads threads when n is large enough to pay for them.
+// kPlanThreads threads when n is large enough to pay for them.  Returns
+// false if any range threw (host memory exhaustion) or a thread could not
+// be started; the ranges are then incomplete.
 constexpr size_t kPlanThreads = 8, kPlanPerThread = 1024;
 template <typename F>
-void parallel_for(size_t n, const F &body)
+bool parallel_for(size_t n, const F &body)
 {
+    std::atomic<bool> ok{true};
+    auto run = [&](size_t k0, size_t k1) {
+        try {
+            body(k0, k1);
+        } catch (...) {
+            ok = false;
+        }
+    };
     const size_t hw = std::max<size_t>(1, std::thread::hardware_concurrency());
     const size_t nth = std::min({kPlanThreads, hw, std::max<size_t>(1, n / kPlanPerThread)});
-    if (nth <= 1) {
-        body(0, n);
-        return;
-    }
+    const size_t per = (n + nth - 1) / std::max<size_t>(nth, 1);
     std::vector<std::thread> pool;
-    const size_t per = (n + nth - 1) / nth;
-    for (size_t t = 1; t < nth; ++t) {
-        const size_t k0 = std::min(n, t * per), k1 = std::min(n, k0 + per);
-        pool.emplace_back([&body, k0, k1] { body(k0, k1); });
+    size_t done = per;  // the calling thread takes the first range
+    try {
+        for (size_t t = 1; t < nth; ++t) {
+            const size_t k0 = std::min(n, t * per), k1 = std::min(n, k0 + per);
+            pool.emplace_back(run, k0, k1);
+            done = k1;
+        }
+    } catch (...) {
+        run(done, n);  // could not start another thread: the rest runs here
     }
-    body(0, std::min(n, per));
+    run(0, std::min(n, per));
     for (auto &th : pool)
         th.join();
+    return ok;
 }
 
 // Peel factor from the text's symbol frequencies.  Section 3 finds r = 2
@@ -1150,11 +1174,13 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
         hbq[i] = bq;
         hbout[i] = (uint32_t)pq.idx;
     };
-    parallel_for(n_st + n_lg + n_bm, [&](size_t k0, size_t k1) {
+    const bool planned = parallel_for(n_st + n_lg + n_bm, [&](size_t k0, size_t k1) {
         Scratch w;
         for (size_t k = k0; k < k1; ++k)
             fill(k, w);
     });
+    if (!planned)
+        return fail(SM_ENOMEM, "batch planning ran out of host memory");
     std::vector<uint64_t> long_steps_off(st_off.begin() + n_st, st_off.end());
     {
         size_t k = 0;

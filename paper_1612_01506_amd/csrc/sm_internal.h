@@ -118,7 +118,7 @@ hipError_t launch_count_staged(const CountArgs &a, int cpl, int r, unsigned grid
 hipError_t launch_count_global(const CountArgs &a, int r, unsigned grid, hipStream_t s);
 hipError_t launch_scan_groups(const unsigned long long *gs, uint64_t ngroups, unsigned long long *go,
                               unsigned long long *total, hipStream_t s);
-hipError_t launch_report_write(const CountArgs &a, uint32_t r, const uint32_t *bc, const unsigned long long *gs,
+hipError_t launch_report_write(const CountArgs &a, uint32_t r, uint32_t *bc, unsigned long long *gs,
                                const unsigned long long *go, uint64_t ngroups, unsigned long long *pos, uint64_t cap,
                                uint32_t win, unsigned grid, hipStream_t s);
 hipError_t launch_fill_report(uint32_t *bc, uint64_t nblocks, unsigned long long *gs, uint64_t ngroups,

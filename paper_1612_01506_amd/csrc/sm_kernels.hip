@@ -583,8 +583,8 @@ __device__ __forceinline__ void write_vector(const uint32_t (&d)[4], uint64_t wb
 
 // win: per-wave LDS window in bytes (1024 + halo), or 0 to read the text
 // from global memory (long patterns).
-__global__ __launch_bounds__(kWG) void k_report_write(CountArgs a, uint32_t r, const uint32_t *bc,
-                                                     const unsigned long long *gs, const unsigned long long *go,
+__global__ __launch_bounds__(kWG) void k_report_write(CountArgs a, uint32_t r, uint32_t *bc,
+                                                     unsigned long long *gs, const unsigned long long *go,
                                                      uint64_t ngroups, unsigned long long *pos, uint64_t cap,
                                                      uint32_t win)
 {
@@ -658,6 +658,15 @@ __global__ __launch_bounds__(kWG) void k_report_write(CountArgs a, uint32_t r, c
             }
         }
         __syncthreads();
+        // leave the group's scratch zeroed for the next report: every nonzero
+        // per-vector count lies in a group with a nonzero sum, so after the
+        // pass both arrays are all zero again
+#pragma unroll
+        for (uint32_t i = 0; i < kGroupBlocks / kWG; ++i)
+            if (c[i])
+                bc[b0 + (kGroupBlocks / kWG) * tid + i] = 0u;
+        if (tid == 0)
+            gs[g] = 0ull;
     }
 }
 
@@ -1092,15 +1101,7 @@ __global__ __launch_bounds__(kBmWG) void k_batch_bitmap(BmArgs a)
 template <int CPL, int R>
 static hipError_t launch_staged_t(const CountArgs &a, unsigned grid, hipStream_t s)
 {
-    static bool attr_set = false;
     const uint32_t lds = 2u * (kWG * 16u * CPL + a.halo);
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_count_staged<CPL, R>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
-        if (e != hipSuccess)
-            return e;
-        attr_set = true;
-    }
     hipLaunchKernelGGL((k_count_staged<CPL, R>), dim3(grid), dim3(kWG), lds, s, a);
     return hipGetLastError();
 }
@@ -1160,18 +1161,10 @@ hipError_t launch_scan_groups(const unsigned long long *gs, uint64_t ngroups, un
     return hipGetLastError();
 }
 
-hipError_t launch_report_write(const CountArgs &a, uint32_t r, const uint32_t *bc, const unsigned long long *gs,
+hipError_t launch_report_write(const CountArgs &a, uint32_t r, uint32_t *bc, unsigned long long *gs,
                                const unsigned long long *go, uint64_t ngroups, unsigned long long *pos, uint64_t cap,
                                uint32_t win, unsigned grid, hipStream_t s)
 {
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_report_write),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
-        if (e != hipSuccess)
-            return e;
-        attr_set = true;
-    }
     hipLaunchKernelGGL(k_report_write, dim3(grid), dim3(kWG), kWaves * win, s, a, r, bc, gs, go, ngroups, pos, cap,
                        win);
     return hipGetLastError();
@@ -1203,14 +1196,6 @@ hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long
 template <int CPL>
 static hipError_t launch_batch_t(const BatchArgs &a, unsigned grid, hipStream_t s)
 {
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch_staged<CPL>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
-        if (e != hipSuccess)
-            return e;
-        attr_set = true;
-    }
     const uint32_t lds = 2u * (kWG * 16u * CPL + a.halo_max) + kQChunk * (uint32_t)sizeof(uint32_t);
     hipLaunchKernelGGL((k_batch_staged<CPL>), dim3(grid), dim3(kWG), lds, s, a);
     return hipGetLastError();
@@ -1231,14 +1216,6 @@ hipError_t launch_batch_staged(const BatchArgs &a, int cpl, unsigned grid, hipSt
 namespace smk {
 hipError_t launch_batch_bitmap(const BmArgs &a, unsigned grid, uint32_t lds_bytes, hipStream_t s)
 {
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch_bitmap),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBmMaxLds);
-        if (e != hipSuccess)
-            return e;
-        attr_set = true;
-    }
     hipLaunchKernelGGL(k_batch_bitmap, dim3(grid), dim3(kBmWG), lds_bytes, s, a);
     return hipGetLastError();
 }
