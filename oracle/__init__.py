@@ -14,6 +14,8 @@ marshals arguments.  Functions and the passages they follow:
 * ``hist``       -- symbol frequencies (Section 2.2).
 * ``order_freq`` -- compare order by increasing symbol frequency (Section 2.2), ties by position.
 * ``order_h`` / ``order_hs`` -- the fixed orders pi_h and pi_hs (Section 2.4).
+* ``bigram`` / ``order_bigram`` -- adjacent-pair frequencies and the bigram-aware order (the
+  conditional-probability strategy Section 2.2 discusses, restricted to adjacent pairs).
 * ``alg4_count`` -- Algorithm 4 (Section 2.3) emulated with a 64-bit found word.
 
 Every function is pinned by ``tests/test_oracle.py`` against brute force, the
@@ -65,6 +67,10 @@ def _load():
         lib.oracle_order_hs.restype = ctypes.c_int
         lib.oracle_report_nonoverlap.argtypes = [u8p, u64, u8p, u64, u8p, u64]
         lib.oracle_report_nonoverlap.restype = i64
+        lib.oracle_bigram.argtypes = [u8p, u64, u8p]
+        lib.oracle_bigram.restype = None
+        lib.oracle_order_bigram.argtypes = [u8p, u64, u8p, u8p, u8p]
+        lib.oracle_order_bigram.restype = ctypes.c_int
         lib.oracle_alg4_count.argtypes = [u8p, u64, u8p, u64, u8p, u64]
         lib.oracle_alg4_count.restype = i64
         _lib = lib
@@ -163,6 +169,24 @@ def order_hs(p) -> np.ndarray:
     p = _u8(p)
     out = np.zeros(max(p.size, 1), dtype=np.int32)
     if _load().oracle_order_hs(_ptr(p), p.size, out.ctypes.data) != 0:
+        raise ValueError("bad pattern length")
+    return out[:p.size]
+
+
+def bigram(t) -> np.ndarray:
+    """(256, 256) uint64: [a, b] = number of s with t[s] == a and t[s+1] == b."""
+    t = _u8(t)
+    out = np.zeros(65536, dtype=np.uint64)
+    _load().oracle_bigram(_ptr(t), t.size, out.ctypes.data)
+    return out.reshape(256, 256)
+
+
+def order_bigram(p, h, bg) -> np.ndarray:
+    p = _u8(p)
+    h = np.ascontiguousarray(h, dtype=np.uint64)
+    bg = np.ascontiguousarray(bg, dtype=np.uint64).reshape(65536)
+    out = np.zeros(max(p.size, 1), dtype=np.int32)
+    if _load().oracle_order_bigram(_ptr(p), p.size, h.ctypes.data, bg.ctypes.data, out.ctypes.data) != 0:
         raise ValueError("bad pattern length")
     return out[:p.size]
 

@@ -108,6 +108,16 @@ void oracle_hist(const uint8_t *t, uint64_t n, uint64_t *hist)
         hist[t[s]]++;
 }
 
+/* Adjacent-pair frequencies: bigram[a * 256 + b] = number of s in [0, n-2]
+ * with t[s] == a and t[s+1] == b.  The statistics behind the bigram-aware
+ * compare order below. */
+void oracle_bigram(const uint8_t *t, uint64_t n, uint64_t *bigram)
+{
+    memset(bigram, 0, 65536 * sizeof(uint64_t));
+    for (uint64_t s = 0; s + 1 < n; ++s)
+        bigram[(uint64_t)t[s] * 256 + t[s + 1]]++;
+}
+
 /* ------------------------------------------------------------------------
  * Frequency order pi (Section 2.2): pattern positions sorted by the text
  * frequency of their symbol, least frequent first.  The paper leaves ties
@@ -178,6 +188,82 @@ int oracle_order_hs(const uint8_t *p, uint64_t m, int32_t *order)
         if (p[h[i]] == 0x20)
             order[k++] = h[i];
     free(h);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Bigram-aware compare order.  Section 2.2 notes that ordering by symbol
+ * frequency alone compares 'qui' as q, u, i although q, i, u is better, since
+ * u nearly always follows q, and points to strategies that compare next the
+ * position least likely to match given the positions already compared.  The
+ * reading taken, restricted to adjacent pairs: repeatedly pick the position j
+ * not yet compared whose estimated match probability e(j) is smallest (ties by
+ * position), where
+ *   e(j) = bigram[p[j-1]][p[j]] / row(p[j-1])   if only j-1 is compared,
+ *          bigram[p[j]][p[j+1]] / col(p[j+1])   if only j+1 is compared,
+ *          the smaller of the two                  if both are,
+ *          hist[p[j]] / (sum of hist)            if neither is;
+ * row(a) and col(b) are the row and column sums of the bigram table, and a
+ * zero denominator gives e = 0.  Fractions are compared exactly.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    uint64_t num, den;
+} frac_t;
+
+static int frac_less(frac_t x, frac_t y)
+{
+    return (unsigned __int128)x.num * y.den < (unsigned __int128)y.num * x.den;
+}
+
+static frac_t frac_of(uint64_t num, uint64_t den)
+{
+    frac_t f = {den ? num : 0, den ? den : 1};
+    return f;
+}
+
+int oracle_order_bigram(const uint8_t *p, uint64_t m, const uint64_t *hist, const uint64_t *bigram,
+                        int32_t *order)
+{
+    if (m == 0 || m > 0x7fffffffULL)
+        return -1;
+    uint64_t total = 0, row[256] = {0}, col[256] = {0};
+    for (int a = 0; a < 256; ++a)
+        total += hist[a];
+    for (int a = 0; a < 256; ++a)
+        for (int b = 0; b < 256; ++b) {
+            row[a] += bigram[a * 256 + b];
+            col[b] += bigram[a * 256 + b];
+        }
+    unsigned char *done = (unsigned char *)calloc((size_t)m, 1);
+    if (!done)
+        return -1;
+    for (uint64_t k = 0; k < m; ++k) {
+        uint64_t best = m;
+        frac_t best_e = {0, 1};
+        for (uint64_t j = 0; j < m; ++j) {
+            if (done[j])
+                continue;
+            const int left = j > 0 && done[j - 1], right = j + 1 < m && done[j + 1];
+            frac_t e;
+            if (left || right) {
+                frac_t el = {0, 1}, er = {0, 1};
+                if (left)
+                    el = frac_of(bigram[(uint64_t)p[j - 1] * 256 + p[j]], row[p[j - 1]]);
+                if (right)
+                    er = frac_of(bigram[(uint64_t)p[j] * 256 + p[j + 1]], col[p[j + 1]]);
+                e = !right ? el : !left ? er : (frac_less(er, el) ? er : el);
+            } else {
+                e = frac_of(hist[p[j]], total);
+            }
+            if (best == m || frac_less(e, best_e)) {
+                best = j;
+                best_e = e;
+            }
+        }
+        order[k] = (int32_t)best;
+        done[best] = 1;
+    }
+    free(done);
     return 0;
 }
 

@@ -294,3 +294,82 @@ def test_nonoverlap_periodic_and_cap():
     assert oracle.count_nonoverlap(b"abc", b"ab") == 0
     with pytest.raises(ValueError):
         oracle.count_nonoverlap(b"", b"abc")
+
+
+# ------------------------------------------------------------- bigram-aware order
+def test_bigram_counts_vs_bincount():
+    g = np.random.default_rng(3)
+    for n in (0, 1, 2, 3, 1000, 65_537):
+        t = g.integers(0, 256, size=n, dtype=np.uint8)
+        want = np.bincount(t[:-1].astype(np.int64) * 256 + t[1:], minlength=65536) if n > 1 else np.zeros(65536)
+        assert oracle.bigram(t).reshape(-1).tolist() == want.astype(np.uint64).tolist()
+    t = np.frombuffer(b"abab", dtype=np.uint8)
+    b = oracle.bigram(t)
+    assert b[ord("a"), ord("b")] == 2 and b[ord("b"), ord("a")] == 1 and int(b.sum()) == 3
+
+
+def test_bigram_order_qui_example():
+    """Section 2.2's example: u nearly always follows q, so q, i, u beats frequency order q, u, i."""
+    t = b"qui " * 10 + b"ii " * 20 + b"xu " * 5
+    h, bg = oracle.hist(t), oracle.bigram(t)
+    assert h[ord("q")] < h[ord("u")] < h[ord("i")]
+    assert oracle.order_freq(b"qui", h).tolist() == [0, 1, 2]
+    assert oracle.order_bigram(b"qui", h, bg).tolist() == [0, 2, 1]
+
+
+def test_bigram_order_reduces_to_frequency_under_independence():
+    """With bigram[a][b] = h_a h_b and hist = h * sum(h), every conditional estimate equals the
+    unconditional one, so the order is the frequency order (ties by position)."""
+    g = np.random.default_rng(11)
+    for trial in range(40):
+        hs = np.zeros(256, dtype=np.uint64)
+        syms = g.choice(256, size=int(g.integers(2, 12)), replace=False)
+        hs[syms] = g.integers(1, 50, size=syms.size).astype(np.uint64)
+        S = int(hs.sum())
+        bg = np.outer(hs, hs).astype(np.uint64)
+        h = hs * np.uint64(S)
+        m = int(g.integers(1, 40))
+        p = bytes(g.choice(syms, size=m).astype(np.uint8))
+        assert oracle.order_bigram(p, h, bg).tolist() == oracle.order_freq(p, h).tolist(), trial
+
+
+def _tables(pairs, hist):
+    bg = np.zeros((256, 256), dtype=np.uint64)
+    for (a, b), v in pairs.items():
+        bg[ord(a), ord(b)] = v
+    h = np.zeros(256, dtype=np.uint64)
+    for a, v in hist.items():
+        h[ord(a)] = v
+    return h, bg
+
+
+def test_bigram_order_backward_conditional_uses_column_sums():
+    # p = "xab": b is rarest; then a (right neighbour b compared) has e = bg[a][b] / col(b) = 5/10,
+    # x has e = hist[x] / total = 30/100, so x comes before a.  With row(a) = 100 instead of
+    # col(b) a would come first.
+    h, bg = _tables({("a", "b"): 5, ("z", "b"): 5, ("a", "z"): 95}, {"x": 30, "a": 60, "b": 10})
+    assert oracle.order_bigram(b"xab", h, bg).tolist() == [2, 0, 1]
+
+
+def test_bigram_order_both_neighbours_take_the_smaller_estimate():
+    # p = "uvwxy": w (rarest) first, then u; then v has both neighbours compared:
+    # min(bg[u][v]/row(u), bg[v][w]/col(w)) = min(0.9, 0.1) = 0.1, which beats x at bg[w][x]/row(w)
+    # = 0.2 and y at 0.5.
+    h, bg = _tables({("u", "v"): 9, ("u", "q"): 1, ("v", "w"): 1, ("q", "w"): 9, ("w", "x"): 2,
+                     ("w", "q"): 8},
+                    {"u": 1, "v": 40, "w": 0, "x": 40, "y": 50})
+    assert oracle.order_bigram(b"uvwxy", h, bg).tolist() == [2, 0, 1, 3, 4]
+
+
+def test_bigram_order_is_a_permutation_and_result_invariant():
+    g = np.random.default_rng(5)
+    t = g.integers(0, 6, size=5000, dtype=np.uint8)
+    h, bg = oracle.hist(t), oracle.bigram(t)
+    for m in (1, 2, 7, 40):
+        p = bytes(t[100:100 + m])
+        o = oracle.order_bigram(p, h, bg)
+        assert sorted(o.tolist()) == list(range(m))
+        for r in (1, 2, min(m, 5)):
+            assert oracle.alg4_count(p, t, o, r) == oracle.count(p, t)
+    with pytest.raises(ValueError):
+        oracle.order_bigram(b"", h, bg)

@@ -25,6 +25,11 @@ MUTANTS = {
                                "            found |= simd_compare(t, i, nvalid, p, j);\n            if (found == 0)"),
     "alg4_inverted_exit": ("        if (found == 0)\n            continue;", "        if (found != 0)\n            continue;"),
     "alg4_window_off_by_one": ("if (t[i + k + j] == p[j])", "if (t[i + k + j] == p[j ? j - 1 : 0])"),
+    "bigram_row_for_backward": ("er = frac_of(bigram[(uint64_t)p[j] * 256 + p[j + 1]], col[p[j + 1]]);",
+                                "er = frac_of(bigram[(uint64_t)p[j] * 256 + p[j + 1]], row[p[j]]);"),
+    "bigram_max_of_neighbours": ("(frac_less(er, el) ? er : el)", "(frac_less(er, el) ? el : er)"),
+    "bigram_ignores_conditionals": ("            if (left || right) {\n                frac_t el",
+                                    "            if (0) {\n                frac_t el"),
     "nonoverlap_resume_early": ("            s += m;\n", "            s += m - 1 + (m == 1);\n"),
 }
 
