@@ -546,6 +546,79 @@ def run_small(args):
     return lines
 
 
+# ---------------------------------------------------------------------- bigram
+def run_bigram(args):
+    """Compare orders on a correlated text: an order-1 Markov text over 26 letters and space (1 GiB),
+    20 substring patterns for each m in {4, 8, 16, 32, 64}; count-kernel time per order."""
+    import torch
+
+    import oracle
+    import paper_1612_01506_amd as sm
+    import synth
+
+    dev = torch.device("cuda:0")
+    n = args.n
+    t0 = time.time()
+    t_host = synth.markov_text(n, family=8, stream=0)
+    log(f"[bench] markov text {n} B in {time.time() - t0:.1f}s")
+    t_dev = torch.from_numpy(t_host).to(dev)
+    text = sm.Text(t_dev)
+    bg_dev = sm.bigram(t_dev, text.hist)                       # pair counts (first call also warms up)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        sm.bigram(t_dev, text.hist)
+    e1.record()
+    torch.cuda.synchronize()
+    bigram_us = e0.elapsed_time(e1) * 1e3 / 3
+    text._bigram = bg_dev.cpu().numpy().view(np.uint64).copy()
+    g = synth.rng(8, 1)
+    ms = (4, 8, 16, 32, 64)
+    pats = [synth.substring_pattern(t_host, m, g)[0] for m in ms for _ in range(20)]
+    res = {}
+    counts_by_order = {}
+    for kind in ("ltr", "h", "freq", "bigram"):
+        if kind == "ltr":
+            orders = None
+        elif kind == "bigram":
+            orders = [sm.order("bigram", p, text.hist, text.bigram) for p in pats]
+        else:
+            orders = [sm.order(kind, p, text.hist) for p in pats]
+        ps = sm.Patterns(pats, orders)
+        out = torch.zeros(len(pats), dtype=torch.int64, device=dev)
+        for i in range(len(pats)):
+            ps.count_async(i, t_dev, out[i:i + 1], peel=2)
+        out.zero_()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in pats]
+        for i in range(len(pats)):
+            ev[i][0].record()
+            ps.count_async(i, t_dev, out[i:i + 1], peel=2)
+            ev[i][1].record()
+        torch.cuda.synchronize()
+        counts_by_order[kind] = out.cpu().numpy()
+        per_m = {}
+        for i, p in enumerate(pats):
+            per_m.setdefault(len(p), []).append(ev[i][0].elapsed_time(ev[i][1]))
+        res[kind] = {m: round(n / (np.mean(v) * 1e-3) / 1e9, 1) for m, v in per_m.items()}
+        ps.close()
+    for kind in counts_by_order:
+        assert np.array_equal(counts_by_order[kind], counts_by_order["ltr"]), kind
+    for k in range(0, len(pats), 20):
+        assert oracle.count(pats[k], t_host) == counts_by_order["bigram"][k], ("oracle", len(pats[k]))
+    mean = {k: round(float(np.mean(list(v.values()))), 1) for k, v in res.items()}
+    return [{
+        "metric": "text GB/s per search (% HBM peak)", "unit": "GB/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "value": mean["bigram"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic (seeded order-1 Markov text over 26 letters and space; substring patterns)",
+        "ms_per_step": None,
+        "config": {"workload": f"bigram: {n}-byte order-1 Markov text, 20 substrings for each m in {{4..64}}, "
+                               "peel 2, count kernel time per compare order",
+                   "GBps_by_order_and_m": res, "mean_GBps_by_order": mean,
+                   "bigram_table_us": round(bigram_us, 1)},
+    }]
+
+
 # ------------------------------------------------------------------ nonoverlap
 def run_nonoverlap(args):
     """Disjoint-occurrence counts (greedy leftmost) beside the all-starts counts: the 1 GiB Zipf text
@@ -707,7 +780,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="zipf", choices=["zipf", "batched", "serve", "single", "small", "nonoverlap"])
+    ap.add_argument("--workload", default="zipf", choices=["zipf", "batched", "serve", "single", "small", "nonoverlap", "bigram"])
     ap.add_argument("--reps", type=int, default=1000, help="single: searches timed per form")
     ap.add_argument("--rates", type=float, nargs="+", default=[200, 1000, 5000, 20000, 50000, 100000],
                     help="serve: offered loads in requests/s")
@@ -735,7 +808,7 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     res = {"zipf": run_zipf, "batched": run_batched, "serve": run_serve, "single": run_single,
-           "small": run_small, "nonoverlap": run_nonoverlap}[args.workload](args)
+           "small": run_small, "nonoverlap": run_nonoverlap, "bigram": run_bigram}[args.workload](args)
     for r in (res if isinstance(res, list) else [res]):
         print(json.dumps(r), flush=True)
 

@@ -106,6 +106,29 @@ int32_t sm_histogram(const uint8_t *t, uint64_t n, uint64_t *hist_dev, void *str
  *   order_out: host, m x int32. */
 int32_t sm_order(int32_t kind, const uint8_t *p, uint64_t m, const uint64_t *hist_host, int32_t *order_out);
 
+/* Adjacent-pair counts, the statistics of the bigram-aware order below.
+ * bigram_dev: device, 65536 x uint64, overwritten with [a * 256 + b] =
+ * #{s : t[s] == a, t[s+1] == b}.  hist_host (optional, host 256 x uint64, the
+ * text's histogram) lets the library skip the pass over first symbols that
+ * do not occur (one pass per half of the byte range otherwise).
+ * Asynchronous on `stream`.  t: device, n bytes. */
+int32_t sm_bigram(const uint8_t *t, uint64_t n, const uint64_t *hist_host, uint64_t *bigram_dev, void *stream);
+
+/* Bigram-aware compare order (host, synchronous).  Section 2.2 observes that
+ * frequency order compares 'qui' as q, u, i although q, i, u is better, since
+ * u nearly always follows q, and mentions comparing next the position least
+ * likely to match given those already compared.  On adjacent pairs: the next
+ * position is the uncompared one with the smallest estimated match
+ * probability -- bigram[a][b] / (row sum of a) from a compared left neighbour
+ * a, bigram[a][b] / (column sum of b) from a compared right neighbour b, the
+ * smaller of the two when both are compared, else hist[x] / (sum of hist); a
+ * zero denominator counts as 0; fractions are compared exactly; ties keep
+ * increasing position.  Only the speed depends on the order.
+ *   p: host, m bytes.  hist_host: host 256 x uint64.  bigram_host: host
+ *   65536 x uint64 as written by sm_bigram.  order_out: host, m x int32. */
+int32_t sm_order_bigram(const uint8_t *p, uint64_t m, const uint64_t *hist_host, const uint64_t *bigram_host,
+                        int32_t *order_out);
+
 /* ------------------------------------------------------- single search */
 
 /* Count (Section 1; Algorithm 4 of Section 2.3 with pi = order, r = default):

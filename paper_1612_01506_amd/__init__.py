@@ -25,7 +25,7 @@ from ._lib import (SM_NONOVERLAP, SM_ORDER_FREQ, SM_ORDER_H, SM_ORDER_HS, SM_ORD
                    sm_params, sm_query, sm_text)
 
 __all__ = ["Text", "PackedTexts", "Patterns", "SmError", "histogram", "order", "count", "count_async", "report",
-           "report_async", "count_batch", "BatchPlan", "version", "device_cus"]
+           "report_async", "count_batch", "BatchPlan", "bigram", "version", "device_cus"]
 
 ORDER_KINDS = {"ltr": SM_ORDER_LTR, "freq": SM_ORDER_FREQ, "h": SM_ORDER_H, "hs": SM_ORDER_HS}
 
@@ -90,6 +90,7 @@ class Text:
         _dev_text(t)
         self.t = t
         self._hist: np.ndarray | None = None
+        self._bigram: np.ndarray | None = None
 
     @property
     def n(self) -> int:
@@ -100,6 +101,13 @@ class Text:
         if self._hist is None:
             self._hist = histogram(self.t).cpu().numpy().view(np.uint64).copy()
         return self._hist
+
+    @property
+    def bigram(self) -> np.ndarray:
+        """(256, 256) adjacent-pair counts, computed on the device once."""
+        if self._bigram is None:
+            self._bigram = bigram(self.t, self.hist).cpu().numpy().view(np.uint64).copy()
+        return self._bigram
 
 
 def version() -> int:
@@ -119,8 +127,20 @@ def histogram(t, stream=None) -> torch.Tensor:
     return out
 
 
-def order(kind: str, p, hist=None) -> np.ndarray:
-    """Compare order pi (0-based permutation): 'ltr', 'freq' (needs hist), 'h' or 'hs'."""
+def bigram(t, hist=None, stream=None) -> torch.Tensor:
+    """Adjacent-pair counts: (256, 256) device int64 tensor, [a, b] = #{s : t[s] == a, t[s+1] == b}
+    (asynchronous).  hist (the text's host histogram), if given, lets empty passes be skipped."""
+    ptr, n = _dev_text(t)
+    dev = t.t.device if isinstance(t, Text) else t.device
+    h = None if hist is None else np.ascontiguousarray(np.asarray(hist).astype(np.uint64))
+    out = torch.empty((256, 256), dtype=torch.int64, device=dev)
+    check(load().sm_bigram(ptr, n, _ptr(h), out.data_ptr(), _stream(stream)))
+    return out
+
+
+def order(kind: str, p, hist=None, bigram=None) -> np.ndarray:
+    """Compare order pi (0-based permutation): 'ltr', 'freq' (needs hist), 'h', 'hs' or 'bigram'
+    (needs hist and the (256, 256) pair counts)."""
     a = _pat(p)
     if a.size == 0:
         raise ValueError("pattern length must be >= 1")
@@ -130,6 +150,14 @@ def order(kind: str, p, hist=None) -> np.ndarray:
         if h.size != 256:
             raise ValueError("hist must have 256 entries")
     out = np.empty(a.size, dtype=np.int32)
+    if kind == "bigram":
+        if h is None or bigram is None:
+            raise ValueError("the bigram order needs hist and bigram")
+        bg = np.ascontiguousarray(np.asarray(bigram).astype(np.uint64)).reshape(-1)
+        if bg.size != 65536:
+            raise ValueError("bigram must have 256 x 256 entries")
+        check(load().sm_order_bigram(_ptr(a), a.size, _ptr(h), _ptr(bg), out.ctypes.data))
+        return out
     check(load().sm_order(ORDER_KINDS[kind], _ptr(a), a.size, _ptr(h), out.ctypes.data))
     return out
 
@@ -138,9 +166,11 @@ def _resolve_order(order_arg, p: np.ndarray, text) -> np.ndarray | None:
     if order_arg is None or (isinstance(order_arg, str) and order_arg == "ltr"):
         return None
     if isinstance(order_arg, str):
-        if order_arg == "freq":
+        if order_arg in ("freq", "bigram"):
             if not isinstance(text, Text):
                 text = Text(text)
+            if order_arg == "bigram":
+                return order("bigram", p, text.hist, text.bigram)
             return order("freq", p, text.hist)
         return order(order_arg, p)
     o = np.ascontiguousarray(np.asarray(order_arg, dtype=np.int32))

@@ -21,7 +21,7 @@ EXPORTS = (
     "sm_count", "sm_count_ex", "sm_count_async", "sm_report", "sm_report_ex", "sm_count_batch",
     "sm_patterns_create", "sm_patterns_destroy", "sm_patterns_count", "sm_patterns_report",
     "sm_report_async", "sm_patterns_report_async", "sm_patterns_create_ordered",
-    "sm_batch_create", "sm_batch_run", "sm_batch_destroy",
+    "sm_batch_create", "sm_batch_run", "sm_batch_destroy", "sm_bigram", "sm_order_bigram",
 )
 
 
@@ -75,6 +75,8 @@ def load() -> ctypes.CDLL:
         "sm_batch_create": ([P(sm_query), u64, P(sm_text), u64, P(sm_params), P(vp)], i32),
         "sm_batch_run": ([vp, vp, vp], i32),
         "sm_batch_destroy": ([vp], i32),
+        "sm_bigram": ([vp, u64, vp, vp, vp], i32),
+        "sm_order_bigram": ([vp, u64, vp, vp, vp], i32),
         "sm_patterns_destroy": ([vp], i32),
         "sm_patterns_create_ordered": ([u64, P(vp), P(u64), i32, vp, P(vp)], i32),
         "sm_patterns_count": ([vp, u64, vp, u64, P(sm_params), vp, vp], i32),

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <deque>
 #include <functional>
+#include <queue>
 #include <thread>
 #include <memory>
 #include <mutex>
@@ -355,6 +356,84 @@ void order_freq_sparse(const uint64_t *hist, const uint8_t *p, uint64_t m, int32
 
 // Patterns of at least this total length against one histogram share a FreqRanks.
 constexpr uint64_t kRanksMinBytes = 1024;
+
+// Bigram-aware order (the conditional-probability strategy Section 2.2
+// discusses, on adjacent pairs): repeatedly compare next the position with
+// the smallest estimated match probability given the compared positions --
+// the forward conditional bigram[a][b] / row(a) from a compared left
+// neighbour a, the backward one bigram[a][b] / col(b) from a compared right
+// neighbour b, the smaller when both are compared, else hist[x] / total; a
+// zero denominator gives 0.  Exact fraction comparisons, ties by position.
+// A heap with per-position versions gives O(m log m).
+struct Frac {
+    uint64_t num, den;
+};
+
+bool frac_lt(Frac x, Frac y)
+{
+    return (unsigned __int128)x.num * y.den < (unsigned __int128)y.num * x.den;
+}
+
+Frac make_frac(uint64_t num, uint64_t den)
+{
+    return den ? Frac{num, den} : Frac{0, 1};
+}
+
+void order_bigram(const uint8_t *p, uint64_t m, const uint64_t *hist, const uint64_t *bigram, int32_t *o)
+{
+    uint64_t total = 0, row[256] = {}, col[256] = {};
+    for (int a = 0; a < 256; ++a)
+        total += hist[a];
+    for (int a = 0; a < 256; ++a)
+        for (int b = 0; b < 256; ++b) {
+            row[a] += bigram[a * 256 + b];
+            col[b] += bigram[a * 256 + b];
+        }
+    std::vector<uint8_t> done(m, 0);
+    std::vector<uint32_t> version(m, 0);
+    auto estimate = [&](uint64_t j) -> Frac {
+        const bool left = j > 0 && done[j - 1], right = j + 1 < m && done[j + 1];
+        if (!left && !right)
+            return make_frac(hist[p[j]], total);
+        Frac el{0, 1}, er{0, 1};
+        if (left)
+            el = make_frac(bigram[(uint64_t)p[j - 1] * 256 + p[j]], row[p[j - 1]]);
+        if (right)
+            er = make_frac(bigram[(uint64_t)p[j] * 256 + p[j + 1]], col[p[j + 1]]);
+        return !right ? el : !left ? er : (frac_lt(er, el) ? er : el);
+    };
+    struct Item {
+        Frac e;
+        uint64_t j;
+        uint32_t ver;
+    };
+    auto after = [](const Item &x, const Item &y) {  // heap order: smallest (e, j) on top
+        if (frac_lt(x.e, y.e))
+            return false;
+        if (frac_lt(y.e, x.e))
+            return true;
+        return x.j > y.j;
+    };
+    std::priority_queue<Item, std::vector<Item>, decltype(after)> heap(after);
+    for (uint64_t j = 0; j < m; ++j)
+        heap.push({estimate(j), j, 0});
+    for (uint64_t k = 0; k < m; ++k) {
+        Item it = heap.top();
+        heap.pop();
+        while (done[it.j] || it.ver != version[it.j]) {
+            it = heap.top();
+            heap.pop();
+        }
+        o[k] = (int32_t)it.j;
+        done[it.j] = 1;
+        for (int dj = -1; dj <= 1; dj += 2) {
+            const int64_t nj = (int64_t)it.j + dj;
+            if (nj < 0 || (uint64_t)nj >= m || done[nj])
+                continue;
+            heap.push({estimate((uint64_t)nj), (uint64_t)nj, ++version[nj]});
+        }
+    }
+}
 
 // Section 2.4, 1-based listing 1, m, 4, 7, ..., 3, 6, ..., 2, 5, ...: position 1,
 // position m, then the residue chains 1, 0, 2 (mod 3) upward from 4, 3, 2,
@@ -1360,6 +1439,52 @@ int32_t sm_histogram(const uint8_t *t, uint64_t n, uint64_t *hist_dev, void *str
     const uint64_t grid =
         std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(nchunks, kHistWG), (uint64_t)std::max(d->cus, 1) * 2));
     HIP_TRY(launch_hist(tv, h, (unsigned)grid, s));
+    return SM_OK;
+}
+
+int32_t sm_bigram(const uint8_t *t, uint64_t n, const uint64_t *hist_host, uint64_t *bigram_dev, void *stream)
+{
+    g_err.clear();
+    SM_TRY(check_text(t, n));
+    if (!bigram_dev)
+        return fail(SM_EINVAL, "bigram_dev is NULL");
+    Dev *d;
+    SM_TRY(get_dev(&d));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    unsigned long long *out = reinterpret_cast<unsigned long long *>(bigram_dev);
+    HIP_TRY(launch_fill_u64(out, 65536, 0ull, s));
+    if (n < 2)
+        return SM_OK;
+    const TextView tv = make_view(t, n);
+    const uint64_t nchunks = tv.end16 / 16;
+    const unsigned grid =
+        (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(nchunks, kBgWG), (uint64_t)std::max(d->cus, 1)));
+    for (uint32_t half = 0; half < 2; ++half) {
+        if (hist_host) {  // skip a half whose first symbols do not occur
+            uint64_t c = 0;
+            for (int b = 128 * (int)half; b < 128 * (int)half + 128; ++b)
+                c += hist_host[b];
+            if (c == 0)
+                continue;
+        }
+        HIP_TRY(launch_bigram(tv, half, out, grid, s));
+    }
+    return SM_OK;
+}
+
+int32_t sm_order_bigram(const uint8_t *p, uint64_t m, const uint64_t *hist_host, const uint64_t *bigram_host,
+                        int32_t *order_out)
+{
+    g_err.clear();
+    if (m == 0 || m >= (1ull << 31))
+        return fail(SM_EINVAL, "pattern length m must be in 1..2^31-1");
+    if (!p || !order_out || !hist_host || !bigram_host)
+        return fail(SM_EINVAL, "p, hist_host, bigram_host and order_out must not be NULL");
+    try {
+        order_bigram(p, m, hist_host, bigram_host, order_out);
+    } catch (const std::bad_alloc &) {
+        return fail(SM_ENOMEM, "bigram order: out of host memory");
+    }
     return SM_OK;
 }
 

@@ -11,6 +11,8 @@ constexpr uint32_t kWG = 256;            // threads per workgroup: four wave64
 constexpr uint32_t kWaves = kWG / 64;
 constexpr uint32_t kHistWG = 1024;        // histogram workgroup: 16 waves sharing 64 lane copies
 constexpr uint32_t kHistLds = 256 * 64 * 4;
+constexpr uint32_t kBgWG = 1024;          // adjacent-pair counts: one 16-wave workgroup per CU
+constexpr uint32_t kBgLds = 128 * 256 * 4; // half of the 256 x 256 table per pass
 constexpr uint32_t kBlock = 1024;        // starts per wave vector: 64 lanes x 4 dwords x 4 bytes
 constexpr uint32_t kMaxPeel = 8;         // largest peel factor r compiled in
 constexpr uint32_t kStepPad = 8;         // zero entries after every step table (one-ahead loads)
@@ -137,6 +139,7 @@ hipError_t launch_no_chunk_counts(const uint32_t *mark, uint64_t c, unsigned lon
 hipError_t launch_no_compact(const unsigned long long *pos, const uint32_t *mark, uint64_t c,
                              const unsigned long long *go, uint64_t ng, unsigned long long *out, uint64_t cap,
                              hipStream_t s);
+hipError_t launch_bigram(const TextView &tv, uint32_t half, unsigned long long *out, unsigned grid, hipStream_t s);
 // Sets the dynamic-LDS limits of all kernels on the current device.
 hipError_t prime_kernel_attrs();
 

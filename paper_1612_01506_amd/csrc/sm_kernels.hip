@@ -743,6 +743,60 @@ __global__ __launch_bounds__(kHistWG) void k_hist(TextView tv, unsigned long lon
         atomicAdd(&hist[bin], (unsigned long long)sum);
 }
 
+// Adjacent-pair counts for the bigram-aware compare order: out[a * 256 + b]
+// += number of s with t[s] == a, t[s+1] == b, for the first symbols a in
+// [128 * half, 128 * half + 128).  A 1024-thread workgroup (one per CU) keeps
+// that half of the table, 128 x 256 counters, in LDS and adds its nonzero
+// counters to the global table at the end.  Each thread takes 16-byte chunks;
+// the byte after a chunk comes from a one-byte load (usually cached).
+__device__ __forceinline__ void bigram_add(uint32_t *tab, uint32_t half, uint32_t a, uint32_t b)
+{
+    if ((a >> 7) == half)
+        atomicAdd(&tab[((a & 127u) << 8) | b], 1u);
+}
+
+__global__ __launch_bounds__(kBgWG) void k_bigram(TextView tv, uint32_t half, unsigned long long *out)
+{
+    extern __shared__ __align__(16) uint32_t tab[];  // [128][256]
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t i = tid; i < 128u * 256u / 4u; i += kBgWG)
+        reinterpret_cast<uint4 *>(tab)[i] = make_uint4(0, 0, 0, 0);
+    __syncthreads();
+    const uint64_t lo = tv.first, hi = tv.first + tv.n;  // pairs start at s in [lo, hi - 1)
+    if (hi >= lo + 2) {
+        const uint64_t c0 = lo / 16u, c1 = (hi - 2) / 16u + 1;  // chunks holding a pair start
+        for (uint64_t c = c0 + (uint64_t)blockIdx.x * kBgWG + tid; c < c1; c += (uint64_t)gridDim.x * kBgWG) {
+            const uint64_t u = 16u * c;
+            const uint4 v = *reinterpret_cast<const uint4 *>(tv.base + u);
+            const uint32_t nb = u + 16u < hi ? (uint32_t)tv.base[u + 16u] : 0u;
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+            if (u >= lo && u + 16u < hi) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const uint32_t a = (w[i >> 2] >> (8 * (i & 3))) & 0xFFu;
+                    const uint32_t b = i < 15 ? (w[(i + 1) >> 2] >> (8 * ((i + 1) & 3))) & 0xFFu : nb;
+                    bigram_add(tab, half, a, b);
+                }
+            } else {
+                for (int i = 0; i < 16; ++i) {
+                    const uint64_t s = u + (uint64_t)i;
+                    if (s < lo || s + 1u >= hi)
+                        continue;
+                    const uint32_t a = (w[i >> 2] >> (8 * (i & 3))) & 0xFFu;
+                    const uint32_t b = i < 15 ? (w[(i + 1) >> 2] >> (8 * ((i + 1) & 3))) & 0xFFu : nb;
+                    bigram_add(tab, half, a, b);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < 128u * 256u; i += kBgWG) {
+        const uint32_t v = tab[i];
+        if (v)
+            atomicAdd(&out[(uint64_t)half * 32768u + i], (unsigned long long)v);
+    }
+}
+
 // Zeroes the per-vector counts (16-byte stores; bc is 16-byte aligned) and the group sums.
 __global__ void k_fill_report(uint32_t *bc, uint64_t n, unsigned long long *gs, uint64_t ng)
 {
@@ -1185,6 +1239,12 @@ hipError_t launch_hist(const TextView &tv, unsigned long long *hist, unsigned gr
     return hipGetLastError();
 }
 
+hipError_t launch_bigram(const TextView &tv, uint32_t half, unsigned long long *out, unsigned grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bigram, dim3(grid), dim3(kBgWG), kBgLds, s, tv, half, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v, hipStream_t s)
 {
     const uint64_t g = (n + 255) / 256;
@@ -1302,6 +1362,8 @@ hipError_t prime_kernel_attrs()
     if ((e = lds_attr(&k_report_write, (int)kMaxLds)) != hipSuccess)
         return e;
     if ((e = lds_attr(&k_hist, (int)kHistLds)) != hipSuccess)
+        return e;
+    if ((e = lds_attr(&k_bigram, (int)kBgLds)) != hipSuccess)
         return e;
     return lds_attr(&k_batch_bitmap, (int)kBmMaxLds);
 }

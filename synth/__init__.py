@@ -15,7 +15,10 @@ sources with matching alphabet sizes:
 * sigma = 4: ACGT uniform (stand-in for E.coli);
 * sigma = 20: the 20 one-letter amino-acid codes (stand-in for the protein file);
 * sigma = 2: {'0', '1'} uniform (adversarial small alphabet);
-* periodic texts u^q (closed-form counts, long partial matches).
+* periodic texts u^q (closed-form counts, long partial matches);
+* an order-1 Markov text over 26 letters and space whose rows are Zipf laws
+  over seeded permutations (adjacent symbols strongly correlated, as in
+  natural language; used to measure the bigram-aware compare order).
 
 Bytes are produced by a counter-based splitmix64 hash (Steele, Lea and Flood,
 OOPSLA 2014): byte i depends only on (key, i), so a GiB-scale text can be made
@@ -94,6 +97,9 @@ def _lib():
     lib.synth_text.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_char_p,
                                ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
     lib.synth_text.restype = None
+    lib.synth_markov.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_char_p,
+                                 ctypes.c_void_p, ctypes.c_int]
+    lib.synth_markov.restype = None
     return lib
 
 
@@ -147,6 +153,55 @@ def periodic_text(n: int, unit: bytes) -> np.ndarray:
     u = np.frombuffer(unit, dtype=np.uint8)
     reps = -(-n // len(u)) if n else 0
     return np.tile(u, reps)[:n].copy()
+
+
+LETTERS = b"abcdefghijklmnopqrstuvwxyz "
+
+
+def markov_thresholds(sigma: int = 27, s: float = 1.3, family: int = 8, stream: int = 0) -> np.ndarray:
+    """(sigma, sigma-1) uint32 inverse-CDF rows: row a is Zipf(s) over a seeded permutation of the
+    successors, so each symbol has a few likely followers."""
+    g = rng(family, 20_000 + stream)
+    k = np.arange(1, sigma + 1, dtype=np.float64)
+    rows = []
+    for _ in range(sigma):
+        pk = k ** (-float(s))
+        pk /= pk.sum()
+        probs = np.empty(sigma)
+        probs[g.permutation(sigma)] = pk           # rank r -> a seeded successor
+        c = np.cumsum(probs)[:-1]
+        rows.append(np.minimum(np.rint(c * 2.0**32), 2.0**32 - 1).astype(np.uint64).astype(np.uint32))
+    return np.stack(rows)
+
+
+def markov_text(n: int, family: int = 8, stream: int = 0, s: float = 1.3) -> np.ndarray:
+    """Order-1 Markov text over LETTERS (bulk C path; sequential)."""
+    thr = np.ascontiguousarray(markov_thresholds(len(LETTERS), s, family, stream))
+    out = np.empty(n, dtype=np.uint8)
+    if n:
+        _lib().synth_markov(out.ctypes.data, n, stream_key(family, stream) & (2**64 - 1), LETTERS,
+                            thr.ctypes.data, len(LETTERS))
+    return out
+
+
+def markov_text_numpy(n: int, family: int = 8, stream: int = 0, s: float = 1.3) -> np.ndarray:
+    """Reference (Python loop) form of markov_text, for small n."""
+    thr = markov_thresholds(len(LETTERS), s, family, stream)
+    key = np.uint64(stream_key(family, stream))
+    i = np.arange(1, n + 1, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = key + i * _GAMMA
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        z = z ^ (z >> np.uint64(31))
+    u = (z >> np.uint64(32)).astype(np.uint32)
+    sym = np.frombuffer(LETTERS, dtype=np.uint8)
+    out = np.empty(n, dtype=np.uint8)
+    x = 0
+    for j in range(n):
+        x = int(np.searchsorted(thr[x], u[j], side="right"))
+        out[j] = sym[x]
+    return out
 
 
 # -------------------------------------------------------------------------- patterns

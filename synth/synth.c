@@ -16,6 +16,7 @@
  */
 #include <stdint.h>
 #include <stddef.h>
+#include <stdlib.h>
 
 static inline uint64_t mix64(uint64_t z)
 {
@@ -43,4 +44,42 @@ void synth_text(uint8_t *out, uint64_t n, uint64_t key, const uint8_t *symbols,
         }
         out[i] = symbols[lo];
     }
+}
+
+/* Order-1 Markov text: byte i is symbols[x_i], where x_i is drawn by inverse
+ * CDF from row x_{i-1} of a transition table (x_{-1} = 0) with the same
+ * counter-based uniform u_i as above.  thr holds nsym rows of nsym - 1
+ * non-decreasing thresholds.  Sequential: each byte depends on the previous. */
+void synth_markov(uint8_t *out, uint64_t n, uint64_t key, const uint8_t *symbols, const uint32_t *thr, int nsym)
+{
+    /* guide table: for each row and each value of the top 12 bits of u, the
+     * number of thresholds below that 2^20-wide bucket; the exact count then
+     * needs a short forward scan (the same result as a binary search) */
+    enum { GB = 12 };
+    const int nthr = nsym - 1;
+    uint8_t *guide = (uint8_t *)malloc((size_t)nsym << GB);
+    if (!guide)
+        return;
+    for (int r = 0; r < nsym; ++r) {
+        const uint32_t *row = thr + (size_t)r * (size_t)nthr;
+        int k = 0;
+        for (uint32_t b = 0; b < (1u << GB); ++b) {
+            const uint32_t lo = b << (32 - GB);
+            while (k < nthr && row[k] < lo)
+                ++k;
+            guide[((size_t)r << GB) + b] = (uint8_t)k;
+        }
+    }
+    int x = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+        uint64_t z = key + (i + 1) * 0x9E3779B97F4A7C15ULL;
+        uint32_t u = (uint32_t)(mix64(z) >> 32);
+        const uint32_t *row = thr + (size_t)x * (size_t)nthr;
+        int k = guide[((size_t)x << GB) + (u >> (32 - GB))];
+        while (k < nthr && row[k] <= u)
+            ++k;
+        x = k;
+        out[i] = symbols[x];
+    }
+    free(guide);
 }

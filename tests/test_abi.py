@@ -126,3 +126,36 @@ def test_freq_order_ties_and_skew():
     big[ord("y")] = 3
     for p in (b"axbyxa", b"yyxxaa" * 200):
         assert sm.order("freq", p, big).tolist() == oracle.order_freq(p, big).tolist()
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_library_bigram_order_matches_oracle(seed):
+    """The library's heap-based bigram order equals the oracle's direct definition."""
+    g = np.random.default_rng(seed)
+    sigma = [2, 4, 20, 95, 256, 3][seed]
+    # a correlated text: each symbol mostly followed by one favourite successor
+    fav = g.integers(0, sigma, size=sigma)
+    t = np.empty(20_000, dtype=np.int64)
+    t[0] = 0
+    r = g.random(t.size)
+    x = g.integers(0, sigma, size=t.size)
+    for i in range(1, t.size):
+        t[i] = fav[t[i - 1]] if r[i] < 0.6 else x[i]
+    t = (t % 256).astype(np.uint8)
+    h, bg = oracle.hist(t), oracle.bigram(t)
+    for m in (1, 2, 3, 8, 33, 200, 1500):
+        o = g.integers(0, t.size - m)
+        p = bytes(t[o:o + m]) if g.random() < 0.8 else bytes(g.integers(0, 256, size=m, dtype=np.uint8))
+        assert sm.order("bigram", p, h, bg).tolist() == oracle.order_bigram(p, h, bg).tolist(), (seed, m)
+
+
+def test_bigram_order_validation():
+    lib = _lib.load()
+    p = np.frombuffer(b"abc", dtype=np.uint8)
+    h = np.ones(256, dtype=np.uint64)
+    out = np.zeros(3, dtype=np.int32)
+    assert "NULL" in _err(lib.sm_order_bigram(p.ctypes.data, 3, h.ctypes.data, None, out.ctypes.data))
+    assert "m must be" in _err(lib.sm_order_bigram(p.ctypes.data, 0, h.ctypes.data, h.ctypes.data, out.ctypes.data))
+    with pytest.raises(ValueError):
+        sm.order("bigram", b"abc", h)
+    assert lib.sm_bigram(None, 0, None, None, None) == _lib.SM_EINVAL

@@ -592,3 +592,41 @@ def test_nonoverlap_patterns_and_rejections(dev):
     assert rc == sm._lib.SM_EINVAL and "synchronous" in lib.sm_last_error().decode()
     torch.cuda.synchronize()
     assert int(c.item()) == 0
+
+
+# ------------------------------------------------------------- bigram statistics
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 15, 16, 17, 31, 33, 4096, 100_003, 3_000_001])
+@pytest.mark.parametrize("offset", [0, 5, 15])
+def test_bigram_counts(dev, n, offset):
+    t = rand_text(n, 256, 31 * n + offset)
+    td = to_dev(t, dev, offset)
+    assert sm.bigram(td).cpu().numpy().astype(np.uint64).tolist() == oracle.bigram(t).tolist()
+
+
+def test_bigram_counts_skewed_and_one_half(dev):
+    """Zipf text over printable bytes (one pass skipped through the histogram), high bytes only,
+    a single repeated byte, and a text spanning many workgroups."""
+    for t in (synth.zipf_text(20_000_003, 95, 1.0, family=9, stream=5),
+              (rand_text(1_000_001, 256, 4) | np.uint8(0x80)),
+              np.full(2_000_001, 0xC3, dtype=np.uint8),
+              rand_text(50_000_017, 4, 8)):
+        td = sm.Text(to_dev(t, dev, 7))
+        want = oracle.bigram(t)
+        assert td.bigram.tolist() == want.tolist()
+        assert sm.bigram(td.t).cpu().numpy().astype(np.uint64).tolist() == want.tolist()
+
+
+def test_bigram_order_searches(dev):
+    """Counts and reports with the bigram order equal the oracle's (the order changes only speed)."""
+    g = np.random.default_rng(91)
+    t = synth.zipf_text(3_000_000, 95, 1.0, family=9, stream=6)
+    text = sm.Text(to_dev(t, dev, 3))
+    for m in (1, 2, 3, 5, 8, 16, 64, 300):
+        for _ in range(3):
+            p = pick_pattern(t, m, g)
+            o = sm.order("bigram", p, text.hist, text.bigram)
+            assert o.tolist() == oracle.order_bigram(p, oracle.hist(t), oracle.bigram(t)).tolist()
+            want = oracle.count(p, t)
+            assert sm.count(text, p, order="bigram") == want
+            assert sm.report(text, p, order="bigram").cpu().numpy().astype(np.uint64).tolist() == \
+                oracle.report(p, t).tolist()

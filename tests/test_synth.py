@@ -53,3 +53,17 @@ def test_pattern_helpers():
     q = synth.random_pattern(synth.ALPHABETS[95], 33, g)
     assert len(q) == 33 and set(q) <= set(synth.ALPHABETS[95])
     assert synth.periodic_text(7, b"ab").tobytes() == b"abababa"
+
+
+def test_markov_text_matches_reference_and_is_correlated():
+    a = synth.markov_text(20_000, family=8, stream=3)
+    assert a.tolist() == synth.markov_text_numpy(20_000, family=8, stream=3).tolist()
+    assert set(np.unique(a).tolist()) <= set(synth.LETTERS)
+    assert synth.markov_text(5000, stream=1).tolist() != synth.markov_text(5000, stream=2).tolist()
+    # adjacent symbols are far from independent: the most likely successor of the most frequent
+    # symbol is much likelier than that symbol's overall frequency
+    big = synth.markov_text(400_000, stream=0)
+    x = int(np.bincount(big).argmax())
+    nxt = big[1:][big[:-1] == x]
+    top = np.bincount(nxt, minlength=256).max() / nxt.size
+    assert top > 2 * np.bincount(big, minlength=256).max() / big.size
