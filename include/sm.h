@@ -72,7 +72,7 @@ extern "C" {
 typedef struct sm_params {
     int32_t peel;       /* r: compares done before the first zero test, 1..8 (Section 2.3); default 2 */
     int32_t tile_kib;   /* text bytes staged per workgroup tile: 4, 8 or 16 KiB; default by n      */
-    int32_t wgs_per_cu; /* workgroups per compute unit the grid is sized for, 1..32; default 6     */
+    int32_t wgs_per_cu; /* workgroups per compute unit the grid is sized for, 1..32; default 6 (8 for batched byte tiles) */
     int32_t flags;      /* 0 or SM_NONOVERLAP; other bits are rejected (SM_EINVAL)                 */
 } sm_params;
 

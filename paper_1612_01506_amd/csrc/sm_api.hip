@@ -961,7 +961,11 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
     const uint64_t T = 4096ull * cpl;
     const bool peel_given = params && params->peel > 0;
     const int rdef = peel_given ? std::min<int>(params->peel, (int)kMaxPeel) : 2;
-    const int wpc = (params && params->wgs_per_cu > 0) ? std::min(params->wgs_per_cu, 32) : 6;
+    // workgroups per CU: the byte-tile batch kernel measured best at 8 (short per-query work per
+    // tile needs more waves in flight); long queries run the single-search kernel, best at 6
+    const bool wpc_given = params && params->wgs_per_cu > 0;
+    const int wpc = wpc_given ? std::min(params->wgs_per_cu, 32) : 8;
+    const int wpc_long = wpc_given ? wpc : 6;
     const uint64_t target = (uint64_t)std::max(d.cus, 1) * (uint64_t)wpc;
     // two LDS tile buffers of T + halo and the query counters must fit
     const uint64_t max_halo = (kMaxLds - kQChunk * sizeof(uint32_t)) / 2 - T;
@@ -1300,7 +1304,7 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
         L.m = pq.m;
         L.steps_off = long_steps_off[i];
         L.out = pq.idx;
-        L.tu = Tune{(int)long_peel[i], 1, wpc, (int)kChunkLog2};
+        L.tu = Tune{(int)long_peel[i], 1, wpc_long, (int)kChunkLog2};
         lp->longs.push_back(L);
     }
     return SM_OK;
