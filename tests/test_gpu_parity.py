@@ -630,3 +630,44 @@ def test_bigram_order_searches(dev):
             assert sm.count(text, p, order="bigram") == want
             assert sm.report(text, p, order="bigram").cpu().numpy().astype(np.uint64).tolist() == \
                 oracle.report(p, t).tolist()
+
+
+# ------------------------------------------------------------- randomized sweep
+def test_random_sweep_all_entry_points(dev):
+    """Seeded random cases across alphabets, lengths, alignments, orders, peels and tile sizes, through
+    the synchronous, asynchronous, prepared-pattern and batched entry points, all against the oracle."""
+    g = np.random.default_rng(2024)
+    texts, hosts = [], []
+    for k in range(6):
+        n = int(synth.loguniform_ints(1, 3_000_000, 1, g)[0])
+        sigma = int(g.choice([1, 2, 3, 4, 20, 95, 256]))
+        t = (np.full(n, 0x41, dtype=np.uint8) if sigma == 1 else rand_text(n, sigma, 5000 + k))
+        hosts.append(t)
+        texts.append(sm.Text(to_dev(t, dev, int(g.integers(0, 16)))))
+    queries, want = [], []
+    for k in range(240):
+        ti = int(g.integers(0, len(hosts)))
+        t = hosts[ti]
+        m = int(synth.loguniform_ints(1, 5000, 1, g)[0])
+        p = pick_pattern(t, m, g, planted=g.random() < 0.75) if t.size else bytes([65] * m)
+        order = [None, "ltr", "freq", "h", "hs", "bigram"][k % 6]
+        peel = int(g.choice([1, 2, 3, 5, 8]))
+        tile = int(g.choice([4, 8, 16]))
+        c = oracle.count(p, t)
+        if k % 4 == 0:
+            assert sm.count(texts[ti], p, order=order, peel=peel, tile_kib=tile) == c, (k, ti, m)
+        elif k % 4 == 1:
+            out = torch.zeros(1, dtype=torch.int64, device=dev)
+            sm.count_async(texts[ti], p, out, order=order, peel=peel, tile_kib=tile)
+            assert int(out.item()) == c, (k, ti, m)
+        elif k % 4 == 2:
+            cap = int(g.integers(0, 50))
+            pos, total = sm.report(texts[ti], p, order=order, cap=cap, peel=peel, return_count=True)
+            assert total == c and pos.cpu().numpy().astype(np.uint64).tolist() == oracle.report(p, t, cap).tolist()
+        else:
+            assert sm.count(texts[ti], p, overlap=False) == oracle.count_nonoverlap(p, t), (k, ti, m)
+        queries.append((ti, p))
+        want.append(c)
+    assert sm.count_batch(texts, queries).cpu().tolist() == want
+    with sm.BatchPlan(texts, queries, peel=3, tile_kib=4) as plan:
+        assert plan.run().cpu().tolist() == want
