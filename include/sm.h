@@ -232,6 +232,21 @@ typedef struct sm_query {
 int32_t sm_count_batch(const sm_query *q, uint64_t nq, const sm_text *texts, uint64_t nt,
                        uint64_t *counts_dev, const sm_params *params, void *stream);
 
+/* Batched report (Section 2.1: the reporting version) of many queries in one
+ * pass per text and chunk: query i's min(total_i, caps[i]) smallest starts,
+ * strictly increasing, go to pos_dev + caps[0] + ... + caps[i-1] (device,
+ * caps[0] + ... + caps[nq-1] x uint64), and total_i, its full count, to
+ * totals_dev[i] (device, nq x uint64).  The queries of a text share the
+ * staged tiles of one launch, which also records each query's per-vector
+ * counts; each query's vectors with matches are then searched again and
+ * written in order, as in sm_report.  Queries, texts and orders as in
+ * sm_count_batch (the bitmap mode is not used).  caps: host, nq x uint64.
+ * Asynchronous on `stream`; host inputs are consumed before return.  Library
+ * scratch of about 4 bytes per 1024 text bytes per query is shared by all
+ * reporting batches on the device, which are ordered by an event. */
+int32_t sm_report_batch(const sm_query *q, uint64_t nq, const sm_text *texts, uint64_t nt, const uint64_t *caps,
+                        uint64_t *pos_dev, uint64_t *totals_dev, const sm_params *params, void *stream);
+
 /* A planned batch (Section 1 problem statement, one count per query, as
  * sm_count_batch).  sm_batch_create validates and plans the batch exactly as
  * sm_count_batch does and uploads its tables (step tables, tile and query

@@ -25,7 +25,7 @@ from ._lib import (SM_NONOVERLAP, SM_ORDER_FREQ, SM_ORDER_H, SM_ORDER_HS, SM_ORD
                    sm_params, sm_query, sm_text)
 
 __all__ = ["Text", "PackedTexts", "Patterns", "SmError", "histogram", "order", "count", "count_async", "report",
-           "report_async", "count_batch", "BatchPlan", "bigram", "version", "device_cus"]
+           "report_async", "count_batch", "report_batch", "BatchPlan", "bigram", "version", "device_cus"]
 
 ORDER_KINDS = {"ltr": SM_ORDER_LTR, "freq": SM_ORDER_FREQ, "h": SM_ORDER_H, "hs": SM_ORDER_HS}
 
@@ -333,6 +333,26 @@ def count_batch(texts: Sequence, queries: Iterable, peel=None, tile_kib=None, wg
                                 _params(peel, tile_kib, wgs_per_cu), _stream(stream)))
     del keep
     return out[:nq]
+
+
+def report_batch(texts: Sequence, queries: Iterable, caps, peel=None, tile_kib=None, wgs_per_cu=None,
+                 stream=None, use_hist: bool = True):
+    """Ordered start positions of many (text_id, pattern[, order]) queries, one pass per text
+    (asynchronous).  caps[i] bounds query i's list.  Returns (positions, totals): positions is one
+    device int64 tensor holding query i's min(total_i, caps[i]) smallest starts at offset
+    sum(caps[:i]); totals holds every full count (device int64)."""
+    qarr, tarr, nt, nq, dev, keep = _marshal_batch(texts, queries, use_hist)
+    caps = np.ascontiguousarray(np.asarray(caps, dtype=np.uint64).reshape(-1))
+    if caps.size != nq:
+        raise ValueError("one cap per query")
+    dev = dev or "cuda"
+    pos = torch.empty(max(int(caps.sum()), 1), dtype=torch.int64, device=dev)
+    totals = torch.empty(max(nq, 1), dtype=torch.int64, device=dev)
+    check(load().sm_report_batch(qarr.ctypes.data_as(ctypes.POINTER(sm_query)), nq,
+                                 tarr.ctypes.data_as(ctypes.POINTER(sm_text)), nt, _ptr(caps), pos.data_ptr(),
+                                 totals.data_ptr(), _params(peel, tile_kib, wgs_per_cu), _stream(stream)))
+    del keep
+    return pos, totals[:nq]
 
 
 class BatchPlan:

@@ -22,6 +22,7 @@ EXPORTS = (
     "sm_patterns_create", "sm_patterns_destroy", "sm_patterns_count", "sm_patterns_report",
     "sm_report_async", "sm_patterns_report_async", "sm_patterns_create_ordered",
     "sm_batch_create", "sm_batch_run", "sm_batch_destroy", "sm_bigram", "sm_order_bigram",
+    "sm_report_batch",
 )
 
 
@@ -76,6 +77,7 @@ def load() -> ctypes.CDLL:
         "sm_batch_run": ([vp, vp, vp], i32),
         "sm_batch_destroy": ([vp], i32),
         "sm_bigram": ([vp, u64, vp, vp, vp], i32),
+        "sm_report_batch": ([P(sm_query), u64, P(sm_text), u64, vp, vp, vp, P(sm_params), vp], i32),
         "sm_order_bigram": ([vp, u64, vp, vp, vp], i32),
         "sm_patterns_destroy": ([vp], i32),
         "sm_patterns_create_ordered": ([u64, P(vp), P(u64), i32, vp, P(vp)], i32),

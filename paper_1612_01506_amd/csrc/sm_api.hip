@@ -81,6 +81,11 @@ struct Dev {
     // indices, marks and chunk sums in one buffer
     uint8_t *no_buf = nullptr;
     size_t no_cap = 0;
+    // reporting batches: per-query vector counts, group sums and offsets
+    uint8_t *rb_buf = nullptr;
+    size_t rb_cap = 0;
+    hipEvent_t rb_ev = nullptr;  // recorded after each reporting batch's last kernel
+    bool rb_pending = false;
 };
 
 constexpr int kMaxDev = 64;
@@ -886,8 +891,19 @@ struct LaunchPlan {
         TextView tv;
         uint64_t m, steps_off, out;
         Tune tu;
+        uint32_t *bc = nullptr;  // reporting: per-vector counts and group sums
+        unsigned long long *gs = nullptr;
     };
     std::vector<Long> longs;
+    // reporting batches: where each query's step table went and its peel
+    std::vector<uint64_t> steps_of;  // per caller query index (step-pool index), or ~0 if none
+    std::vector<uint32_t> peel_of;
+};
+
+// Per-query scratch of a reporting batch (device), indexed by query.
+struct ReportScratch {
+    std::vector<uint32_t *> bc;
+    std::vector<unsigned long long *> gs;
 };
 
 // Runs body(begin, end) over [0, n) split into contiguous ranges, on up to
@@ -952,9 +968,13 @@ using AllocFn = std::function<int(size_t, uint8_t **, uint8_t **)>;
 // long), builds every table into host memory obtained from `alloc` (which
 // also names the device address the tables will live at) and fills `lp`.
 int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uint64_t nt, const sm_params *params,
-               const AllocFn &alloc, LaunchPlan *lp)
+               const AllocFn &alloc, LaunchPlan *lp, const ReportScratch *rep = nullptr)
 {
     lp->nq = nq;
+    if (rep) {
+        lp->steps_of.assign(nq, ~0ull);
+        lp->peel_of.assign(nq, 0);
+    }
     const int cpl = (params && (params->tile_kib == 4 || params->tile_kib == 8 || params->tile_kib == 16))
                         ? params->tile_kib / 4
                         : 2;
@@ -1004,7 +1024,7 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
     std::vector<uint32_t> smap_slot(nt, 0);
     uint32_t n_smaps = 0;
     for (uint64_t t = 0; t < nt; ++t) {
-        text_bm[t] = !smaps[t].empty() && nbm[t] >= kBmMinQueries;
+        text_bm[t] = !rep && !smaps[t].empty() && nbm[t] >= kBmMinQueries;  // reports need byte tiles
         if (text_bm[t])
             smap_slot[t] = n_smaps++;
     }
@@ -1224,6 +1244,10 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
             const int32_t *o = order_of(pq.idx, w);
             build_steps(Q.p, Q.m, o, hs + st_off[k]);
             const uint32_t r = peel_of(pq.idx, o, (double)kBlock);
+            if (rep) {
+                lp->steps_of[pq.idx] = st_off[k];
+                lp->peel_of[pq.idx] = r;
+            }
             if (k >= n_st) {
                 long_peel[k - n_st] = r;
                 return;
@@ -1235,6 +1259,10 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
             bq.m = (uint32_t)pq.m;
             bq.r = r;
             bq.out = (uint32_t)pq.idx;
+            if (rep) {
+                bq.block_counts = rep->bc[pq.idx];
+                bq.group_sums = rep->gs[pq.idx];
+            }
             hq[k] = bq;
             return;
         }
@@ -1305,6 +1333,10 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
         L.steps_off = long_steps_off[i];
         L.out = pq.idx;
         L.tu = Tune{(int)long_peel[i], 1, wpc_long, (int)kChunkLog2};
+        if (rep) {
+            L.bc = rep->bc[pq.idx];
+            L.gs = rep->gs[pq.idx];
+        }
         lp->longs.push_back(L);
     }
     return SM_OK;
@@ -1341,7 +1373,7 @@ int launch_plan(Dev &d, const LaunchPlan &lp, const uint8_t *dev, unsigned long 
     }
     for (const auto &L : lp.longs)
         SM_TRY(launch_count(d, L.tv, L.m, reinterpret_cast<const uint64_t *>(dev + lp.o_steps) + L.steps_off, L.tu,
-                            counts + L.out, nullptr, nullptr, s));
+                            counts + L.out, L.bc, L.gs, s));
     return SM_OK;
 }
 
@@ -1417,6 +1449,8 @@ int32_t sm_shutdown(void)
         if (d->go) (void)hipFree(d->go);
         if (d->rep_ev) (void)hipEventDestroy(d->rep_ev);
         if (d->no_buf) (void)hipFree(d->no_buf);
+        if (d->rb_buf) (void)hipFree(d->rb_buf);
+        if (d->rb_ev) (void)hipEventDestroy(d->rb_ev);
         delete d;
         g_devs[i] = nullptr;
     }
@@ -1744,16 +1778,159 @@ int32_t sm_count_batch(const sm_query *q, uint64_t nq, const sm_text *texts, uin
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     Upload u;
     LaunchPlan lp;
+    bool reserved = false;
     AllocFn alloc = [&](size_t bytes, uint8_t **h, uint8_t **dv) {
         SM_TRY(ring_reserve(*d, bytes, &u));
+        reserved = true;
         *h = u.host;
         *dv = u.dev;
         return (int)SM_OK;
     };
-    SM_TRY(plan_batch(*d, q, nq, texts, nt, params, alloc, &lp));
+    {
+        const int prc = plan_batch(*d, q, nq, texts, nt, params, alloc, &lp);
+        if (prc < 0) {
+            const std::string msg = g_err;
+            if (reserved)
+                (void)ring_commit(*d, u, s);  // give the reservation back
+            return fail(prc, msg);
+        }
+    }
     int rc = ring_copy(u, lp.bytes, s);
     if (rc == SM_OK)
         rc = launch_plan(*d, lp, u.dev, reinterpret_cast<unsigned long long *>(counts_dev), s);
+    const std::string msg = g_err;
+    const int rc2 = ring_commit(*d, u, s);
+    if (rc < 0)
+        return fail(rc, msg);
+    return rc2;
+}
+
+int32_t sm_report_batch(const sm_query *q, uint64_t nq, const sm_text *texts, uint64_t nt, const uint64_t *caps,
+                        uint64_t *pos_dev, uint64_t *totals_dev, const sm_params *params, void *stream)
+{
+    g_err.clear();
+    if (nq == 0)
+        return SM_OK;
+    if (!caps || !totals_dev)
+        return fail(SM_EINVAL, "caps or totals_dev is NULL");
+    SM_TRY(check_flags(params, false));
+    SM_TRY(validate_batch(q, nq, texts, nt));
+    uint64_t total_cap = 0;
+    for (uint64_t i = 0; i < nq; ++i) {
+        if (caps[i] > (1ull << 60) || total_cap + caps[i] > (1ull << 60))
+            return fail(SM_EINVAL, "query " + std::to_string(i) + ": caps too large");
+        total_cap += caps[i];
+    }
+    if (total_cap > 0 && !pos_dev)
+        return fail(SM_EINVAL, "pos_dev is NULL with caps > 0");
+    Dev *d;
+    SM_TRY(get_dev(&d));
+    std::lock_guard<std::mutex> lk(d->mu);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    // per-query report scratch: vector counts, group sums, group offsets
+    std::vector<uint64_t> nb(nq, 0), ng(nq, 0), o_bc(nq, 0), o_gs(nq, 0), o_go(nq, 0);
+    size_t bytes = 0;
+    for (uint64_t i = 0; i < nq; ++i) {
+        const sm_text &tx = texts[q[i].text_id];
+        if (q[i].m > tx.n)
+            continue;
+        const uint64_t last = (reinterpret_cast<uintptr_t>(tx.t) & 15u) + tx.n - q[i].m;
+        nb[i] = ceil_div(last + 1, kBlock);
+        ng[i] = ceil_div(nb[i], kGroupBlocks);
+        o_bc[i] = bytes;
+        bytes += round_up(nb[i] * sizeof(uint32_t), 256);
+        o_gs[i] = bytes;
+        bytes += round_up(ng[i] * sizeof(unsigned long long), 256);
+        o_go[i] = bytes;
+        bytes += round_up(ng[i] * sizeof(unsigned long long), 256);
+    }
+    if (!d->rb_ev)
+        HIP_TRY(hipEventCreateWithFlags(&d->rb_ev, hipEventDisableTiming));
+    if (d->rb_cap < bytes) {
+        if (d->rb_pending)
+            HIP_TRY(hipEventSynchronize(d->rb_ev));  // the old buffer may still be in use
+        if (d->rb_buf)
+            HIP_TRY(hipFree(d->rb_buf));
+        d->rb_buf = nullptr;
+        d->rb_cap = 0;
+        hipError_t e = hipMalloc(reinterpret_cast<void **>(&d->rb_buf), bytes);
+        if (e != hipSuccess)
+            return fail(SM_ENOMEM, std::string("report batch scratch: ") + hipGetErrorString(e));
+        d->rb_cap = bytes;
+    }
+    if (d->rb_pending)
+        HIP_TRY(hipStreamWaitEvent(s, d->rb_ev, 0));  // scratch is shared by all reporting batches
+    if (bytes)
+        HIP_TRY(launch_fill_u64(reinterpret_cast<unsigned long long *>(d->rb_buf), bytes / 8, 0ull, s));
+    ReportScratch rs;
+    rs.bc.assign(nq, nullptr);
+    rs.gs.assign(nq, nullptr);
+    for (uint64_t i = 0; i < nq; ++i)
+        if (nb[i]) {
+            rs.bc[i] = reinterpret_cast<uint32_t *>(d->rb_buf + o_bc[i]);
+            rs.gs[i] = reinterpret_cast<unsigned long long *>(d->rb_buf + o_gs[i]);
+        }
+    Upload u;
+    LaunchPlan lp;
+    bool reserved = false;
+    AllocFn alloc = [&](size_t b, uint8_t **h, uint8_t **dv) {
+        SM_TRY(ring_reserve(*d, b, &u));
+        reserved = true;
+        *h = u.host;
+        *dv = u.dev;
+        return (int)SM_OK;
+    };
+    {
+        const int prc = plan_batch(*d, q, nq, texts, nt, params, alloc, &lp, &rs);
+        if (prc < 0) {
+            const std::string msg = g_err;
+            if (reserved)
+                (void)ring_commit(*d, u, s);  // give the reservation back
+            return fail(prc, msg);
+        }
+    }
+    unsigned long long *totals = reinterpret_cast<unsigned long long *>(totals_dev);
+    int rc = ring_copy(u, lp.bytes, s);
+    if (rc == SM_OK)
+        rc = launch_plan(*d, lp, u.dev, totals, s);  // counts, plus the per-vector counts of every query
+    // per query: offsets of its groups, then the ordered write of its matching vectors
+    const int wpc = (params && params->wgs_per_cu > 0) ? std::min(params->wgs_per_cu, 32) : 6;
+    const uint64_t target = (uint64_t)std::max(d->cus, 1) * (uint64_t)wpc;
+    uint64_t off = 0;
+    for (uint64_t i = 0; i < nq && rc == SM_OK; ++i) {
+        const uint64_t cap = caps[i];
+        uint64_t *pos = cap ? pos_dev + off : nullptr;
+        off += cap;
+        if (!nb[i])
+            continue;
+        const sm_text &tx = texts[q[i].text_id];
+        CountArgs a{};
+        a.tv = make_view(tx.t, tx.n);
+        a.last = a.tv.first + tx.n - q[i].m;
+        a.nblocks = nb[i];
+        a.steps = reinterpret_cast<const uint64_t *>(u.dev + lp.o_steps) + lp.steps_of[i];
+        a.m = (uint32_t)q[i].m;
+        uint32_t *bc = rs.bc[i];
+        unsigned long long *gs = rs.gs[i];
+        unsigned long long *go = reinterpret_cast<unsigned long long *>(d->rb_buf + o_go[i]);
+        hipError_t e = launch_scan_groups(gs, ng[i], go, totals + i, s);
+        uint64_t win = kBlock + halo_for(q[i].m);
+        if (kWaves * win + kGroupBlocks * sizeof(uint32_t) + 64 > kMaxLds)
+            win = 0;  // long pattern: read the text from global memory
+        const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(ng[i], target));
+        if (e == hipSuccess)
+            e = launch_report_write(a, lp.peel_of[i], bc, gs, go, ng[i], reinterpret_cast<unsigned long long *>(pos),
+                                    cap, (uint32_t)win, grid, s);
+        if (e != hipSuccess)
+            rc = fail(SM_EDEVICE, std::string("report batch: ") + hipGetErrorString(e));
+    }
+    if (rc == SM_OK) {
+        hipError_t e = hipEventRecord(d->rb_ev, s);
+        if (e == hipSuccess)
+            d->rb_pending = true;
+        else
+            rc = fail(SM_EDEVICE, std::string("report batch: ") + hipGetErrorString(e));
+    }
     const std::string msg = g_err;
     const int rc2 = ring_commit(*d, u, s);
     if (rc < 0)

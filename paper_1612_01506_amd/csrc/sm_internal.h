@@ -65,6 +65,10 @@ struct BatchQuery {
     uint32_t r;          // peel factor, 1..min(kMaxPeel, m)
     uint32_t out;        // output slot
     uint32_t pad;
+    // reporting queries: nonzero per-vector counts (array zeroed before) and
+    // their sums per kGroupBlocks group, as the single-search report pass; null otherwise
+    uint32_t *block_counts;
+    unsigned long long *group_sums;
 };
 
 struct BatchArgs {

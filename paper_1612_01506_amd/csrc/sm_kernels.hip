@@ -886,8 +886,17 @@ __global__ __launch_bounds__(kWG) void k_batch_staged(BatchArgs a)
                 uint32_t d[4];
                 init_alive(wb, C.tv.first, Q.last, lane, d);
                 const LdsText tx{buf + boff, buf + boff + 4u * lane};
-                if (search_vector_rt(st, Q.r, Q.m, lane, d, tx))
-                    cnt += count_alive(d);
+                if (search_vector_rt(st, Q.r, Q.m, lane, d, tx)) {
+                    const uint32_t c = count_alive(d);
+                    cnt += c;
+                    if (Q.block_counts) {  // reporting query: per-vector count for the ordered write
+                        const uint32_t sv = wave_sum32(c);
+                        if (lane == 0 && sv) {
+                            Q.block_counts[wb / kBlock] = sv;
+                            atomicAdd(&Q.group_sums[wb / kBlock / kGroupBlocks], (unsigned long long)sv);
+                        }
+                    }
+                }
             }
             if (__any(cnt != 0u)) {
                 const uint32_t s = wave_sum32(cnt);

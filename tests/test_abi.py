@@ -77,6 +77,10 @@ def test_validation_before_any_device_call():
     q = np.zeros(1, dtype=sm._QUERY_DT)
     assert "synchronous" in _err(lib.sm_count_batch(q.ctypes.data_as(ctypes.POINTER(_lib.sm_query)), 1, None, 0, 8,
                                                     ctypes.byref(no), None))
+    # reporting batch: NULL caps / totals
+    assert "caps" in _err(lib.sm_report_batch(q.ctypes.data_as(ctypes.POINTER(_lib.sm_query)), 1, None, 0, None,
+                                              None, 8, None, None))
+    assert lib.sm_report_batch(None, 0, None, 0, None, None, None, None, None) == _lib.SM_OK
     # histogram: NULL output
     assert lib.sm_histogram(None, 0, None, None) == _lib.SM_EINVAL
 

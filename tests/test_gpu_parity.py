@@ -671,3 +671,45 @@ def test_random_sweep_all_entry_points(dev):
     assert sm.count_batch(texts, queries).cpu().tolist() == want
     with sm.BatchPlan(texts, queries, peel=3, tile_kib=4) as plan:
         assert plan.run().cpu().tolist() == want
+
+
+# ------------------------------------------------------------- batched reports
+def test_report_batch_parity(dev):
+    """Ordered positions of many queries from one reporting batch: every list, total and cap against
+    the oracle; texts with histograms and many queries stay in byte-tile mode; long patterns use the
+    global kernel."""
+    g = np.random.default_rng(4321)
+    sizes = [(200_003, 2), (1_500_000, 95), (70_001, 4), (33, 20), (400_000, 256)]
+    hosts = [rand_text(n, s, 77 + i) for i, (n, s) in enumerate(sizes)]
+    texts = [sm.Text(to_dev(t, dev, (3 * i) % 16)) for i, t in enumerate(hosts)]
+    queries, caps = [], []
+    for k in range(300):
+        ti = int(g.integers(0, len(hosts)))
+        t = hosts[ti]
+        m = int(synth.loguniform_ints(1, 3000, 1, g)[0])
+        p = pick_pattern(t, m, g, planted=g.random() < 0.8)
+        queries.append((ti, p, [None, "freq", "h"][k % 3]))
+        caps.append(int(g.choice([0, 1, 5, 1000, 100_000])))
+    queries.append((1, bytes(hosts[1][500:500 + 40_000]), None))   # long: global kernel
+    caps.append(3)
+    queries.append((3, b"x" * 100, None))                             # m > n
+    caps.append(10)
+    pos, totals = sm.report_batch(texts, queries, caps)
+    pos = pos.cpu().numpy().astype(np.uint64)
+    totals = totals.cpu().tolist()
+    off = 0
+    for i, ((ti, p, _), cap) in enumerate(zip(queries, caps)):
+        total, want = oracle.report_full(p, hosts[ti], cap)
+        assert totals[i] == total, i
+        assert pos[off:off + min(total, cap)].tolist() == want.tolist(), i
+        off += cap
+    assert totals == sm.count_batch(texts, [(ti, p) for ti, p, _ in queries]).cpu().tolist()
+    # a second batch reuses the shared scratch (it must start from zero again)
+    pos2, totals2 = sm.report_batch(texts, queries[:50], caps[:50], peel=3)
+    assert totals2.cpu().tolist() == totals[:50]
+    pos2 = pos2.cpu().numpy().astype(np.uint64)
+    off = 0
+    for i in range(50):                       # only the written part of each segment is defined
+        k = min(totals[i], caps[i])
+        assert pos2[off:off + k].tolist() == pos[off:off + k].tolist(), i
+        off += caps[i]
