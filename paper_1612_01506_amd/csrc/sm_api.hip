@@ -836,6 +836,14 @@ struct PlanQuery {
     uint32_t bucket;  // halo (byte tiles) or pattern-length (bitmaps) bucket
 };
 
+// A text of at least kSoloMinBytes with at most kSoloMaxQueries byte-tile queries runs them
+// through the single-search kernel.
+constexpr uint64_t kSoloMinBytes = 64ull << 20;
+constexpr uint64_t kSoloMaxQueries = 2;
+
+// Reporting batches are split so that one part's per-query scratch stays within this many bytes.
+constexpr uint64_t kRepScratchMax = 8ull << 30;
+
 // A text runs in bitmap mode when it has a histogram and at least this many queries.
 constexpr uint64_t kBmMinQueries = 32;
 
@@ -1029,6 +1037,15 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
             smap_slot[t] = n_smaps++;
     }
 
+    // byte-tile candidates per text (queries not taken by the bitmap mode)
+    std::vector<uint64_t> nstaged(nt, 0);
+    for (uint64_t i = 0; i < nq; ++i) {
+        const uint32_t t = q[i].text_id;
+        if (q[i].m <= texts[t].n &&
+            !(text_bm[t] && q[i].m <= 4096 && bm_lds(nslots[t], bm_wps(bm_bucket(q[i].m))) <= kBmMaxLds))
+            nstaged[t]++;
+    }
+
     // ---- classify queries
     std::vector<PlanQuery> staged, longq, bmq;
     uint64_t total_steps = 0, total_bm_steps = 0;
@@ -1055,7 +1072,10 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
         while (b < halo)
             b <<= 1;
         pq.bucket = (uint32_t)b;
-        if (halo <= max_halo)
+        // a large text with very few byte-tile queries runs them through the single-search
+        // kernel (compile-time peel, one launch each), which is faster than a shared pass there
+        const bool solo = texts[t].n >= kSoloMinBytes && nstaged[t] <= kSoloMaxQueries;
+        if (halo <= max_halo && !solo)
             staged.push_back(pq);
         else
             longq.push_back(pq);
@@ -1332,7 +1352,10 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
         L.m = pq.m;
         L.steps_off = long_steps_off[i];
         L.out = pq.idx;
-        L.tu = Tune{(int)long_peel[i], 1, wpc_long, (int)kChunkLog2};
+        // long patterns: 4 KiB tiles (room for the halo); solo queries: the single-search tile
+        const bool fits8 = 2 * (8192 + halo_for(pq.m)) <= kMaxLds;
+        L.tu = Tune{(int)long_peel[i], (texts[pq.text].n >= (8ull << 20) && fits8) ? 2 : 1, wpc_long,
+                    (int)kChunkLog2};
         if (rep) {
             L.bc = rep->bc[pq.idx];
             L.gs = rep->gs[pq.idx];
@@ -1805,28 +1828,12 @@ int32_t sm_count_batch(const sm_query *q, uint64_t nq, const sm_text *texts, uin
     return rc2;
 }
 
-int32_t sm_report_batch(const sm_query *q, uint64_t nq, const sm_text *texts, uint64_t nt, const uint64_t *caps,
-                        uint64_t *pos_dev, uint64_t *totals_dev, const sm_params *params, void *stream)
+// One reporting batch whose scratch fits (see sm_report_batch); the caller
+// holds d->mu.
+static int report_batch_part(Dev *d, const sm_query *q, uint64_t nq, const sm_text *texts, uint64_t nt,
+                      const uint64_t *caps, uint64_t *pos_dev, uint64_t *totals_dev, const sm_params *params,
+                      hipStream_t s)
 {
-    g_err.clear();
-    if (nq == 0)
-        return SM_OK;
-    if (!caps || !totals_dev)
-        return fail(SM_EINVAL, "caps or totals_dev is NULL");
-    SM_TRY(check_flags(params, false));
-    SM_TRY(validate_batch(q, nq, texts, nt));
-    uint64_t total_cap = 0;
-    for (uint64_t i = 0; i < nq; ++i) {
-        if (caps[i] > (1ull << 60) || total_cap + caps[i] > (1ull << 60))
-            return fail(SM_EINVAL, "query " + std::to_string(i) + ": caps too large");
-        total_cap += caps[i];
-    }
-    if (total_cap > 0 && !pos_dev)
-        return fail(SM_EINVAL, "pos_dev is NULL with caps > 0");
-    Dev *d;
-    SM_TRY(get_dev(&d));
-    std::lock_guard<std::mutex> lk(d->mu);
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     // per-query report scratch: vector counts, group sums, group offsets
     std::vector<uint64_t> nb(nq, 0), ng(nq, 0), o_bc(nq, 0), o_gs(nq, 0), o_go(nq, 0);
     size_t bytes = 0;
@@ -1870,11 +1877,24 @@ int32_t sm_report_batch(const sm_query *q, uint64_t nq, const sm_text *texts, ui
             rs.bc[i] = reinterpret_cast<uint32_t *>(d->rb_buf + o_bc[i]);
             rs.gs[i] = reinterpret_cast<unsigned long long *>(d->rb_buf + o_gs[i]);
         }
+    // one upload: the batch plan's tables, then the reporting descriptors and the work-item list
+    uint64_t nd = 0, nitems = 0;
+    for (uint64_t i = 0; i < nq; ++i)
+        if (nb[i]) {
+            ++nd;
+            nitems += ng[i];
+        }
+    if (nitems >= (1ull << 32))
+        return fail(SM_EINVAL, "report batch too large: more than 2^32 groups");
+    const size_t rep_items_off = round_up(nd * sizeof(RepDesc), 256);
+    const size_t rep_bytes = rep_items_off + nitems * sizeof(uint32_t);
     Upload u;
     LaunchPlan lp;
     bool reserved = false;
+    size_t o_rep = 0;
     AllocFn alloc = [&](size_t b, uint8_t **h, uint8_t **dv) {
-        SM_TRY(ring_reserve(*d, b, &u));
+        o_rep = round_up(b, 256);
+        SM_TRY(ring_reserve(*d, o_rep + rep_bytes, &u));
         reserved = true;
         *h = u.host;
         *dv = u.dev;
@@ -1890,37 +1910,53 @@ int32_t sm_report_batch(const sm_query *q, uint64_t nq, const sm_text *texts, ui
         }
     }
     unsigned long long *totals = reinterpret_cast<unsigned long long *>(totals_dev);
-    int rc = ring_copy(u, lp.bytes, s);
-    if (rc == SM_OK)
-        rc = launch_plan(*d, lp, u.dev, totals, s);  // counts, plus the per-vector counts of every query
-    // per query: offsets of its groups, then the ordered write of its matching vectors
-    const int wpc = (params && params->wgs_per_cu > 0) ? std::min(params->wgs_per_cu, 32) : 6;
-    const uint64_t target = (uint64_t)std::max(d->cus, 1) * (uint64_t)wpc;
-    uint64_t off = 0;
-    for (uint64_t i = 0; i < nq && rc == SM_OK; ++i) {
+    RepDesc *hd = reinterpret_cast<RepDesc *>(u.host + o_rep);
+    uint32_t *hitem = reinterpret_cast<uint32_t *>(u.host + o_rep + rep_items_off);
+    uint32_t win_max = 0;
+    uint64_t off = 0, k = 0, item = 0;
+    for (uint64_t i = 0; i < nq; ++i) {
         const uint64_t cap = caps[i];
         uint64_t *pos = cap ? pos_dev + off : nullptr;
         off += cap;
         if (!nb[i])
             continue;
         const sm_text &tx = texts[q[i].text_id];
-        CountArgs a{};
-        a.tv = make_view(tx.t, tx.n);
-        a.last = a.tv.first + tx.n - q[i].m;
-        a.nblocks = nb[i];
-        a.steps = reinterpret_cast<const uint64_t *>(u.dev + lp.o_steps) + lp.steps_of[i];
-        a.m = (uint32_t)q[i].m;
-        uint32_t *bc = rs.bc[i];
-        unsigned long long *gs = rs.gs[i];
-        unsigned long long *go = reinterpret_cast<unsigned long long *>(d->rb_buf + o_go[i]);
-        hipError_t e = launch_scan_groups(gs, ng[i], go, totals + i, s);
+        RepDesc D{};
+        D.tv = make_view(tx.t, tx.n);
+        D.last = D.tv.first + tx.n - q[i].m;
+        D.nblocks = nb[i];
+        D.steps = reinterpret_cast<const uint64_t *>(u.dev + lp.o_steps) + lp.steps_of[i];
+        D.m = (uint32_t)q[i].m;
+        D.r = lp.peel_of[i];
         uint64_t win = kBlock + halo_for(q[i].m);
         if (kWaves * win + kGroupBlocks * sizeof(uint32_t) + 64 > kMaxLds)
             win = 0;  // long pattern: read the text from global memory
-        const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(ng[i], target));
-        if (e == hipSuccess)
-            e = launch_report_write(a, lp.peel_of[i], bc, gs, go, ng[i], reinterpret_cast<unsigned long long *>(pos),
-                                    cap, (uint32_t)win, grid, s);
+        D.win = (uint32_t)win;
+        win_max = std::max(win_max, D.win);
+        D.bc = rs.bc[i];
+        D.gs = rs.gs[i];
+        D.go = reinterpret_cast<unsigned long long *>(d->rb_buf + o_go[i]);
+        D.total = totals + i;
+        D.pos = reinterpret_cast<unsigned long long *>(pos);
+        D.cap = cap;
+        D.ngroups = ng[i];
+        D.item0 = item;
+        hd[k] = D;
+        std::fill(hitem + item, hitem + item + ng[i], (uint32_t)k);
+        item += ng[i];
+        ++k;
+    }
+    int rc = ring_copy(u, o_rep + rep_bytes, s);
+    if (rc == SM_OK)
+        rc = launch_plan(*d, lp, u.dev, totals, s);  // counts, plus the per-vector counts of every query
+    if (rc == SM_OK && nd) {
+        // every query's group offsets, then the ordered writes of all matching vectors: two launches
+        const int wpc = (params && params->wgs_per_cu > 0) ? std::min(params->wgs_per_cu, 32) : 6;
+        const uint64_t target = (uint64_t)std::max(d->cus, 1) * (uint64_t)wpc;
+        const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(nitems, target));
+        hipError_t e = launch_report_multi(reinterpret_cast<const RepDesc *>(u.dev + o_rep), nd,
+                                           reinterpret_cast<const uint32_t *>(u.dev + o_rep + rep_items_off), nitems,
+                                           win_max, grid, s);
         if (e != hipSuccess)
             rc = fail(SM_EDEVICE, std::string("report batch: ") + hipGetErrorString(e));
     }
@@ -1936,6 +1972,54 @@ int32_t sm_report_batch(const sm_query *q, uint64_t nq, const sm_text *texts, ui
     if (rc < 0)
         return fail(rc, msg);
     return rc2;
+}
+
+
+int32_t sm_report_batch(const sm_query *q, uint64_t nq, const sm_text *texts, uint64_t nt, const uint64_t *caps,
+                        uint64_t *pos_dev, uint64_t *totals_dev, const sm_params *params, void *stream)
+{
+    g_err.clear();
+    if (nq == 0)
+        return SM_OK;
+    if (!caps || !totals_dev)
+        return fail(SM_EINVAL, "caps or totals_dev is NULL");
+    SM_TRY(check_flags(params, false));
+    SM_TRY(validate_batch(q, nq, texts, nt));
+    uint64_t total_cap = 0;
+    for (uint64_t i = 0; i < nq; ++i) {
+        if (caps[i] > (1ull << 60) || total_cap + caps[i] > (1ull << 60))
+            return fail(SM_EINVAL, "query " + std::to_string(i) + ": caps too large");
+        total_cap += caps[i];
+    }
+    if (total_cap > 0 && !pos_dev)
+        return fail(SM_EINVAL, "pos_dev is NULL with caps > 0");
+    Dev *d;
+    SM_TRY(get_dev(&d));
+    std::lock_guard<std::mutex> lk(d->mu);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    // split into parts whose per-query scratch (vector counts, group sums and offsets) stays bounded
+    uint64_t i0 = 0, pos_off = 0;
+    while (i0 < nq) {
+        uint64_t i1 = i0, need = 0, part_cap = 0;
+        while (i1 < nq) {
+            const sm_text &tx = texts[q[i1].text_id];
+            uint64_t b = 0;
+            if (q[i1].m <= tx.n) {
+                const uint64_t nbk = ceil_div((reinterpret_cast<uintptr_t>(tx.t) & 15u) + tx.n - q[i1].m + 1, kBlock);
+                b = round_up(nbk * 4, 256) + 2 * round_up(ceil_div(nbk, kGroupBlocks) * 8, 256);
+            }
+            if (i1 > i0 && need + b > kRepScratchMax)
+                break;
+            need += b;
+            part_cap += caps[i1];
+            ++i1;
+        }
+        SM_TRY(report_batch_part(d, q + i0, i1 - i0, texts, nt, caps + i0, pos_dev ? pos_dev + pos_off : nullptr,
+                                 totals_dev + i0, params, s));
+        pos_off += part_cap;
+        i0 = i1;
+    }
+    return SM_OK;
 }
 
 int32_t sm_batch_create(const sm_query *q, uint64_t nq, const sm_text *texts, uint64_t nt, const sm_params *params,

@@ -71,6 +71,23 @@ struct BatchQuery {
     unsigned long long *group_sums;
 };
 
+// One query of a reporting batch, for the group scan and the ordered writes.
+struct RepDesc {
+    TextView tv;
+    uint64_t last, nblocks;
+    const uint64_t *steps;
+    uint32_t m, r;
+    uint32_t win;                  // per-wave LDS window bytes, or 0: read from global memory
+    uint32_t pad;
+    uint32_t *bc;                  // nonzero per-vector counts
+    unsigned long long *gs, *go;   // group sums and their exclusive offsets
+    unsigned long long *total;     // full count
+    unsigned long long *pos;       // output segment
+    uint64_t cap;
+    uint64_t ngroups;
+    uint64_t item0;                // first work item (group 0) of this query
+};
+
 struct BatchArgs {
     const BatchChunk *chunks;
     const uint32_t *tile_chunk;  // chunk of every global tile
@@ -144,6 +161,8 @@ hipError_t launch_no_compact(const unsigned long long *pos, const uint32_t *mark
                              const unsigned long long *go, uint64_t ng, unsigned long long *out, uint64_t cap,
                              hipStream_t s);
 hipError_t launch_bigram(const TextView &tv, uint32_t half, unsigned long long *out, unsigned grid, hipStream_t s);
+hipError_t launch_report_multi(const RepDesc *descs, uint64_t nq, const uint32_t *item_query, uint64_t nitems,
+                               uint32_t win_max, unsigned grid, hipStream_t s);
 // Sets the dynamic-LDS limits of all kernels on the current device.
 hipError_t prime_kernel_attrs();
 

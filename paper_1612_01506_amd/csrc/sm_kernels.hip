@@ -583,6 +583,92 @@ __device__ __forceinline__ void write_vector(const uint32_t (&d)[4], uint64_t wb
 
 // win: per-wave LDS window in bytes (1024 + halo), or 0 to read the text
 // from global memory (long patterns).
+// One group of kGroupBlocks vectors of a report: exclusive offsets of its
+// vectors in LDS, then every vector with matches is searched again (its
+// window staged in the wave's LDS region `mine` of win bytes, or read from
+// global memory when win is 0) and its starts written in increasing order.
+// Leaves the group's per-vector counts and sum zeroed.  Whole workgroup.
+__device__ __forceinline__ void report_write_group(const CountArgs &a, uint32_t r, uint32_t *bc,
+                                                   unsigned long long *gs, const unsigned long long *go, uint64_t g,
+                                                   unsigned long long *pos, uint64_t cap, uint32_t win, uint8_t *mine,
+                                                   uint32_t *off, uint32_t *wsum)
+{
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = wave_id();
+    if (gs[g] == 0)
+        return;
+    const uint64_t b0 = g * kGroupBlocks;
+    // exclusive offsets of the group's vectors (4 consecutive per thread)
+    uint32_t c[kGroupBlocks / kWG], s = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < kGroupBlocks / kWG; ++i) {
+        const uint64_t b = b0 + (kGroupBlocks / kWG) * tid + i;
+        c[i] = b < a.nblocks ? bc[b] : 0u;
+        s += c[i];
+    }
+    uint32_t inc = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t v = __shfl_up(inc, o, 64);
+        if (lane >= (uint32_t)o)
+            inc += v;
+    }
+    if (lane == 63u)
+        wsum[wave] = inc;
+    __syncthreads();
+    uint32_t run = inc - s;
+    for (uint32_t w = 0; w < wave; ++w)
+        run += wsum[w];
+#pragma unroll
+    for (uint32_t i = 0; i < kGroupBlocks / kWG; ++i) {
+        off[(kGroupBlocks / kWG) * tid + i] = run;
+        run += c[i];
+    }
+    __syncthreads();
+    const unsigned long long gbase = go[g];
+    for (uint32_t j0 = wave * 64u; j0 < kGroupBlocks; j0 += kWaves * 64u) {
+        const uint64_t bb = b0 + j0 + lane;
+        unsigned long long nz = __ballot(bb < a.nblocks && bc[bb] != 0u);
+        while (nz) {
+            const int bit = __ffsll((long long)nz) - 1;
+            nz &= nz - 1;
+            const uint64_t wb = (b0 + j0 + (uint64_t)bit) * kBlock;
+            uint32_t d[4];
+            init_alive(wb, a.tv.first, a.last, lane, d);
+            bool alive;
+            if (win) {
+                for (uint32_t ch = lane; ch < win / 16u; ch += 64u) {
+                    const uint64_t u = wb + 16ull * ch;
+                    *reinterpret_cast<uint4 *>(mine + 16u * ch) =
+                        u < a.tv.end16 ? *reinterpret_cast<const uint4 *>(a.tv.base + u) : make_uint4(0, 0, 0, 0);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                const LdsText tx{mine, mine + 4u * lane};
+                alive = search_vector_rt(a.steps, r, a.m, lane, d, tx);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            } else {
+                const GlobalText tx{&a.tv, wb, wb + 4u * lane};
+                alive = search_vector_rt(a.steps, r, a.m, lane, d, tx);
+            }
+            if (alive)
+                write_vector(d, wb, a.tv.first, lane, gbase + off[j0 + bit], pos, cap);
+        }
+    }
+    __syncthreads();
+    // leave the group's scratch zeroed for the next report: every nonzero
+    // per-vector count lies in a group with a nonzero sum, so after the pass
+    // both arrays are all zero again
+#pragma unroll
+    for (uint32_t i = 0; i < kGroupBlocks / kWG; ++i)
+        if (c[i])
+            bc[b0 + (kGroupBlocks / kWG) * tid + i] = 0u;
+    if (tid == 0)
+        gs[g] = 0ull;
+}
+
 __global__ __launch_bounds__(kWG) void k_report_write(CountArgs a, uint32_t r, uint32_t *bc,
                                                      unsigned long long *gs, const unsigned long long *go,
                                                      uint64_t ngroups, unsigned long long *pos, uint64_t cap,
@@ -591,82 +677,58 @@ __global__ __launch_bounds__(kWG) void k_report_write(CountArgs a, uint32_t r, u
     extern __shared__ __align__(16) uint8_t wlds[];
     __shared__ uint32_t off[kGroupBlocks];
     __shared__ uint32_t wsum[kWaves];
-    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = wave_id();
-    uint8_t *mine = wlds + wave * win;
-    for (uint64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
-        if (gs[g] == 0)
-            continue;
-        const uint64_t b0 = g * kGroupBlocks;
-        // exclusive offsets of the group's vectors (4 consecutive per thread)
-        uint32_t c[kGroupBlocks / kWG], s = 0;
-#pragma unroll
-        for (uint32_t i = 0; i < kGroupBlocks / kWG; ++i) {
-            const uint64_t b = b0 + (kGroupBlocks / kWG) * tid + i;
-            c[i] = b < a.nblocks ? bc[b] : 0u;
-            s += c[i];
-        }
-        uint32_t inc = s;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t v = __shfl_up(inc, o, 64);
-            if (lane >= (uint32_t)o)
-                inc += v;
-        }
-        if (lane == 63u)
-            wsum[wave] = inc;
+    uint8_t *mine = wlds + wave_id() * win;
+    for (uint64_t g = blockIdx.x; g < ngroups; g += gridDim.x)
+        report_write_group(a, r, bc, gs, go, g, pos, cap, win, mine, off, wsum);
+}
+
+// Reporting batch: the group offsets of every query (one workgroup of 1024
+// threads per query, as k_scan_groups) ...
+__global__ __launch_bounds__(1024) void k_scan_groups_multi(const RepDesc *descs)
+{
+    __shared__ unsigned long long part[1024];
+    const RepDesc D = ldc(&descs[blockIdx.x]);
+    const uint32_t tid = threadIdx.x;
+    const uint64_t ng = D.ngroups, per = (ng + 1023u) / 1024u;
+    const uint64_t b0 = min((uint64_t)tid * per, ng), b1 = min(b0 + per, ng);
+    unsigned long long s = 0;
+    for (uint64_t i = b0; i < b1; ++i)
+        s += D.gs[i];
+    part[tid] = s;
+    __syncthreads();
+    for (uint32_t o = 1; o < 1024u; o <<= 1) {
+        const unsigned long long v = tid >= o ? part[tid - o] : 0ull;
         __syncthreads();
-        uint32_t run = inc - s;
-        for (uint32_t w = 0; w < wave; ++w)
-            run += wsum[w];
-#pragma unroll
-        for (uint32_t i = 0; i < kGroupBlocks / kWG; ++i) {
-            off[(kGroupBlocks / kWG) * tid + i] = run;
-            run += c[i];
-        }
+        part[tid] += v;
         __syncthreads();
-        const unsigned long long gbase = go[g];
-        for (uint32_t j0 = wave * 64u; j0 < kGroupBlocks; j0 += kWaves * 64u) {
-            const uint64_t bb = b0 + j0 + lane;
-            unsigned long long nz = __ballot(bb < a.nblocks && bc[bb] != 0u);
-            while (nz) {
-                const int bit = __ffsll((long long)nz) - 1;
-                nz &= nz - 1;
-                const uint64_t wb = (b0 + j0 + (uint64_t)bit) * kBlock;
-                uint32_t d[4];
-                init_alive(wb, a.tv.first, a.last, lane, d);
-                bool alive;
-                if (win) {
-                    for (uint32_t ch = lane; ch < win / 16u; ch += 64u) {
-                        const uint64_t u = wb + 16ull * ch;
-                        *reinterpret_cast<uint4 *>(mine + 16u * ch) =
-                            u < a.tv.end16 ? *reinterpret_cast<const uint4 *>(a.tv.base + u) : make_uint4(0, 0, 0, 0);
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    const LdsText tx{mine, mine + 4u * lane};
-                    alive = search_vector_rt(a.steps, r, a.m, lane, d, tx);
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                } else {
-                    const GlobalText tx{&a.tv, wb, wb + 4u * lane};
-                    alive = search_vector_rt(a.steps, r, a.m, lane, d, tx);
-                }
-                if (alive)
-                    write_vector(d, wb, a.tv.first, lane, gbase + off[j0 + bit], pos, cap);
-            }
-        }
-        __syncthreads();
-        // leave the group's scratch zeroed for the next report: every nonzero
-        // per-vector count lies in a group with a nonzero sum, so after the
-        // pass both arrays are all zero again
-#pragma unroll
-        for (uint32_t i = 0; i < kGroupBlocks / kWG; ++i)
-            if (c[i])
-                bc[b0 + (kGroupBlocks / kWG) * tid + i] = 0u;
-        if (tid == 0)
-            gs[g] = 0ull;
+    }
+    unsigned long long run = tid ? part[tid - 1] : 0ull;
+    for (uint64_t i = b0; i < b1; ++i) {
+        D.go[i] = run;
+        run += D.gs[i];
+    }
+    if (tid == 1023u)
+        *D.total = part[1023];
+}
+
+// ... and the ordered writes of all their groups: work item i is group
+// i - descs[q].item0 of query q = item_query[i].
+__global__ __launch_bounds__(kWG) void k_report_write_multi(const RepDesc *descs, const uint32_t *item_query,
+                                                           uint64_t nitems)
+{
+    extern __shared__ __align__(16) uint8_t wlds[];
+    __shared__ uint32_t off[kGroupBlocks];
+    __shared__ uint32_t wsum[kWaves];
+    for (uint64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const RepDesc D = ldc(&descs[ldc(&item_query[it])]);
+        CountArgs a{};
+        a.tv = D.tv;
+        a.last = D.last;
+        a.nblocks = D.nblocks;
+        a.steps = D.steps;
+        a.m = D.m;
+        report_write_group(a, D.r, D.bc, D.gs, D.go, it - D.item0, D.pos, D.cap, D.win, wlds + wave_id() * D.win,
+                           off, wsum);
     }
 }
 
@@ -1233,6 +1295,17 @@ hipError_t launch_report_write(const CountArgs &a, uint32_t r, uint32_t *bc, uns
     return hipGetLastError();
 }
 
+hipError_t launch_report_multi(const RepDesc *descs, uint64_t nq, const uint32_t *item_query, uint64_t nitems,
+                               uint32_t win_max, unsigned grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scan_groups_multi, dim3((unsigned)nq), dim3(1024), 0, s, descs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || nitems == 0)
+        return e;
+    hipLaunchKernelGGL(k_report_write_multi, dim3(grid), dim3(kWG), kWaves * win_max, s, descs, item_query, nitems);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_report(uint32_t *bc, uint64_t nblocks, unsigned long long *gs, uint64_t ngroups,
                               hipStream_t s)
 {
@@ -1369,6 +1442,8 @@ hipError_t prime_kernel_attrs()
         (e = prime_cpl<4>()) != hipSuccess)
         return e;
     if ((e = lds_attr(&k_report_write, (int)kMaxLds)) != hipSuccess)
+        return e;
+    if ((e = lds_attr(&k_report_write_multi, (int)kMaxLds)) != hipSuccess)
         return e;
     if ((e = lds_attr(&k_hist, (int)kHistLds)) != hipSuccess)
         return e;

@@ -6,9 +6,11 @@ streams; whenever a slot frees up, every request queued by then (up to
 `max_batch`) is admitted and sent to the device in one batched count
 (sm_count_batch: one persistent launch shared by all patterns of a text).
 A reporting request is counted first; its position buffer (count x 8 bytes)
-is then reserved against an HBM budget and the reporting search runs as its
-own asynchronous launch.  A request whose position list alone exceeds the
-budget is rejected; others wait until reserved memory frees up.
+is then reserved against an HBM budget.  Reporting requests whose buffers fit
+go, as many as fit, into one batched report (sm_report_batch: one shared pass
+per text, then ordered writes per request).  A request whose position list
+alone exceeds the budget is rejected; others wait until reserved memory frees
+up.
 
 Each request's result is the same alone and in the mix: the counts of a
 batch are those of independent searches (Section 1 problem statement, one
@@ -89,21 +91,26 @@ class GpuExecutor:
             ev.record(s)
         return (ev, host, counts)
 
-    def launch_report(self, slot: int, req: Request, cap: int):
-        from . import report_async
+    def launch_reports(self, slot: int, reqs: list, caps: list):
+        """One batched report (a lone request takes the single-search report path, which is
+        faster for one pattern)."""
+        from . import report_async, report_batch
 
         torch = self.torch
         s = self.streams[slot]
         with torch.cuda.stream(s):
-            pos = torch.empty(max(cap, 1), dtype=torch.int64, device=self.device)
-            total = torch.empty(1, dtype=torch.int64, device=self.device)
-            report_async(self.texts[req.text_id], req.pattern, pos[:cap] if cap else pos[:0], total,
-                         order="freq", stream=s)
-            htot = torch.empty(1, dtype=torch.int64, pin_memory=True)
-            htot.copy_(total, non_blocking=True)
+            if len(reqs) == 1:
+                r, cap = reqs[0], int(caps[0])
+                pos = torch.empty(max(cap, 1), dtype=torch.int64, device=self.device)
+                totals = torch.empty(1, dtype=torch.int64, device=self.device)
+                report_async(self.texts[r.text_id], r.pattern, pos[:cap], totals, order="freq", stream=s)
+            else:
+                pos, totals = report_batch(self.texts, [(r.text_id, r.pattern) for r in reqs], caps, stream=s)
+            htot = torch.empty(len(reqs), dtype=torch.int64, pin_memory=True)
+            htot.copy_(totals, non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(s)
-        return (ev, pos, htot, total, cap)
+        return (ev, pos, htot, totals, list(caps))
 
     def ready(self, handle) -> bool:
         return handle[0].query()
@@ -111,11 +118,14 @@ class GpuExecutor:
     def counts(self, handle) -> np.ndarray:
         return handle[1].numpy().copy()
 
-    def report(self, handle):
-        """(full count, positions as a device int64 tensor)."""
-        _, pos, htot, _, cap = handle
-        total = int(htot[0])
-        return total, pos[:min(total, cap)]
+    def reports(self, handle) -> list:
+        """[(full count, positions as a device int64 tensor)] per request of the batch."""
+        _, pos, htot, _, caps = handle
+        out, off = [], 0
+        for total, cap in zip(htot.numpy().tolist(), caps):
+            out.append((int(total), pos[off:off + min(int(total), cap)]))
+            off += cap
+        return out
 
 
 class Server:
@@ -192,25 +202,31 @@ class Server:
         return None
 
     def _admit(self) -> None:
-        # reporting searches whose position buffers now fit
+        # reporting searches whose position buffers now fit: as many as fit go into one batch
         while self.mem_wait and len(self.inflight) < self.max_inflight:
-            r = self.mem_wait[0]
-            need = 8 * r.count
-            if self.reserved + need > self.hbm_budget:
-                break
             slot = self._free_slot()
             if slot is None:
                 break
-            self.mem_wait.popleft()
+            group, need = [], 0
+            while self.mem_wait and len(group) < self.max_batch:
+                b = 8 * self.mem_wait[0].count
+                if self.reserved + need + b > self.hbm_budget:
+                    break
+                group.append(self.mem_wait.popleft())
+                need += b
+            if not group:
+                break
             self._reserve(need)
-            r.status = "reporting"
+            for r in group:
+                r.status = "reporting"
             try:
-                h = self.ex.launch_report(slot, r, r.count)
-            except Exception as e:  # noqa: BLE001 - a device error fails this request only
+                h = self.ex.launch_reports(slot, group, [r.count for r in group])
+            except Exception as e:  # noqa: BLE001 - a device error fails these requests only
                 self._release(need)
-                self._finish_error(r, str(e))
+                for r in group:
+                    self._finish_error(r, str(e))
                 continue
-            self.inflight.append(_Flight("report", h, [r], need, slot))
+            self.inflight.append(_Flight("report", h, group, need, slot))
         # everything queued so far goes into one batched count
         while self.queue and len(self.inflight) < self.max_inflight:
             slot = self._free_slot()
@@ -256,15 +272,15 @@ class Server:
                     self._finish(r, now)
                     n += 1
             else:
-                r = f.reqs[0]
-                total, pos = self.ex.report(f.handle)
+                results = self.ex.reports(f.handle)
                 self._release(f.reserved)
-                if total != r.count:
-                    self._finish_error(r, f"report total {total} != count {r.count}")
-                else:
-                    r.positions = pos
-                    self._finish(r, now)
-                    n += 1
+                for r, (total, pos) in zip(f.reqs, results):
+                    if total != r.count:
+                        self._finish_error(r, f"report total {total} != count {r.count}")
+                    else:
+                        r.positions = pos
+                        self._finish(r, now)
+                        n += 1
         self.inflight = still
         return n
 

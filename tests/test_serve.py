@@ -22,6 +22,7 @@ class FakeExecutor:
         self.delay = delay
         self.fail_batches = set(fail_batches)
         self.launches = 0
+        self.report_batches = []
         self.active = 0
         self.max_active = 0
 
@@ -38,10 +39,14 @@ class FakeExecutor:
         counts = np.array([oracle.count(r.pattern, self.texts[r.text_id]) for r in reqs], dtype=np.int64)
         return {"left": self.delay, "counts": counts}
 
-    def launch_report(self, slot, req, cap):
+    def launch_reports(self, slot, reqs, caps):
         self._start()
-        pos = oracle.report(req.pattern, self.texts[req.text_id])
-        return {"left": self.delay, "total": int(pos.size), "pos": pos[:cap]}
+        self.report_batches.append(len(reqs))
+        res = []
+        for r, cap in zip(reqs, caps):
+            pos = oracle.report(r.pattern, self.texts[r.text_id])
+            res.append((int(pos.size), pos[:cap]))
+        return {"left": self.delay, "reports": res}
 
     def ready(self, h):
         if h["left"] > 0:
@@ -55,8 +60,8 @@ class FakeExecutor:
     def counts(self, h):
         return h["counts"]
 
-    def report(self, h):
-        return h["total"], h["pos"]
+    def reports(self, h):
+        return h["reports"]
 
 
 def make_texts():
@@ -139,3 +144,18 @@ def test_failures_stay_confined():
         stuck = Server(FakeExecutor(texts, nslots=1, delay=10**9))
         stuck.submit(0, b"a")
         stuck.drain(timeout=0.05)
+
+
+def test_reports_share_one_batch():
+    """Reporting requests admitted together go to the device as one batched report."""
+    texts = make_texts()
+    ex = FakeExecutor(texts, nslots=1, delay=1)
+    srv = Server(ex)
+    g = np.random.default_rng(3)
+    reqs = [srv.submit(k % len(texts), synth.substring_pattern(texts[k % len(texts)], 3, g)[0], report=True)
+            for k in range(10)]
+    srv.drain()
+    assert all(r.status == "done" for r in reqs)
+    assert ex.report_batches == [10]
+    for r in reqs:
+        assert np.array_equal(np.asarray(r.positions, dtype=np.uint64), oracle.report(r.pattern, texts[r.text_id]))
