@@ -789,8 +789,9 @@ def main():
                     help="also run one plain device copy of the text (HBM counter scale)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the search would shard)", file=sys.stderr)
+        print("bench.py measures one GPU only: the search has no multi-GPU path (the design notes "
+              "describe how it would shard: start positions split with an (m-1)-byte halo, counts "
+              "summed by an all-reduce)", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
