@@ -883,7 +883,7 @@ int validate_batch(const sm_query *q, uint64_t nq, const sm_text *texts, uint64_
 struct LaunchPlan {
     size_t bytes = 0;
     size_t o_items = 0, o_tchunk = 0, o_queries = 0, o_steps = 0, o_bitems = 0, o_bq = 0, o_bout = 0,
-           o_smap = 0, o_bsteps = 0;
+           o_smap = 0, o_bsteps = 0, o_reports = 0;  // o_reports: reporting batches only (0: none)
     uint64_t nq = 0;
     // bitmap launch
     uint64_t n_bitems = 0;
@@ -1173,13 +1173,15 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
     const size_t o_bsteps = o_smap + round_up((uint64_t)n_smaps * 256, 256);
     if (total_bm_steps >= (1ull << 32))
         return fail(SM_EINVAL, "batch too large: pattern bytes in bitmap mode exceed 2^32");
-    const size_t bytes = o_bsteps + round_up(total_bm_steps * sizeof(uint32_t), 256);
+    const size_t o_reports = o_bsteps + round_up(total_bm_steps * sizeof(uint32_t), 256);
+    const size_t bytes = o_reports + (rep ? round_up(std::max<size_t>(staged.size(), 1) * sizeof(BatchReport), 256) : 0);
     uint8_t *uhost = nullptr, *udev = nullptr;
     SM_TRY(alloc(bytes, &uhost, &udev));
     lp->bytes = bytes;
     std::copy(bchunks_t.begin(), bchunks_t.end(), reinterpret_cast<BatchChunk *>(uhost + o_items));
     std::copy(tile_chunk.begin(), tile_chunk.end(), reinterpret_cast<uint32_t *>(uhost + o_tchunk));
     BatchQuery *hq = reinterpret_cast<BatchQuery *>(uhost + o_queries);
+    BatchReport *hrep = rep ? reinterpret_cast<BatchReport *>(uhost + o_reports) : nullptr;
     uint64_t *hs = reinterpret_cast<uint64_t *>(uhost + o_steps);
     BmItem *hbi = reinterpret_cast<BmItem *>(uhost + o_bitems);
     BmQuery *hbq = reinterpret_cast<BmQuery *>(uhost + o_bq);
@@ -1279,11 +1281,9 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
             bq.m = (uint32_t)pq.m;
             bq.r = r;
             bq.out = (uint32_t)pq.idx;
-            if (rep) {
-                bq.block_counts = rep->bc[pq.idx];
-                bq.group_sums = rep->gs[pq.idx];
-            }
             hq[k] = bq;
+            if (rep)
+                hrep[k] = BatchReport{rep->bc[pq.idx], rep->gs[pq.idx]};
             return;
         }
         const size_t i = k - n_st - n_lg;
@@ -1334,6 +1334,7 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
     lp->o_bout = o_bout;
     lp->o_smap = o_smap;
     lp->o_bsteps = o_bsteps;
+    lp->o_reports = rep ? o_reports : 0;
     lp->n_bitems = bitems.size();
     lp->bm_words = (uint32_t)round_up(bm_words, 4);
     {
@@ -1388,6 +1389,7 @@ int launch_plan(Dev &d, const LaunchPlan &lp, const uint8_t *dev, unsigned long 
         a.tile_chunk = reinterpret_cast<const uint32_t *>(dev + lp.o_tchunk);
         a.ntiles = lp.ntiles;
         a.queries = reinterpret_cast<const BatchQuery *>(dev + lp.o_queries);
+        a.reports = lp.o_reports ? reinterpret_cast<const BatchReport *>(dev + lp.o_reports) : nullptr;
         a.steps = reinterpret_cast<const uint64_t *>(dev + lp.o_steps);
         a.counts = counts;
         a.halo_max = lp.halo_max;

@@ -65,8 +65,12 @@ struct BatchQuery {
     uint32_t r;          // peel factor, 1..min(kMaxPeel, m)
     uint32_t out;        // output slot
     uint32_t pad;
-    // reporting queries: nonzero per-vector counts (array zeroed before) and
-    // their sums per kGroupBlocks group, as the single-search report pass; null otherwise
+};
+
+// Reporting batches, per query (same index as BatchQuery): nonzero per-vector
+// counts (array zeroed before) and their sums per kGroupBlocks group, as the
+// single-search report pass writes them.
+struct BatchReport {
     uint32_t *block_counts;
     unsigned long long *group_sums;
 };
@@ -93,6 +97,7 @@ struct BatchArgs {
     const uint32_t *tile_chunk;  // chunk of every global tile
     uint64_t ntiles;             // global tiles
     const BatchQuery *queries;
+    const BatchReport *reports;  // reporting batches only (else null)
     const uint64_t *steps;
     unsigned long long *counts;
     uint32_t halo_max;           // largest chunk halo (LDS buffer size)

@@ -887,7 +887,7 @@ __global__ void k_fill_u64(unsigned long long *p, uint64_t n, unsigned long long
 // may belong to another text.  Every query of the tile's chunk runs over the
 // staged tile; per-query counts gather in LDS and are flushed (one 64-bit
 // atomicAdd per nonzero query) whenever the workgroup moves to another chunk.
-template <int CPL>
+template <int CPL, bool REPORT>
 __global__ __launch_bounds__(kWG) void k_batch_staged(BatchArgs a)
 {
     extern __shared__ __align__(16) uint8_t lds[];
@@ -951,11 +951,12 @@ __global__ __launch_bounds__(kWG) void k_batch_staged(BatchArgs a)
                 if (search_vector_rt(st, Q.r, Q.m, lane, d, tx)) {
                     const uint32_t c = count_alive(d);
                     cnt += c;
-                    if (Q.block_counts) {  // reporting query: per-vector count for the ordered write
+                    if constexpr (REPORT) {  // per-vector count for the ordered write
+                        const BatchReport P = ldc(&a.reports[q]);
                         const uint32_t sv = wave_sum32(c);
                         if (lane == 0 && sv) {
-                            Q.block_counts[wb / kBlock] = sv;
-                            atomicAdd(&Q.group_sums[wb / kBlock / kGroupBlocks], (unsigned long long)sv);
+                            P.block_counts[wb / kBlock] = sv;
+                            atomicAdd(&P.group_sums[wb / kBlock / kGroupBlocks], (unsigned long long)sv);
                         }
                     }
                 }
@@ -1339,7 +1340,10 @@ template <int CPL>
 static hipError_t launch_batch_t(const BatchArgs &a, unsigned grid, hipStream_t s)
 {
     const uint32_t lds = 2u * (kWG * 16u * CPL + a.halo_max) + kQChunk * (uint32_t)sizeof(uint32_t);
-    hipLaunchKernelGGL((k_batch_staged<CPL>), dim3(grid), dim3(kWG), lds, s, a);
+    if (a.reports)
+        hipLaunchKernelGGL((k_batch_staged<CPL, true>), dim3(grid), dim3(kWG), lds, s, a);
+    else
+        hipLaunchKernelGGL((k_batch_staged<CPL, false>), dim3(grid), dim3(kWG), lds, s, a);
     return hipGetLastError();
 }
 
@@ -1426,7 +1430,8 @@ static hipError_t prime_cpl()
                         reinterpret_cast<const void *>(&k_count_staged<CPL, 6>),
                         reinterpret_cast<const void *>(&k_count_staged<CPL, 7>),
                         reinterpret_cast<const void *>(&k_count_staged<CPL, 8>),
-                        reinterpret_cast<const void *>(&k_batch_staged<CPL>)};
+                        reinterpret_cast<const void *>(&k_batch_staged<CPL, false>),
+                        reinterpret_cast<const void *>(&k_batch_staged<CPL, true>)};
     for (const void *k : ks) {
         hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
         if (e != hipSuccess)
