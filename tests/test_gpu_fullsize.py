@@ -117,3 +117,24 @@ def test_periodic_256mib_closed_forms(dev):
         for order in ("ltr", "freq"):
             assert sm.count(td, b"a" * k, order=order) == n - k + 1
             assert sm.count(td, b"a" * (k - 1) + b"b", order=order) == 0
+
+
+def test_text_beyond_4gib(dev):
+    """64-bit coordinates: a 4.5 GiB text, patterns planted past 2^32; counts, positions and the
+    histogram against the oracle."""
+    n = (9 << 30) // 2
+    t = synth.uniform_text(n, 4, family=6, stream=3)
+    planted = [(1 << 32) + 12_345, n - 40, (3 << 30) + 7]
+    p = b"GATTACAGATTACAGG"
+    for o in planted:
+        t[o:o + len(p)] = np.frombuffer(p, dtype=np.uint8)
+    td = torch.from_numpy(t).to(dev)
+    text = sm.Text(td)
+    assert text.hist.tolist() == oracle.hist(t).tolist()
+    want = oracle.report(p, t)
+    assert set(planted) <= set(want.tolist())
+    assert sm.count(text, p, order="freq") == want.size
+    assert sm.report(text, p).cpu().numpy().astype(np.uint64).tolist() == want.tolist()
+    q = b"ACGTA"
+    assert sm.count(text, q) == oracle.count(q, t)
+    assert sm.count_batch([text], [(0, p), (0, q)]).cpu().tolist() == [want.size, oracle.count(q, t)]
