@@ -73,6 +73,7 @@ struct Dev {
     unsigned long long *gs = nullptr, *go = nullptr;
     size_t g_cap = 0;
     hipEvent_t rep_ev = nullptr;  // recorded after each report's last kernel
+    hipStream_t rep_stream = nullptr;  // ... on this stream
     bool rep_pending = false;
     // bc and gs must be zero when a report's count pass starts; the write pass
     // leaves them zero, so only fresh scratch or an unfinished report needs a fill
@@ -85,6 +86,7 @@ struct Dev {
     uint8_t *rb_buf = nullptr;
     size_t rb_cap = 0;
     hipEvent_t rb_ev = nullptr;  // recorded after each reporting batch's last kernel
+    hipStream_t rb_stream = nullptr;  // ... on this stream
     bool rb_pending = false;
 };
 
@@ -647,8 +649,8 @@ int report_count_pass(Dev &d, const TextView &tv, uint64_t m, const uint64_t *st
     SM_TRY(ensure_report_scratch(d, nblocks, ngroups));
     if (!d.rep_ev)
         HIP_TRY(hipEventCreateWithFlags(&d.rep_ev, hipEventDisableTiming));
-    if (d.rep_pending)
-        HIP_TRY(hipStreamWaitEvent(s, d.rep_ev, 0));  // scratch is shared by all reports
+    if (d.rep_pending && d.rep_stream != s)  // scratch is shared by all reports (in order on one stream)
+        HIP_TRY(hipStreamWaitEvent(s, d.rep_ev, 0));
     if (d.rep_dirty)
         HIP_TRY(launch_fill_report(d.bc, d.bc_cap, d.gs, d.g_cap, s));
     d.rep_dirty = true;  // until a write pass has cleaned up after this count pass
@@ -674,9 +676,10 @@ int report_write_pass(Dev &d, const TextView &tv, uint64_t m, const uint64_t *st
     uint64_t win = kBlock + halo_for(m);
     if (kWaves * win + kGroupBlocks * sizeof(uint32_t) + 64 > kMaxLds)
         win = 0;  // long pattern: read the text from global memory
-    HIP_TRY(launch_report_write(a, (uint32_t)tu.r, d.bc, d.gs, d.go, ngroups,
+    HIP_TRY(launch_report_write(a, d.bc, d.gs, d.go, ngroups,
                                 reinterpret_cast<unsigned long long *>(pos), cap, (uint32_t)win, ggrid, s));
     HIP_TRY(hipEventRecord(d.rep_ev, s));
+    d.rep_stream = s;
     d.rep_pending = true;
     d.rep_dirty = false;
     return SM_OK;
@@ -903,9 +906,8 @@ struct LaunchPlan {
         unsigned long long *gs = nullptr;
     };
     std::vector<Long> longs;
-    // reporting batches: where each query's step table went and its peel
+    // reporting batches: where each query's step table went
     std::vector<uint64_t> steps_of;  // per caller query index (step-pool index), or ~0 if none
-    std::vector<uint32_t> peel_of;
 };
 
 // Per-query scratch of a reporting batch (device), indexed by query.
@@ -979,10 +981,8 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
                const AllocFn &alloc, LaunchPlan *lp, const ReportScratch *rep = nullptr)
 {
     lp->nq = nq;
-    if (rep) {
+    if (rep)
         lp->steps_of.assign(nq, ~0ull);
-        lp->peel_of.assign(nq, 0);
-    }
     const int cpl = (params && (params->tile_kib == 4 || params->tile_kib == 8 || params->tile_kib == 16))
                         ? params->tile_kib / 4
                         : 2;
@@ -1124,6 +1124,7 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
         bc.q_begin = c.q0;
         bc.q_end = c.q1;
         bc.halo = halo_for(c.m_max);
+        bc.ntiles = (uint32_t)ntiles;
         halo_max = std::max(halo_max, bc.halo);
         tile_chunk.insert(tile_chunk.end(), ntiles, (uint32_t)bchunks_t.size());
         bchunks_t.push_back(bc);
@@ -1266,10 +1267,8 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
             const int32_t *o = order_of(pq.idx, w);
             build_steps(Q.p, Q.m, o, hs + st_off[k]);
             const uint32_t r = peel_of(pq.idx, o, (double)kBlock);
-            if (rep) {
+            if (rep)
                 lp->steps_of[pq.idx] = st_off[k];
-                lp->peel_of[pq.idx] = r;
-            }
             if (k >= n_st) {
                 long_peel[k - n_st] = r;
                 return;
@@ -1649,27 +1648,40 @@ int32_t sm_patterns_create(uint64_t np, const uint8_t *const *p, const uint64_t 
     }
     Dev *d;
     SM_TRY(get_dev(&d));
-    sm_patterns *ps = new sm_patterns();
+    std::unique_ptr<sm_patterns> ps(new sm_patterns());
     ps->dev = d->id;
-    std::vector<uint64_t> host(std::max<uint64_t>(total, 1));
-    uint64_t at = 0;
-    for (uint64_t i = 0; i < np; ++i) {
-        build_steps(p[i], m[i], order ? order[i] : nullptr, host.data() + at);
-        ps->off.push_back(at);
-        ps->m.push_back(m[i]);
-        at += m[i] + kStepPad;
-    }
-    hipError_t e = hipMalloc(reinterpret_cast<void **>(&ps->steps), host.size() * sizeof(uint64_t));
-    if (e == hipSuccess)
-        e = hipMemcpy(ps->steps, host.data(), host.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-        if (ps->steps)
-            (void)hipFree(ps->steps);
-        delete ps;
+    const size_t bytes = std::max<uint64_t>(total, 1) * sizeof(uint64_t);
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&ps->steps), bytes);
+    if (e != hipSuccess)
         return fail(e == hipErrorOutOfMemory ? SM_ENOMEM : SM_EDEVICE,
-                    std::string("pattern set upload: ") + hipGetErrorString(e));
+                    std::string("pattern set: ") + hipGetErrorString(e));
+    // the tables are built in pinned staging and go up in one copy (a copy
+    // from pageable memory is staged by the runtime in many small pieces)
+    std::lock_guard<std::mutex> lk(d->mu);
+    Upload u;
+    int rc = ring_reserve(*d, bytes, &u);
+    if (rc == SM_OK) {
+        uint64_t *host = reinterpret_cast<uint64_t *>(u.host);
+        uint64_t at = 0;
+        for (uint64_t i = 0; i < np; ++i) {
+            build_steps(p[i], m[i], order ? order[i] : nullptr, host + at);
+            ps->off.push_back(at);
+            ps->m.push_back(m[i]);
+            at += m[i] + kStepPad;
+        }
+        if ((e = hipMemcpyAsync(ps->steps, u.host, bytes, hipMemcpyHostToDevice, nullptr)) != hipSuccess)
+            rc = fail(SM_EDEVICE, std::string("pattern set upload: ") + hipGetErrorString(e));
+        const int rc2 = ring_commit(*d, u, nullptr);
+        if (rc == SM_OK)
+            rc = rc2;
     }
-    *out = ps;
+    if (rc == SM_OK && (e = hipStreamSynchronize(nullptr)) != hipSuccess)
+        rc = fail(SM_EDEVICE, std::string("pattern set upload: ") + hipGetErrorString(e));
+    if (rc != SM_OK) {
+        (void)hipFree(ps->steps);
+        return rc;
+    }
+    *out = ps.release();
     return SM_OK;
 }
 
@@ -1867,8 +1879,8 @@ static int report_batch_part(Dev *d, const sm_query *q, uint64_t nq, const sm_te
             return fail(SM_ENOMEM, std::string("report batch scratch: ") + hipGetErrorString(e));
         d->rb_cap = bytes;
     }
-    if (d->rb_pending)
-        HIP_TRY(hipStreamWaitEvent(s, d->rb_ev, 0));  // scratch is shared by all reporting batches
+    if (d->rb_pending && d->rb_stream != s)  // scratch is shared by all reporting batches (in order on one stream)
+        HIP_TRY(hipStreamWaitEvent(s, d->rb_ev, 0));
     if (bytes)
         HIP_TRY(launch_fill_u64(reinterpret_cast<unsigned long long *>(d->rb_buf), bytes / 8, 0ull, s));
     ReportScratch rs;
@@ -1929,7 +1941,6 @@ static int report_batch_part(Dev *d, const sm_query *q, uint64_t nq, const sm_te
         D.nblocks = nb[i];
         D.steps = reinterpret_cast<const uint64_t *>(u.dev + lp.o_steps) + lp.steps_of[i];
         D.m = (uint32_t)q[i].m;
-        D.r = lp.peel_of[i];
         uint64_t win = kBlock + halo_for(q[i].m);
         if (kWaves * win + kGroupBlocks * sizeof(uint32_t) + 64 > kMaxLds)
             win = 0;  // long pattern: read the text from global memory
@@ -1964,8 +1975,10 @@ static int report_batch_part(Dev *d, const sm_query *q, uint64_t nq, const sm_te
     }
     if (rc == SM_OK) {
         hipError_t e = hipEventRecord(d->rb_ev, s);
-        if (e == hipSuccess)
+        if (e == hipSuccess) {
             d->rb_pending = true;
+            d->rb_stream = s;
+        }
         else
             rc = fail(SM_EDEVICE, std::string("report batch: ") + hipGetErrorString(e));
     }

@@ -55,7 +55,7 @@ struct BatchChunk {
     uint64_t tile0;
     uint32_t q_begin, q_end;  // into the BatchQuery array
     uint32_t halo;            // LDS halo bytes for the chunk's longest pattern
-    uint32_t pad;
+    uint32_t ntiles;
 };
 
 struct BatchQuery {
@@ -80,9 +80,8 @@ struct RepDesc {
     TextView tv;
     uint64_t last, nblocks;
     const uint64_t *steps;
-    uint32_t m, r;
+    uint32_t m;
     uint32_t win;                  // per-wave LDS window bytes, or 0: read from global memory
-    uint32_t pad;
     uint32_t *bc;                  // nonzero per-vector counts
     unsigned long long *gs, *go;   // group sums and their exclusive offsets
     unsigned long long *total;     // full count
@@ -146,9 +145,9 @@ hipError_t launch_count_staged(const CountArgs &a, int cpl, int r, unsigned grid
 hipError_t launch_count_global(const CountArgs &a, int r, unsigned grid, hipStream_t s);
 hipError_t launch_scan_groups(const unsigned long long *gs, uint64_t ngroups, unsigned long long *go,
                               unsigned long long *total, hipStream_t s);
-hipError_t launch_report_write(const CountArgs &a, uint32_t r, uint32_t *bc, unsigned long long *gs,
-                               const unsigned long long *go, uint64_t ngroups, unsigned long long *pos, uint64_t cap,
-                               uint32_t win, unsigned grid, hipStream_t s);
+hipError_t launch_report_write(const CountArgs &a, uint32_t *bc, unsigned long long *gs, const unsigned long long *go,
+                               uint64_t ngroups, unsigned long long *pos, uint64_t cap, uint32_t win, unsigned grid,
+                               hipStream_t s);
 hipError_t launch_fill_report(uint32_t *bc, uint64_t nblocks, unsigned long long *gs, uint64_t ngroups,
                               hipStream_t s);
 hipError_t launch_hist(const TextView &tv, unsigned long long *hist, unsigned grid, hipStream_t s);

@@ -333,6 +333,33 @@ __device__ __forceinline__ bool search_vector_rt(const uint64_t *steps, uint32_t
     return search_tail(steps, r, m, lane, d, tx);
 }
 
+// Search of a vector whose number of matches `want` (>= 1) is already known
+// from the count pass: the matches are among the starts still alive after any
+// prefix of the compares, so once exactly `want` are alive, d is final.  The
+// compares go in groups of kTestEach per test (from none), so a vector whose
+// survivors are its matches costs a few compares whatever m is; a handful of
+// other survivors facing many more compares are verified one at a time.
+template <typename Text>
+__device__ __forceinline__ void search_known(const uint64_t *steps, uint32_t m, uint32_t lane, uint32_t want,
+                                             uint32_t (&d)[4], const Text &tx)
+{
+    uint32_t l = 0;
+    while (l < m) {
+        const uint32_t alive = wave_sum32(count_alive(d));
+        if (alive <= want)
+            return;
+        if (m - l >= kVerifyMin && alive <= kVerifyMax) {
+            verify_candidates(steps, l, m, lane, d, tx);
+            return;
+        }
+        const uint32_t g = min(kTestEach, m - l);
+#pragma unroll 1
+        for (uint32_t u = 0; u < g; ++u)
+            tx.step(ldc(&steps[l + u]), d);
+        l += g;
+    }
+}
+
 // ------------------------------------------------------------- tile staging
 
 template <int CPL>
@@ -581,14 +608,13 @@ __device__ __forceinline__ void write_vector(const uint32_t (&d)[4], uint64_t wb
     }
 }
 
-// win: per-wave LDS window in bytes (1024 + halo), or 0 to read the text
-// from global memory (long patterns).
 // One group of kGroupBlocks vectors of a report: exclusive offsets of its
-// vectors in LDS, then every vector with matches is searched again (its
-// window staged in the wave's LDS region `mine` of win bytes, or read from
-// global memory when win is 0) and its starts written in increasing order.
-// Leaves the group's per-vector counts and sum zeroed.  Whole workgroup.
-__device__ __forceinline__ void report_write_group(const CountArgs &a, uint32_t r, uint32_t *bc,
+// vectors in LDS, then every vector with matches is searched again, knowing
+// its count (its window staged in the wave's LDS region `mine` of win bytes,
+// 1024 + halo, or read from global memory when win is 0 for long patterns),
+// and its starts written in increasing order.  Leaves the group's per-vector
+// counts and sum zeroed.  Whole workgroup.
+__device__ __forceinline__ void report_write_group(const CountArgs &a, uint32_t *bc,
                                                    unsigned long long *gs, const unsigned long long *go, uint64_t g,
                                                    unsigned long long *pos, uint64_t cap, uint32_t win, uint8_t *mine,
                                                    uint32_t *off, uint32_t *wsum)
@@ -627,14 +653,15 @@ __device__ __forceinline__ void report_write_group(const CountArgs &a, uint32_t 
     const unsigned long long gbase = go[g];
     for (uint32_t j0 = wave * 64u; j0 < kGroupBlocks; j0 += kWaves * 64u) {
         const uint64_t bb = b0 + j0 + lane;
-        unsigned long long nz = __ballot(bb < a.nblocks && bc[bb] != 0u);
+        const uint32_t cb = bb < a.nblocks ? bc[bb] : 0u;
+        unsigned long long nz = __ballot(cb != 0u);
         while (nz) {
             const int bit = __ffsll((long long)nz) - 1;
             nz &= nz - 1;
+            const uint32_t want = (uint32_t)__builtin_amdgcn_readlane((int)cb, bit);
             const uint64_t wb = (b0 + j0 + (uint64_t)bit) * kBlock;
             uint32_t d[4];
             init_alive(wb, a.tv.first, a.last, lane, d);
-            bool alive;
             if (win) {
                 for (uint32_t ch = lane; ch < win / 16u; ch += 64u) {
                     const uint64_t u = wb + 16ull * ch;
@@ -645,16 +672,15 @@ __device__ __forceinline__ void report_write_group(const CountArgs &a, uint32_t 
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 const LdsText tx{mine, mine + 4u * lane};
-                alive = search_vector_rt(a.steps, r, a.m, lane, d, tx);
+                search_known(a.steps, a.m, lane, want, d, tx);
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             } else {
                 const GlobalText tx{&a.tv, wb, wb + 4u * lane};
-                alive = search_vector_rt(a.steps, r, a.m, lane, d, tx);
+                search_known(a.steps, a.m, lane, want, d, tx);
             }
-            if (alive)
-                write_vector(d, wb, a.tv.first, lane, gbase + off[j0 + bit], pos, cap);
+            write_vector(d, wb, a.tv.first, lane, gbase + off[j0 + bit], pos, cap);
         }
     }
     __syncthreads();
@@ -669,7 +695,7 @@ __device__ __forceinline__ void report_write_group(const CountArgs &a, uint32_t 
         gs[g] = 0ull;
 }
 
-__global__ __launch_bounds__(kWG) void k_report_write(CountArgs a, uint32_t r, uint32_t *bc,
+__global__ __launch_bounds__(kWG) void k_report_write(CountArgs a, uint32_t *bc,
                                                      unsigned long long *gs, const unsigned long long *go,
                                                      uint64_t ngroups, unsigned long long *pos, uint64_t cap,
                                                      uint32_t win)
@@ -679,7 +705,7 @@ __global__ __launch_bounds__(kWG) void k_report_write(CountArgs a, uint32_t r, u
     __shared__ uint32_t wsum[kWaves];
     uint8_t *mine = wlds + wave_id() * win;
     for (uint64_t g = blockIdx.x; g < ngroups; g += gridDim.x)
-        report_write_group(a, r, bc, gs, go, g, pos, cap, win, mine, off, wsum);
+        report_write_group(a, bc, gs, go, g, pos, cap, win, mine, off, wsum);
 }
 
 // Reporting batch: the group offsets of every query (one workgroup of 1024
@@ -727,7 +753,7 @@ __global__ __launch_bounds__(kWG) void k_report_write_multi(const RepDesc *descs
         a.nblocks = D.nblocks;
         a.steps = D.steps;
         a.m = D.m;
-        report_write_group(a, D.r, D.bc, D.gs, D.go, it - D.item0, D.pos, D.cap, D.win, wlds + wave_id() * D.win,
+        report_write_group(a, D.bc, D.gs, D.go, it - D.item0, D.pos, D.cap, D.win, wlds + wave_id() * D.win,
                            off, wsum);
     }
 }
@@ -1287,12 +1313,11 @@ hipError_t launch_scan_groups(const unsigned long long *gs, uint64_t ngroups, un
     return hipGetLastError();
 }
 
-hipError_t launch_report_write(const CountArgs &a, uint32_t r, uint32_t *bc, unsigned long long *gs,
-                               const unsigned long long *go, uint64_t ngroups, unsigned long long *pos, uint64_t cap,
-                               uint32_t win, unsigned grid, hipStream_t s)
+hipError_t launch_report_write(const CountArgs &a, uint32_t *bc, unsigned long long *gs, const unsigned long long *go,
+                               uint64_t ngroups, unsigned long long *pos, uint64_t cap, uint32_t win, unsigned grid,
+                               hipStream_t s)
 {
-    hipLaunchKernelGGL(k_report_write, dim3(grid), dim3(kWG), kWaves * win, s, a, r, bc, gs, go, ngroups, pos, cap,
-                       win);
+    hipLaunchKernelGGL(k_report_write, dim3(grid), dim3(kWG), kWaves * win, s, a, bc, gs, go, ngroups, pos, cap, win);
     return hipGetLastError();
 }
 
