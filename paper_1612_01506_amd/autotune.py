@@ -4,14 +4,15 @@ For every cell (alphabet class, pattern-length bucket, text-size bucket) the
 tuner times count searches of substring patterns on a seeded synthetic text
 over a grid of tile size, workgroups per compute unit and peel factor r, and
 keeps the fastest setting.  None of these parameters changes a result.  The
-paper's observations seed the grid: with frequency order r = 2 is best for
-large alphabets, r = 3 for protein and r = 5 for DNA (Section 3).
+grid holds every compiled peel factor r = 1..8, which includes the paper's
+choices with frequency order: r = 2 for large alphabets, r = 3 for protein
+and r = 5 for DNA (Section 3).
 
-The table is a JSON file keyed by GPU architecture and HIP version
-(`tuning/<arch>.json` next to this module).  The binding consults it for
-searches on texts whose histogram it knows (`Text` objects) when the caller
-gives no explicit parameters; with no table for the current device it passes
-nothing and the library's defaults apply.
+The table is one JSON file per GPU architecture (`tuning/<arch>.json` next to
+this module), which records the HIP version it was measured with.  The
+binding consults it for searches on texts whose histogram it knows (`Text`
+objects) when the caller gives no explicit parameters; with no table for the
+current device it passes nothing and the library's defaults apply.
 
     python -m paper_1612_01506_amd.autotune --out tuned.json
 """
@@ -30,7 +31,10 @@ TABLE_DIR = os.path.join(_HERE, "tuning")
 CLASSES = (2, 4, 20, 95)            # alphabet classes (symbols present)
 M_BUCKETS = (8, 64, 512, 4096)       # upper bounds of pattern-length buckets
 N_BUCKETS = (16 << 20, 1 << 62)      # upper bounds of text-size buckets
-GRID = [(tk, w, r) for tk in (4, 8, 16) for w in (4, 6, 8) for r in (1, 2, 3, 5)]
+TILE_KIB = (4, 8, 16)
+WGS_PER_CU = (4, 6, 8)
+PEELS = (1, 2, 3, 4, 5, 6, 7, 8)     # every compiled peel factor
+GRID = [(tk, w, r) for tk in TILE_KIB for w in WGS_PER_CU for r in PEELS]
 
 _table = None
 _table_key = None
@@ -89,7 +93,7 @@ def params_for(hist, m: int, n: int) -> dict | None:
     return {"tile_kib": e["tile_kib"], "wgs_per_cu": e["wgs_per_cu"], "peel": e["peel"]}
 
 
-def tune(sizes=(8 << 20, 256 << 20), patterns_per_cell: int = 4, reps: int = 3, log=print) -> dict:
+def tune(sizes=(8 << 20, 1 << 30), patterns_per_cell: int = 4, reps: int = 3, log=print) -> dict:
     import torch
 
     from . import Patterns, Text
@@ -138,7 +142,7 @@ def tune(sizes=(8 << 20, 256 << 20), patterns_per_cell: int = 4, reps: int = 3, 
             del t
             torch.cuda.empty_cache()
     return {"arch": arch, "hip": hip, "created": time.strftime("%Y-%m-%d"),
-            "grid": {"tile_kib": [4, 8, 16], "wgs_per_cu": [4, 6, 8], "peel": [1, 2, 3, 5]},
+            "grid": {"tile_kib": list(TILE_KIB), "wgs_per_cu": list(WGS_PER_CU), "peel": list(PEELS)},
             "classes": list(CLASSES), "m_buckets": list(M_BUCKETS), "n_buckets": list(N_BUCKETS),
             "cells": cells, "timings_us": timings}
 
