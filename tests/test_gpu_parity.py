@@ -313,6 +313,30 @@ def test_prepared_patterns(dev):
         sm.Patterns([b"ab", b""])
 
 
+def test_pattern_set_larger_than_half_the_upload_ring(dev):
+    """Step tables over 32 MiB (half the 64 MiB pinned ring) go up through a dedicated staging buffer;
+    a small set created right after reuses the ring.  Counts against the oracle."""
+    g = np.random.default_rng(77)
+    t = rand_text(3_000_000, 20, 21)
+    td = to_dev(t, dev, 3)
+    # 5 patterns of 1 MB: 5 x (1 MB + 8) step entries x 8 B = 40 MB of tables
+    big = [bytes(t[o:o + 1_000_000]) for o in g.integers(0, t.size - 1_000_000, size=4)] + \
+          [bytes(rand_text(1_000_000, 20, 22))]
+    ps = sm.Patterns(big)
+    small = sm.Patterns([bytes(t[10:20]), b"zz"])
+    out = torch.zeros(len(big) + 2, dtype=torch.int64, device=dev)
+    for i in range(len(big)):
+        ps.count_async(i, td, out[i:i + 1])
+    for i in range(2):
+        small.count_async(i, td, out[len(big) + i:len(big) + i + 1])
+    torch.cuda.synchronize()
+    want = [oracle.count(p, t) for p in big] + [oracle.count(bytes(t[10:20]), t), oracle.count(b"zz", t)]
+    assert out.cpu().tolist() == want
+    assert min(want[:4]) >= 1
+    ps.close()
+    small.close()
+
+
 def test_report_async_two_streams(dev):
     """Async reports on two streams share the library's report scratch; results must be exact."""
     g = np.random.default_rng(8)
