@@ -38,6 +38,7 @@ GRID = [(tk, w, r) for tk in TILE_KIB for w in WGS_PER_CU for r in PEELS]
 
 _table = None
 _table_key = None
+_device_keys: dict = {}   # device index -> (architecture, HIP version)
 
 
 def alphabet_class(hist) -> int:
@@ -55,9 +56,13 @@ def _bucket(v: int, bounds) -> int:
 def _device_key():
     import torch
 
-    props = torch.cuda.get_device_properties(0)
-    arch = props.gcnArchName.split(":")[0]
-    return arch, torch.version.hip or "unknown"
+    dev = torch.cuda.current_device()
+    key = _device_keys.get(dev)
+    if key is None:
+        props = torch.cuda.get_device_properties(dev)
+        key = (props.gcnArchName.split(":")[0], torch.version.hip or "unknown")
+        _device_keys[dev] = key
+    return key
 
 
 def load_table(path: str | None = None):
