@@ -78,13 +78,18 @@ class GpuExecutor:
         return len(self.streams)
 
     def launch_counts(self, slot: int, reqs: list):
-        from . import count_batch
+        """One batched count (a lone request takes the single-search path: no batch planning)."""
+        from . import count_async, count_batch
 
         torch = self.torch
         s = self.streams[slot]
-        queries = [(r.text_id, r.pattern) for r in reqs]
         with torch.cuda.stream(s):
-            counts = count_batch(self.texts, queries, stream=s)
+            if len(reqs) == 1:
+                r = reqs[0]
+                counts = torch.zeros(1, dtype=torch.int64, device=self.device)
+                count_async(self.texts[r.text_id], r.pattern, counts, order="freq", stream=s)
+            else:
+                counts = count_batch(self.texts, [(r.text_id, r.pattern) for r in reqs], stream=s)
             host = torch.empty(len(reqs), dtype=torch.int64, pin_memory=True)
             host.copy_(counts, non_blocking=True)
             ev = torch.cuda.Event()

@@ -484,6 +484,26 @@ def test_serving_alone_equals_mix(dev):
             assert np.array_equal(pos.astype(np.uint64), oracle.report(r.pattern, texts_h[r.text_id]))
 
 
+def test_serving_lone_requests(dev):
+    """Requests served one at a time take the single-search count and report paths."""
+    from paper_1612_01506_amd.serve import GpuExecutor, Server
+    texts_h = [synth.zipf_text(2_000_000, 95, 1.0, family=5, stream=3), rand_text(1_000_001, 4, 78)]
+    ex = GpuExecutor([to_dev(t, dev, 5 + i) for i, t in enumerate(texts_h)], nstreams=2)
+    srv = Server(ex, hbm_budget=1 << 24)
+    g = np.random.default_rng(13)
+    for k in range(12):
+        ti = k % 2
+        p = synth.substring_pattern(texts_h[ti], int(g.integers(2, 40)), g)[0]
+        r = srv.submit(ti, p, report=(k % 3 == 0))
+        srv.drain()
+        assert r.status == "done", (r.status, r.error)
+        assert r.count == oracle.count(p, texts_h[ti])
+        if r.report:
+            pos = r.positions.cpu().numpy() if hasattr(r.positions, "cpu") else r.positions
+            assert np.array_equal(pos.astype(np.uint64), oracle.report(p, texts_h[ti]))
+    assert srv.batches >= 12
+
+
 def test_batch_plan_graph_replay(dev):
     """A planned batch equals the one-shot batch and the oracle, eagerly and replayed from a graph.
 
