@@ -1164,8 +1164,10 @@ __device__ __forceinline__ void bm_step(const uint32_t *bm, uint32_t e, uint32_t
 // chunk of <= kBmQChunk queries).  Per tile: zero the bitmaps, set one bit per
 // text byte (LDS atomic OR), then wave w runs queries w, w + 16, ... over the
 // 8192 starts of the tile: the first r compares unconditionally, then one zero
-// test (a wave-wide ballot) after each further compare (Algorithm 4).  Each
-// query's count for the item gathers in an LDS counter owned by one wave.
+// test (a wave-wide ballot) after each further compare (Algorithm 4).  A wave
+// takes its queries in pairs and issues the two peels' compares side by side,
+// so the LDS reads of both are in flight together.  Each query's count for the
+// item gathers in an LDS counter owned by one wave.
 __global__ __launch_bounds__(kBmWG) void k_batch_bitmap(BmArgs a)
 {
     extern __shared__ __align__(16) uint32_t bm[];
@@ -1205,15 +1207,8 @@ __global__ __launch_bounds__(kBmWG) void k_batch_bitmap(BmArgs a)
             }
             __syncthreads();
             const uint64_t tile_end = ts + kBmT - 1u;
-            uint32_t q = I.q_begin + wave;
-            BmQuery nxt = q < I.q_end ? ldc(&a.queries[q]) : BmQuery{};
-            for (; q < I.q_end; q += kBmWaves) {
-                const BmQuery Q = nxt;
-                if (q + kBmWaves < I.q_end)
-                    nxt = ldc(&a.queries[q + kBmWaves]);  // next record in flight during this query
-                const uint32_t m = Q.mr & 0xFFFFFFu, r = Q.mr >> 24;
-                const uint64_t last = hi - m;
-                uint32_t f[4];
+            auto init_f = [&](const BmQuery &Q, uint32_t (&f)[4]) {
+                const uint64_t last = hi - (Q.mr & 0xFFFFFFu);
                 if (ts >= lo && tile_end <= last) {
                     f[0] = f[1] = f[2] = f[3] = 0xFFFFFFFFu;
                 } else {
@@ -1221,11 +1216,12 @@ __global__ __launch_bounds__(kBmWG) void k_batch_bitmap(BmArgs a)
                     for (int v = 0; v < 4; ++v)
                         f[v] = valid_bits(ts + 2048u * v + 32u * lane, lo, last);
                 }
+            };
+            // the rest of one query from compare l0 on, and its count
+            auto finish = [&](const BmQuery &Q, uint32_t (&f)[4], uint32_t l0, uint32_t q) {
+                const uint32_t m = Q.mr & 0xFFFFFFu, r = Q.mr >> 24;
                 const uint32_t *st = a.steps + Q.steps_off;
-                bm_step(bm, Q.e0, lane, f);
-                if (r >= 2u)
-                    bm_step(bm, Q.e1, lane, f);
-                for (uint32_t l = 2; l < r; ++l)
+                for (uint32_t l = l0; l < r; ++l)
                     bm_step(bm, ldc(&st[l]), lane, f);
                 bool alive = __any((f[0] | f[1] | f[2] | f[3]) != 0u);
                 for (uint32_t l = r; alive && l < m; ++l) {
@@ -1237,6 +1233,31 @@ __global__ __launch_bounds__(kBmWG) void k_batch_bitmap(BmArgs a)
                     if (lane == 0)
                         qc[q - I.q_begin] += c;
                 }
+            };
+            // queries q and q + kBmWaves: the peeled compares both have (the smaller r) go side by
+            // side; a lone last query is paired with itself and the copy's result dropped
+            for (uint32_t q = I.q_begin + wave; q < I.q_end; q += 2u * kBmWaves) {
+                const bool two = q + kBmWaves < I.q_end;
+                const BmQuery A = ldc(&a.queries[q]);
+                const BmQuery B = ldc(&a.queries[two ? q + kBmWaves : q]);
+                uint32_t fa[4], fb[4];
+                init_f(A, fa);
+                init_f(B, fb);
+                const uint32_t rj = min(A.mr >> 24, B.mr >> 24);
+                bm_step(bm, A.e0, lane, fa);
+                bm_step(bm, B.e0, lane, fb);
+                if (rj >= 2u) {
+                    bm_step(bm, A.e1, lane, fa);
+                    bm_step(bm, B.e1, lane, fb);
+                }
+                for (uint32_t l = 2; l < rj; ++l) {
+                    const uint32_t ea = ldc(&a.steps[A.steps_off + l]), eb = ldc(&a.steps[B.steps_off + l]);
+                    bm_step(bm, ea, lane, fa);
+                    bm_step(bm, eb, lane, fb);
+                }
+                finish(A, fa, rj, q);
+                if (two)
+                    finish(B, fb, rj, q + kBmWaves);
             }
             __syncthreads();
         }
