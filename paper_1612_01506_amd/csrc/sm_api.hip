@@ -999,7 +999,7 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
     const uint64_t max_halo = (kMaxLds - kQChunk * sizeof(uint32_t)) / 2 - T;
 
     // ---- per-text alphabets (bitmap mode needs the histogram and kBmMinQueries queries)
-    auto bm_wps = [](uint64_t m_max) { return (uint32_t)round_up(258 + ceil_div(m_max, 32), 4); };
+    auto bm_wps = [](uint64_t m_max) { return (uint32_t)round_up(kBmT / 32 + 2 + ceil_div(m_max, 32), 4); };
     auto bm_lds = [&](uint32_t slots, uint32_t wps) {
         return (uint64_t)slots * wps * 4 + 256 + kBmQChunk * sizeof(uint32_t);
     };

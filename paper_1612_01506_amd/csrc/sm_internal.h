@@ -109,7 +109,8 @@ struct BatchArgs {
 // funnel shift + AND per compare.
 constexpr uint32_t kBmWG = 1024;             // threads per bitmap workgroup: 16 waves
 constexpr uint32_t kBmWaves = kBmWG / 64;
-constexpr uint32_t kBmT = 8192;              // starts per bitmap tile: 4 vectors of 64 lanes x 32 bits
+constexpr uint32_t kBmT = 8192;              // starts per bitmap tile: kBmV vectors of 64 lanes x 32 bits
+constexpr int kBmV = (int)(kBmT / 2048);
 constexpr uint32_t kBmQChunk = 1024;         // queries per bitmap work item
 constexpr uint32_t kBmMaxLds = 163840;       // LDS per workgroup on gfx950
 
@@ -117,7 +118,7 @@ struct BmItem {
     TextView tv;
     uint64_t tile_begin, tile_end;  // tiles of kBmT starts
     uint32_t q_begin, q_end;        // into the BmQuery array, at most kBmQChunk
-    uint32_t wps;                   // bitmap words per slot (multiple of 4) >= 258 + ceil(m_max / 32)
+    uint32_t wps;                   // bitmap words per slot (multiple of 4) >= kBmT / 32 + 2 + ceil(m_max / 32)
     uint32_t nslots;                // slots of the text's alphabet
     const uint8_t *smap;            // 256 bytes: symbol -> slot, 0xFF if the symbol is absent
 };

@@ -1150,20 +1150,39 @@ __device__ __forceinline__ uint32_t valid_bits(uint64_t p0, uint64_t first, uint
     return upto_b & ~below_a;
 }
 
-// One compare on the bitmaps for the four 2048-start vectors of the tile:
+// One compare on the bitmaps for the kBmV 2048-start vectors of the tile:
 // bits of the window at offset j are a funnel shift of two bitmap words.
-__device__ __forceinline__ void bm_step(const uint32_t *bm, uint32_t e, uint32_t lane, uint32_t (&f)[4])
+__device__ __forceinline__ void bm_step(const uint32_t *bm, uint32_t e, uint32_t lane, uint32_t (&f)[kBmV])
 {
     const uint32_t base = (e >> 5) + lane, sh = e & 31u;
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
+    for (int v = 0; v < kBmV; ++v)
         f[v] &= __builtin_amdgcn_alignbit(bm[base + 64u * v + 1u], bm[base + 64u * v], sh);
+}
+
+// Wave-uniform: any start of the tile still alive?  And how many.
+__device__ __forceinline__ bool bm_any(const uint32_t (&f)[kBmV])
+{
+    uint32_t o = 0;
+#pragma unroll
+    for (int v = 0; v < kBmV; ++v)
+        o |= f[v];
+    return __any(o != 0u);
+}
+
+__device__ __forceinline__ uint32_t bm_popc(const uint32_t (&f)[kBmV])
+{
+    uint32_t c = 0;
+#pragma unroll
+    for (int v = 0; v < kBmV; ++v)
+        c += __popc(f[v]);
+    return c;
 }
 
 // Persistent batched count over bitmap tiles.  Work item = (text, tile range,
 // chunk of <= kBmQChunk queries).  Per tile: zero the bitmaps, set one bit per
 // text byte (LDS atomic OR), then wave w runs queries w, w + 16, ... over the
-// 8192 starts of the tile: the first r compares unconditionally, then one zero
+// kBmT starts of the tile: the first r compares unconditionally, then one zero
 // test (a wave-wide ballot) after each further compare (Algorithm 4).  A wave
 // takes its queries in pairs and issues the two peels' compares side by side,
 // so the LDS reads of both are in flight together.  Each query's count for the
@@ -1207,29 +1226,35 @@ __global__ __launch_bounds__(kBmWG) void k_batch_bitmap(BmArgs a)
             }
             __syncthreads();
             const uint64_t tile_end = ts + kBmT - 1u;
-            auto init_f = [&](const BmQuery &Q, uint32_t (&f)[4]) {
+            auto init_f = [&](const BmQuery &Q, uint32_t (&f)[kBmV]) {
                 const uint64_t last = hi - (Q.mr & 0xFFFFFFu);
                 if (ts >= lo && tile_end <= last) {
-                    f[0] = f[1] = f[2] = f[3] = 0xFFFFFFFFu;
+                    if constexpr (kBmV == 4) {
+                        f[0] = f[1] = f[2] = f[3] = 0xFFFFFFFFu;
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < kBmV; ++v)
+                            f[v] = 0xFFFFFFFFu;
+                    }
                 } else {
 #pragma unroll
-                    for (int v = 0; v < 4; ++v)
+                    for (int v = 0; v < kBmV; ++v)
                         f[v] = valid_bits(ts + 2048u * v + 32u * lane, lo, last);
                 }
             };
             // the rest of one query from compare l0 on, and its count
-            auto finish = [&](const BmQuery &Q, uint32_t (&f)[4], uint32_t l0, uint32_t q) {
+            auto finish = [&](const BmQuery &Q, uint32_t (&f)[kBmV], uint32_t l0, uint32_t q) {
                 const uint32_t m = Q.mr & 0xFFFFFFu, r = Q.mr >> 24;
                 const uint32_t *st = a.steps + Q.steps_off;
                 for (uint32_t l = l0; l < r; ++l)
                     bm_step(bm, ldc(&st[l]), lane, f);
-                bool alive = __any((f[0] | f[1] | f[2] | f[3]) != 0u);
+                bool alive = bm_any(f);
                 for (uint32_t l = r; alive && l < m; ++l) {
                     bm_step(bm, l == 1u ? Q.e1 : ldc(&st[l]), lane, f);
-                    alive = __any((f[0] | f[1] | f[2] | f[3]) != 0u);
+                    alive = bm_any(f);
                 }
                 if (alive) {
-                    const uint32_t c = wave_sum32(__popc(f[0]) + __popc(f[1]) + __popc(f[2]) + __popc(f[3]));
+                    const uint32_t c = wave_sum32(bm_popc(f));
                     if (lane == 0)
                         qc[q - I.q_begin] += c;
                 }
@@ -1240,7 +1265,7 @@ __global__ __launch_bounds__(kBmWG) void k_batch_bitmap(BmArgs a)
                 const bool two = q + kBmWaves < I.q_end;
                 const BmQuery A = ldc(&a.queries[q]);
                 const BmQuery B = ldc(&a.queries[two ? q + kBmWaves : q]);
-                uint32_t fa[4], fb[4];
+                uint32_t fa[kBmV], fb[kBmV];
                 init_f(A, fa);
                 init_f(B, fb);
                 const uint32_t rj = min(A.mr >> 24, B.mr >> 24);
