@@ -32,7 +32,7 @@ CLASSES = (2, 4, 20, 95)            # alphabet classes (symbols present)
 M_BUCKETS = (8, 64, 512, 4096)       # upper bounds of pattern-length buckets
 N_BUCKETS = (16 << 20, 1 << 62)      # upper bounds of text-size buckets
 TILE_KIB = (4, 8, 16)
-WGS_PER_CU = (4, 6, 8)
+WGS_PER_CU = (4, 5, 6, 8)
 PEELS = (1, 2, 3, 4, 5, 6, 7, 8)     # every compiled peel factor
 GRID = [(tk, w, r) for tk in TILE_KIB for w in WGS_PER_CU for r in PEELS]
 
@@ -98,7 +98,9 @@ def params_for(hist, m: int, n: int) -> dict | None:
     return {"tile_kib": e["tile_kib"], "wgs_per_cu": e["wgs_per_cu"], "peel": e["peel"]}
 
 
-def tune(sizes=(8 << 20, 1 << 30), patterns_per_cell: int = 4, reps: int = 3, log=print) -> dict:
+def tune(sizes=(8 << 20, 1 << 30), patterns_per_cell: int = 4, rounds: int = 3, log=print) -> dict:
+    """Every setting of a cell is timed once per round, the rounds interleaved over the grid so that
+    slow drifts of the device hit all settings alike; a setting's time is its median over the rounds."""
     import torch
 
     from . import Patterns, Text
@@ -123,19 +125,20 @@ def tune(sizes=(8 << 20, 1 << 30), patterns_per_cell: int = 4, reps: int = 3, lo
                 pats = [synth.substring_pattern(t_host, min(m, n), g)[0] for m in ms]
                 ps = Patterns(pats, "freq", t.hist)
                 out = torch.zeros(1, dtype=torch.int64, device=dev)
-                best = None
-                for tk, w, r in GRID:
-                    for i in range(len(pats)):
-                        ps.count_async(i, t.t, out, peel=r, tile_kib=tk, wgs_per_cu=w)
-                    torch.cuda.synchronize()
-                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                    e0.record()
-                    for _ in range(reps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                samples = {cfg: [] for cfg in GRID}
+                for rnd in range(rounds + 1):          # round 0 warms up (attributes, caches) and is not kept
+                    for tk, w, r in GRID:
+                        e0.record()
                         for i in range(len(pats)):
                             ps.count_async(i, t.t, out, peel=r, tile_kib=tk, wgs_per_cu=w)
-                    e1.record()
-                    torch.cuda.synchronize()
-                    us = e0.elapsed_time(e1) * 1e3 / (reps * len(pats))
+                        e1.record()
+                        torch.cuda.synchronize()
+                        if rnd:
+                            samples[(tk, w, r)].append(e0.elapsed_time(e1) * 1e3 / len(pats))
+                best = None
+                for (tk, w, r), v in samples.items():
+                    us = float(np.median(v))
                     timings[f"{sigma}/{mi}/{ni}/{tk}/{w}/{r}"] = round(us, 2)
                     if best is None or us < best[0]:
                         best = (us, tk, w, r)
@@ -155,9 +158,9 @@ def tune(sizes=(8 << 20, 1 << 30), patterns_per_cell: int = 4, reps: int = 3, lo
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--out", required=True)
-    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--rounds", type=int, default=3)
     args = ap.parse_args()
-    tab = tune(reps=args.reps)
+    tab = tune(rounds=args.rounds)
     with open(args.out, "w") as f:
         json.dump(tab, f, indent=1)
     print(f"wrote {args.out}: {len(tab['cells'])} cells")

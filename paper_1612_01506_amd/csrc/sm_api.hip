@@ -482,6 +482,11 @@ void build_steps(const uint8_t *p, uint64_t m, const int32_t *order, uint64_t *o
 
 // Tiles are dealt to workgroups in chunks of 4 contiguous tiles.
 constexpr uint32_t kChunkLog2 = 2;
+// Texts from this size on are read with non-temporal tile loads: repeated
+// searches of a 1 GiB text run about 8% faster with them, while texts of 128
+// to 384 MiB, which the 256 MB last-level cache partly holds between
+// searches, run faster without.
+constexpr uint64_t kStreamLoadBytes = 512ull << 20;
 
 struct Tune {
     int r;
@@ -549,7 +554,7 @@ int launch_count(Dev &d, const TextView &tv, uint64_t m, const uint64_t *steps_d
         a.chunk_log2 = ck;
         const uint64_t nchunks = ceil_div(a.ntiles, 1ull << a.chunk_log2);
         const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(nchunks, target));
-        HIP_TRY(launch_count_staged(a, cpl, tu.r, (unsigned)grid, s));
+        HIP_TRY(launch_count_staged(a, cpl, tu.r, tv.n >= kStreamLoadBytes, (unsigned)grid, s));
     } else {
         const uint64_t grid = std::min<uint64_t>(ceil_div(a.nblocks, kWaves), target);
         HIP_TRY(launch_count_global(a, tu.r, (unsigned)grid, s));

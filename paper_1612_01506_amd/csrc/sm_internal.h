@@ -142,7 +142,8 @@ struct BmArgs {
 };
 
 // Host-side launchers (sm_kernels.hip).  Each returns a hipError_t.
-hipError_t launch_count_staged(const CountArgs &a, int cpl, int r, unsigned grid, hipStream_t s);
+// stream_loads: tile loads with the non-temporal cache policy (texts far larger than the last-level cache)
+hipError_t launch_count_staged(const CountArgs &a, int cpl, int r, bool stream_loads, unsigned grid, hipStream_t s);
 hipError_t launch_count_global(const CountArgs &a, int r, unsigned grid, hipStream_t s);
 hipError_t launch_scan_groups(const unsigned long long *gs, uint64_t ngroups, unsigned long long *go,
                               unsigned long long *total, hipStream_t s);
