@@ -482,10 +482,10 @@ void build_steps(const uint8_t *p, uint64_t m, const int32_t *order, uint64_t *o
 
 // Tiles are dealt to workgroups in chunks of 4 contiguous tiles.
 constexpr uint32_t kChunkLog2 = 2;
-// Texts from this size on are read with non-temporal tile loads: repeated
-// searches of a 1 GiB text run about 8% faster with them, while texts of 128
-// to 384 MiB, which the 256 MB last-level cache partly holds between
-// searches, run faster without.
+// Texts (and byte-tile batches whose texts together are) from this size on
+// are read with non-temporal tile loads: repeated searches of a 1 GiB text run
+// about 8% faster with them, while texts of 128 to 384 MiB, which the 256 MB
+// last-level cache partly holds between searches, run faster without.
 constexpr uint64_t kStreamLoadBytes = 512ull << 20;
 
 struct Tune {
@@ -1398,7 +1398,9 @@ int launch_plan(Dev &d, const LaunchPlan &lp, const uint8_t *dev, unsigned long 
         a.counts = counts;
         a.halo_max = lp.halo_max;
         a.chunk_log2 = kChunkLog2;
-        HIP_TRY(launch_batch_staged(a, lp.cpl, (unsigned)lp.st_grid, s));
+        // the plan's tiles hold all its texts once: stream them when they far exceed the cache
+        const bool stream_loads = lp.ntiles * (4096ull * (uint64_t)lp.cpl) >= kStreamLoadBytes;
+        HIP_TRY(launch_batch_staged(a, lp.cpl, stream_loads, (unsigned)lp.st_grid, s));
     }
     for (const auto &L : lp.longs)
         SM_TRY(launch_count(d, L.tv, L.m, reinterpret_cast<const uint64_t *>(dev + lp.o_steps) + L.steps_off, L.tu,

@@ -154,7 +154,7 @@ hipError_t launch_fill_report(uint32_t *bc, uint64_t nblocks, unsigned long long
                               hipStream_t s);
 hipError_t launch_hist(const TextView &tv, unsigned long long *hist, unsigned grid, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v, hipStream_t s);
-hipError_t launch_batch_staged(const BatchArgs &a, int cpl, unsigned grid, hipStream_t s);
+hipError_t launch_batch_staged(const BatchArgs &a, int cpl, bool stream_loads, unsigned grid, hipStream_t s);
 hipError_t launch_batch_bitmap(const BmArgs &a, unsigned grid, uint32_t lds_bytes, hipStream_t s);
 // Non-overlapping selection over the ascending occurrence list (c entries).
 constexpr uint64_t kNoChunkEntries = 4 * kWG;  // list entries per compaction chunk

@@ -922,11 +922,12 @@ __global__ void k_fill_u64(unsigned long long *p, uint64_t n, unsigned long long
 // may belong to another text.  Every query of the tile's chunk runs over the
 // staged tile; per-query counts gather in LDS and are flushed (one 64-bit
 // atomicAdd per nonzero query) whenever the workgroup moves to another chunk.
-template <int CPL, bool REPORT>
+template <int CPL, bool REPORT, bool STREAM>
 __global__ __launch_bounds__(kWG) void k_batch_staged(BatchArgs a)
 {
     extern __shared__ __align__(16) uint8_t lds[];
     constexpr uint32_t T = kWG * 16u * CPL;
+    constexpr int kPolicy = STREAM ? kLoadStream : kLoadDefault;
     const uint32_t TB = T + a.halo_max;
     uint32_t *qc = reinterpret_cast<uint32_t *>(lds + 2u * TB);
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = wave_id();
@@ -946,7 +947,7 @@ __global__ __launch_bounds__(kWG) void k_batch_staged(BatchArgs a)
     uint64_t g = tile_of(0);
     if (g < a.ntiles) {
         const BatchChunk C = ldc(&a.chunks[ldc(&a.tile_chunk[g])]);
-        dma_tile<CPL>(C.tv, (g - C.tile0) * T, tid, C.halo >> 4, lds);
+        dma_tile<CPL, kPolicy>(C.tv, (g - C.tile0) * T, tid, C.halo >> 4, lds);
     }
     uint32_t cur = 0xFFFFFFFFu;
     for (uint64_t i = 0; g < a.ntiles; ++i) {
@@ -968,7 +969,7 @@ __global__ __launch_bounds__(kWG) void k_batch_staged(BatchArgs a)
         }
         if (gn < a.ntiles) {
             const BatchChunk N = ldc(&a.chunks[ldc(&a.tile_chunk[gn])]);
-            dma_tile<CPL>(N.tv, (gn - N.tile0) * T, tid, N.halo >> 4, lds + ((i + 1) & 1u) * TB);
+            dma_tile<CPL, kPolicy>(N.tv, (gn - N.tile0) * T, tid, N.halo >> 4, lds + ((i + 1) & 1u) * TB);
         }
         for (uint32_t q = C.q_begin; q < C.q_end; ++q) {
             const BatchQuery Q = ldc(&a.queries[q]);
@@ -1422,25 +1423,31 @@ hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long
     return hipGetLastError();
 }
 
-template <int CPL>
+template <int CPL, bool STREAM>
 static hipError_t launch_batch_t(const BatchArgs &a, unsigned grid, hipStream_t s)
 {
     const uint32_t lds = 2u * (kWG * 16u * CPL + a.halo_max) + kQChunk * (uint32_t)sizeof(uint32_t);
     if (a.reports)
-        hipLaunchKernelGGL((k_batch_staged<CPL, true>), dim3(grid), dim3(kWG), lds, s, a);
+        hipLaunchKernelGGL((k_batch_staged<CPL, true, STREAM>), dim3(grid), dim3(kWG), lds, s, a);
     else
-        hipLaunchKernelGGL((k_batch_staged<CPL, false>), dim3(grid), dim3(kWG), lds, s, a);
+        hipLaunchKernelGGL((k_batch_staged<CPL, false, STREAM>), dim3(grid), dim3(kWG), lds, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_batch_staged(const BatchArgs &a, int cpl, unsigned grid, hipStream_t s)
+template <bool STREAM>
+static hipError_t launch_batch_c(const BatchArgs &a, int cpl, unsigned grid, hipStream_t s)
 {
     switch (cpl) {
-    case 1: return launch_batch_t<1>(a, grid, s);
-    case 2: return launch_batch_t<2>(a, grid, s);
-    case 4: return launch_batch_t<4>(a, grid, s);
+    case 1: return launch_batch_t<1, STREAM>(a, grid, s);
+    case 2: return launch_batch_t<2, STREAM>(a, grid, s);
+    case 4: return launch_batch_t<4, STREAM>(a, grid, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_batch_staged(const BatchArgs &a, int cpl, bool stream_loads, unsigned grid, hipStream_t s)
+{
+    return stream_loads ? launch_batch_c<true>(a, cpl, grid, s) : launch_batch_c<false>(a, cpl, grid, s);
 }
 
 }  // namespace smk
@@ -1524,8 +1531,10 @@ static hipError_t prime_cpl()
                         reinterpret_cast<const void *>(&k_count_staged<CPL, 6, true>),
                         reinterpret_cast<const void *>(&k_count_staged<CPL, 7, true>),
                         reinterpret_cast<const void *>(&k_count_staged<CPL, 8, true>),
-                        reinterpret_cast<const void *>(&k_batch_staged<CPL, false>),
-                        reinterpret_cast<const void *>(&k_batch_staged<CPL, true>)};
+                        reinterpret_cast<const void *>(&k_batch_staged<CPL, false, false>),
+                        reinterpret_cast<const void *>(&k_batch_staged<CPL, true, false>),
+                        reinterpret_cast<const void *>(&k_batch_staged<CPL, false, true>),
+                        reinterpret_cast<const void *>(&k_batch_staged<CPL, true, true>)};
     for (const void *k : ks) {
         hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
         if (e != hipSuccess)
