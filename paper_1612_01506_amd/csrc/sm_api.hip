@@ -1507,7 +1507,7 @@ int32_t sm_histogram(const uint8_t *t, uint64_t n, uint64_t *hist_dev, void *str
     // two 64 KiB workgroups fit a compute unit's LDS
     const uint64_t grid =
         std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(nchunks, kHistWG), (uint64_t)std::max(d->cus, 1) * 2));
-    HIP_TRY(launch_hist(tv, h, (unsigned)grid, s));
+    HIP_TRY(launch_hist(tv, h, n >= kStreamLoadBytes, (unsigned)grid, s));
     return SM_OK;
 }
 

@@ -152,7 +152,7 @@ hipError_t launch_report_write(const CountArgs &a, uint32_t *bc, unsigned long l
                                hipStream_t s);
 hipError_t launch_fill_report(uint32_t *bc, uint64_t nblocks, unsigned long long *gs, uint64_t ngroups,
                               hipStream_t s);
-hipError_t launch_hist(const TextView &tv, unsigned long long *hist, unsigned grid, hipStream_t s);
+hipError_t launch_hist(const TextView &tv, unsigned long long *hist, bool stream_loads, unsigned grid, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_batch_staged(const BatchArgs &a, int cpl, bool stream_loads, unsigned grid, hipStream_t s);
 hipError_t launch_batch_bitmap(const BmArgs &a, unsigned grid, uint32_t lds_bytes, hipStream_t s);

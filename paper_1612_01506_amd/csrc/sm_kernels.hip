@@ -786,6 +786,20 @@ __device__ __forceinline__ void hist_add16(uint8_t *hb, uint32_t lane4, uint4 v)
     }
 }
 
+// 16 text bytes, with the streaming (non-temporal) cache policy if STREAM.
+template <bool STREAM>
+__device__ __forceinline__ uint4 load16(const uint8_t *p)
+{
+    if constexpr (STREAM) {
+        typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+        const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+        return make_uint4(v.x, v.y, v.z, v.w);
+    } else {
+        return *reinterpret_cast<const uint4 *>(p);
+    }
+}
+
+template <bool STREAM>
 __global__ __launch_bounds__(kHistWG) void k_hist(TextView tv, unsigned long long *hist)
 {
     extern __shared__ __align__(16) uint32_t h[];  // [256][64]
@@ -801,13 +815,13 @@ __global__ __launch_bounds__(kHistWG) void k_hist(TextView tv, unsigned long lon
     const uint64_t stride = (uint64_t)gridDim.x * kHistWG;
     uint64_t c = c_lo + (uint64_t)blockIdx.x * kHistWG + tid;
     for (; c + stride < c_hi; c += 2 * stride) {
-        const uint4 v0 = *reinterpret_cast<const uint4 *>(tv.base + 16u * c);
-        const uint4 v1 = *reinterpret_cast<const uint4 *>(tv.base + 16u * (c + stride));
+        const uint4 v0 = load16<STREAM>(tv.base + 16u * c);
+        const uint4 v1 = load16<STREAM>(tv.base + 16u * (c + stride));
         hist_add16(hb, lane4, v0);
         hist_add16(hb, lane4, v1);
     }
     if (c < c_hi)
-        hist_add16(hb, lane4, *reinterpret_cast<const uint4 *>(tv.base + 16u * c));
+        hist_add16(hb, lane4, load16<STREAM>(tv.base + 16u * c));
     if (blockIdx.x == 0 && tid < 2u) {
         // edge chunks: the one holding the first bytes (if the text starts mid-chunk) and the one
         // holding the last bytes (if it ends mid-chunk and is not that same chunk)
@@ -1403,9 +1417,12 @@ hipError_t launch_fill_report(uint32_t *bc, uint64_t nblocks, unsigned long long
     return hipGetLastError();
 }
 
-hipError_t launch_hist(const TextView &tv, unsigned long long *hist, unsigned grid, hipStream_t s)
+hipError_t launch_hist(const TextView &tv, unsigned long long *hist, bool stream_loads, unsigned grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_hist, dim3(grid), dim3(kHistWG), kHistLds, s, tv, hist);
+    if (stream_loads)
+        hipLaunchKernelGGL(k_hist<true>, dim3(grid), dim3(kHistWG), kHistLds, s, tv, hist);
+    else
+        hipLaunchKernelGGL(k_hist<false>, dim3(grid), dim3(kHistWG), kHistLds, s, tv, hist);
     return hipGetLastError();
 }
 
@@ -1553,7 +1570,7 @@ hipError_t prime_kernel_attrs()
         return e;
     if ((e = lds_attr(&k_report_write_multi, (int)kMaxLds)) != hipSuccess)
         return e;
-    if ((e = lds_attr(&k_hist, (int)kHistLds)) != hipSuccess)
+    if ((e = lds_attr(&k_hist<false>, (int)kHistLds)) != hipSuccess || (e = lds_attr(&k_hist<true>, (int)kHistLds)) != hipSuccess)
         return e;
     if ((e = lds_attr(&k_bigram, (int)kBgLds)) != hipSuccess)
         return e;
