@@ -897,6 +897,7 @@ struct LaunchPlan {
     uint64_t n_bitems = 0;
     uint32_t bm_words = 0;
     uint64_t bm_grid = 0;
+    bool bm_two = false;  // two workgroups per CU fit the bitmaps' LDS
     // byte-tile launch
     uint64_t ntiles = 0;
     uint32_t halo_max = 0;
@@ -1344,6 +1345,7 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
     {
         const uint32_t lds = lp->bm_words * 4 + 256 + kBmQChunk * sizeof(uint32_t);
         const uint64_t per_cu = std::max<uint64_t>(1, kBmMaxLds / lds);
+        lp->bm_two = per_cu >= 2;
         lp->bm_grid = std::min<uint64_t>(bitems.size(), (uint64_t)std::max(d.cus, 1) * std::min<uint64_t>(per_cu, 2));
     }
     lp->ntiles = tile_chunk.size();
@@ -1385,7 +1387,7 @@ int launch_plan(Dev &d, const LaunchPlan &lp, const uint8_t *dev, unsigned long 
         a.counts = counts;
         a.bm_words = lp.bm_words;
         const uint32_t lds = a.bm_words * 4 + 256 + kBmQChunk * sizeof(uint32_t);
-        HIP_TRY(launch_batch_bitmap(a, (unsigned)lp.bm_grid, lds, s));
+        HIP_TRY(launch_batch_bitmap(a, (unsigned)lp.bm_grid, lds, lp.bm_two, s));
     }
     if (lp.ntiles) {
         BatchArgs a{};

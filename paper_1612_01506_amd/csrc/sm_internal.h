@@ -155,7 +155,8 @@ hipError_t launch_fill_report(uint32_t *bc, uint64_t nblocks, unsigned long long
 hipError_t launch_hist(const TextView &tv, unsigned long long *hist, bool stream_loads, unsigned grid, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_batch_staged(const BatchArgs &a, int cpl, bool stream_loads, unsigned grid, hipStream_t s);
-hipError_t launch_batch_bitmap(const BmArgs &a, unsigned grid, uint32_t lds_bytes, hipStream_t s);
+// two_per_cu: lds_bytes lets two workgroups share a CU (the register-capped instance runs)
+hipError_t launch_batch_bitmap(const BmArgs &a, unsigned grid, uint32_t lds_bytes, bool two_per_cu, hipStream_t s);
 // Non-overlapping selection over the ascending occurrence list (c entries).
 constexpr uint64_t kNoChunkEntries = 4 * kWG;  // list entries per compaction chunk
 hipError_t launch_no_next(const unsigned long long *pos, uint64_t c, uint32_t m, uint32_t *nxt, uint32_t *mark,

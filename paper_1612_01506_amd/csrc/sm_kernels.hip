@@ -1211,7 +1211,7 @@ __device__ __forceinline__ uint32_t bm_popc(const uint32_t (&f)[kBmV])
 // takes its queries in pairs and issues the two peels' compares side by side,
 // so the LDS reads of both are in flight together.  Each query's count for the
 // item gathers in an LDS counter owned by one wave.
-__global__ __launch_bounds__(kBmWG) void k_batch_bitmap(BmArgs a)
+__device__ __forceinline__ void batch_bitmap(const BmArgs &a)
 {
     extern __shared__ __align__(16) uint32_t bm[];
     uint8_t *smap = reinterpret_cast<uint8_t *>(bm + a.bm_words);
@@ -1316,6 +1316,19 @@ __global__ __launch_bounds__(kBmWG) void k_batch_bitmap(BmArgs a)
                 atomicAdd(&a.counts[a.outs[I.q_begin + i]], (unsigned long long)v);
         }
     }
+}
+
+__global__ __launch_bounds__(kBmWG) void k_batch_bitmap(BmArgs a)
+{
+    batch_bitmap(a);
+}
+
+// The same for alphabets whose bitmaps leave room for two workgroups per CU:
+// registers capped at 64 per lane so that both are resident (8 waves per
+// SIMD), which hides more of the latency of small alphabets' long tails.
+__global__ __launch_bounds__(kBmWG) __attribute__((amdgpu_waves_per_eu(8))) void k_batch_bitmap2(BmArgs a)
+{
+    batch_bitmap(a);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -1470,9 +1483,12 @@ hipError_t launch_batch_staged(const BatchArgs &a, int cpl, bool stream_loads, u
 }  // namespace smk
 
 namespace smk {
-hipError_t launch_batch_bitmap(const BmArgs &a, unsigned grid, uint32_t lds_bytes, hipStream_t s)
+hipError_t launch_batch_bitmap(const BmArgs &a, unsigned grid, uint32_t lds_bytes, bool two_per_cu, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_batch_bitmap, dim3(grid), dim3(kBmWG), lds_bytes, s, a);
+    if (two_per_cu)
+        hipLaunchKernelGGL(k_batch_bitmap2, dim3(grid), dim3(kBmWG), lds_bytes, s, a);
+    else
+        hipLaunchKernelGGL(k_batch_bitmap, dim3(grid), dim3(kBmWG), lds_bytes, s, a);
     return hipGetLastError();
 }
 }  // namespace smk
@@ -1574,6 +1590,8 @@ hipError_t prime_kernel_attrs()
         return e;
     if ((e = lds_attr(&k_bigram, (int)kBgLds)) != hipSuccess)
         return e;
-    return lds_attr(&k_batch_bitmap, (int)kBmMaxLds);
+    if ((e = lds_attr(&k_batch_bitmap, (int)kBmMaxLds)) != hipSuccess)
+        return e;
+    return lds_attr(&k_batch_bitmap2, (int)kBmMaxLds);
 }
 }  // namespace smk
