@@ -138,3 +138,23 @@ def test_text_beyond_4gib(dev):
     q = b"ACGTA"
     assert sm.count(text, q) == oracle.count(q, t)
     assert sm.count_batch([text], [(0, p), (0, q)]).cpu().tolist() == [want.size, oracle.count(q, t)]
+
+
+def test_report_batch_over_512mib(dev):
+    """A reporting batch whose texts total more than 512 MiB (streaming tile loads in the byte-tile
+    kernel's reporting instance): every list and total against the oracle."""
+    n = 600 << 20
+    t = synth.zipf_text(n, 95, 1.0, family=15, stream=1)
+    text = sm.Text(torch.from_numpy(t).to(dev))          # no histogram: byte-tile mode for every query
+    g = np.random.default_rng(600)
+    pats = [synth.substring_pattern(t, m, g)[0] for m in (3, 8, 8, 32, 200, 1000)]
+    caps = [50_000, 100, 7, 1000, 10, 1]
+    pos, totals = sm.report_batch([text.t], [(0, p) for p in pats], caps)
+    pos = pos.cpu().numpy().astype(np.uint64)
+    totals = totals.cpu().tolist()
+    off = 0
+    for i, (p, cap) in enumerate(zip(pats, caps)):
+        total, want = oracle.report_full(p, t, cap)
+        assert totals[i] == total, (i, len(p))
+        assert pos[off:off + min(total, cap)].tolist() == want.tolist(), (i, len(p))
+        off += cap
