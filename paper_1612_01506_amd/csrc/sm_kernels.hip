@@ -316,6 +316,8 @@ __device__ __forceinline__ bool search_vector(const uint64_t *steps, const uint6
 #pragma unroll
     for (int l = 0; l < R; ++l)
         tx.step(pk[l], d);
+    if (m == (uint32_t)R)  // every compare done: d is final, and count_alive gives 0 for a dead vector
+        return true;
     if (!any_alive(d))
         return false;
     return search_tail(steps, R, m, lane, d, tx);
