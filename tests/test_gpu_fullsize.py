@@ -36,22 +36,24 @@ def test_single_count_8mib(dev):
 
 def test_zipf_1gib_bench_configuration(dev):
     """1 GiB Zipf text, 100 substrings per m in {2..1024}: prepared frequency-ordered patterns counted
-    and reported asynchronously exactly as the benchmark step does."""
+    and reported asynchronously through the resident Text (the tuning table's launch parameters and
+    streaming tile loads), exactly as the benchmark step does."""
     t, pats = synth.zipf_workload(n=1 << 30, per_m=100)
     td = torch.from_numpy(t).to(dev)
-    hist = sm.histogram(td).cpu().numpy().view(np.uint64)
+    text = sm.Text(td)
+    hist = text.hist
     assert hist.tolist() == oracle.hist(t).tolist()
     patterns = [p for p, _ in pats]
     ps = sm.Patterns(patterns, "freq", hist)
     counts = torch.zeros(len(patterns), dtype=torch.int64, device=dev)
     for i in range(len(patterns)):
-        ps.count_async(i, td, counts[i:i + 1])
+        ps.count_async(i, text, counts[i:i + 1])
     rep = [i for i, (_, r) in enumerate(pats) if r]
     cap = 4096
     pos = torch.empty((len(rep), cap), dtype=torch.int64, device=dev)
     tot = torch.empty(len(rep), dtype=torch.int64, device=dev)
     for k, i in enumerate(rep):
-        ps.report_async(i, td, pos[k], tot[k:k + 1])
+        ps.report_async(i, text, pos[k], tot[k:k + 1])
     torch.cuda.synchronize()
     counts = counts.cpu().numpy()
     tot = tot.cpu().numpy()
@@ -60,9 +62,16 @@ def test_zipf_1gib_bench_configuration(dev):
         assert tot[k] == counts[i]
     for i in range(0, len(patterns), 100):          # one pattern per length against the oracle
         assert counts[i] == oracle.count(patterns[i], t), len(patterns[i])
-    k = 0
-    want = oracle.report(patterns[rep[k]], t)
-    assert pos[k, :min(int(tot[k]), cap)].cpu().numpy().astype(np.uint64).tolist() == want[:cap].tolist()
+    # the default launch (no tuning table: 8 KiB tiles, 6 workgroups per CU) gives the same counts
+    plain = torch.zeros(len(patterns), dtype=torch.int64, device=dev)
+    for i in range(len(patterns)):
+        ps.count_async(i, td, plain[i:i + 1])
+    torch.cuda.synchronize()
+    assert plain.cpu().numpy().tolist() == counts.tolist()
+    for k in range(0, len(rep), 100):                # one reported list per length against the oracle
+        want = oracle.report(patterns[rep[k]], t)
+        got = pos[k, :min(int(tot[k]), cap)].cpu().numpy().astype(np.uint64)
+        assert got.tolist() == want[:cap].tolist(), len(patterns[rep[k]])
     ps.close()
 
 
