@@ -88,6 +88,21 @@ __device__ __forceinline__ void init_alive(uint64_t wb, uint64_t first, uint64_t
     }
 }
 
+// The same dead-start bytes for the vector at tile offset boff, given the
+// valid starts of its tile as tile offsets lo..hi (32-bit, wave uniform),
+// ORed into d.
+__device__ __forceinline__ void mask_dead_tile(uint32_t boff, uint32_t lo, uint32_t hi, uint32_t lane,
+                                               uint32_t (&d)[4])
+{
+    const int32_t vlo = (int32_t)lo - (int32_t)boff, vhi = (int32_t)hi - (int32_t)boff;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int32_t q = (int32_t)(256u * k + 4u * lane);
+        const int32_t cl = min(max(vlo - q, 0), 4), ch = min(max(vhi - q + 1, 0), 4);
+        d[k] |= ~(bytes_below((uint32_t)ch) & ~bytes_below((uint32_t)cl));
+    }
+}
+
 // One compare step from an LDS tile.  lb points at the lane's first dword of
 // the wave vector; the window for pattern position j starts j bytes later.
 __device__ __forceinline__ void step_lds(const uint8_t *lb, uint64_t st, uint32_t (&d)[4])
@@ -97,6 +112,16 @@ __device__ __forceinline__ void step_lds(const uint8_t *lb, uint64_t st, uint32_
 #pragma unroll
     for (int k = 0; k < 4; ++k)
         d[k] |= __builtin_amdgcn_alignbyte(w[64 * k + 1], w[64 * k], sh) ^ rep;
+}
+
+// The first compare of a vector, which sets d instead of ORing into it.
+__device__ __forceinline__ void step_lds_first(const uint8_t *lb, uint64_t st, uint32_t (&d)[4])
+{
+    const uint32_t j = step_pos(st), rep = step_rep(st), sh = j & 3u;
+    const uint32_t *w = reinterpret_cast<const uint32_t *>(lb + (j & ~3u));
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        d[k] = __builtin_amdgcn_alignbyte(w[64 * k + 1], w[64 * k], sh) ^ rep;
 }
 
 __device__ __forceinline__ uint32_t load_dword(const TextView &tv, uint64_t u)
@@ -323,6 +348,29 @@ __device__ __forceinline__ bool search_vector(const uint64_t *steps, const uint6
     return search_tail(steps, R, m, lane, d, tx);
 }
 
+// The same for a vector at tile offset boff of an LDS tile whose valid starts
+// are the tile offsets lo..hi.  The first compare sets d, and the dead starts
+// of an edge vector (one not wholly inside lo..hi) are marked after the peel
+// rather than before: the AND of the compares with the validity mask, taken
+// in another order.  An inner vector thus spends no work on its bounds.
+template <int R>
+__device__ __forceinline__ bool search_vector_tile(const uint64_t *steps, const uint64_t (&pk)[R], uint32_t m,
+                                                   uint32_t lane, uint32_t (&d)[4], const LdsText &tx, bool edge,
+                                                   uint32_t boff, uint32_t lo, uint32_t hi)
+{
+    step_lds_first(tx.lb, pk[0], d);
+#pragma unroll
+    for (int l = 1; l < R; ++l)
+        tx.step(pk[l], d);
+    if (edge)
+        mask_dead_tile(boff, lo, hi, lane, d);
+    if (m == (uint32_t)R)
+        return true;
+    if (!any_alive(d))
+        return false;
+    return search_tail(steps, R, m, lane, d, tx);
+}
+
 // Same with a run-time peel factor r (batch queries carry their own r).
 template <typename Text>
 __device__ __forceinline__ bool search_vector_rt(const uint64_t *steps, uint32_t r, uint32_t m, uint32_t lane,
@@ -499,16 +547,21 @@ __global__ __launch_bounds__(kWG) void k_count_staged(CountArgs a)
         __syncthreads();  // tile visible to all waves; the other buffer is free
         if (next < a.ntiles)
             dma_tile<CPL, kPolicy>(a.tv, next * T, tid, hch, lds + ((i + 1) & 1u) * TB);
+        // the tile's valid starts as 32-bit tile offsets lo..hi (tile < ntiles, so last >= ts)
+        const uint64_t rem = a.last - ts;
+        const uint32_t hi = rem >= T ? T - 1u : (uint32_t)rem;
+        const uint32_t lo = ts < a.tv.first ? (uint32_t)(a.tv.first - ts) : 0u;
 #pragma unroll
         for (int b = 0; b < CPL; ++b) {
             const uint32_t boff = (wave * CPL + b) * kBlock;
             const uint64_t wb = ts + boff;
-            if (wb > a.last)
+            if (boff > hi)
                 break;
             uint32_t d[4];
-            init_alive(wb, a.tv.first, a.last, lane, d);
+            const bool edge = boff < lo || boff + (kBlock - 1u) > hi;
             const LdsText tx{cur + boff, cur + boff + 4u * lane};
-            const uint32_t c = search_vector<R>(a.steps, pk, a.m, lane, d, tx) ? count_alive(d) : 0u;
+            const uint32_t c =
+                search_vector_tile<R>(a.steps, pk, a.m, lane, d, tx, edge, boff, lo, hi) ? count_alive(d) : 0u;
             if (a.block_counts && __any(c != 0u)) {
                 const uint32_t s = wave_sum32(c);
                 if (lane == 0) {
