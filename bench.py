@@ -42,12 +42,12 @@ def kernel_sha() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def traffic_from_profile(n_bytes: int):
+def traffic_from_profile(n_bytes: int, kernel: str):
     """HBM bytes per count launch from the committed rocprofv3 --pmc summary, or None.
 
-    The summary stores FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the count
-    kernel and of a plain copy of known size; it is used only if it was taken
-    on the current kernel source.
+    The summary stores FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of one count
+    kernel instance and of a plain copy of known size; it is used only if it
+    was taken on the current kernel source and for the instance named.
     """
     if not os.path.exists(PMC_SUMMARY):
         return None
@@ -55,7 +55,7 @@ def traffic_from_profile(n_bytes: int):
     for line in open(PMC_SUMMARY):
         if line.startswith("JSON "):
             rec = json.loads(line[5:])
-    if not rec or rec.get("kernel_source_sha") != kernel_sha():
+    if not rec or rec.get("kernel_source_sha") != kernel_sha() or rec.get("kernel") != kernel:
         return None
     fscale = rec["copy_bytes"] / (rec["copy_fetch_kib"] * 1024.0)
     wscale = rec["copy_bytes"] / (rec["copy_write_kib"] * 1024.0)
@@ -154,7 +154,6 @@ def run_zipf(args):
     hev[1].record(stream)
     torch.cuda.synchronize()
     hist_ms = hev[0].elapsed_time(hev[1]) / 5
-    traffic = traffic_from_profile(n)
     from paper_1612_01506_amd import autotune
     launch_by_m = {len(patterns[i]): autotune.params_for(state["hist"], len(patterns[i]), n)
                    for i in range(0, len(patterns), args.per_m)}
@@ -167,6 +166,8 @@ def run_zipf(args):
     dom = max(set(insts), key=insts.count)
     kern = np.array([ms for i, ms in state["kern_ms"] if insts[i] == dom])
     avg_ms = float(kern.mean())
+    stream = str(n >= (512 << 20)).lower()   # the library streams tile loads for texts of 512 MiB and more
+    traffic = traffic_from_profile(n, f"void smk::k_count_staged<{dom[0] // 4}, {dom[1]}, {stream}>(smk::CountArgs)")
     achieved = n / (avg_ms * 1e-3) / 1e9
 
     if args.copy_probe:
@@ -221,8 +222,7 @@ def run_zipf(args):
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            # the library streams tile loads for texts of 512 MiB and more
-            "kernel": f"k_count_staged<{dom[0] // 4},{dom[1]},{str(n >= (512 << 20)).lower()}> ({dom[0]} KiB tiles, "
+            "kernel": f"k_count_staged<{dom[0] // 4},{dom[1]},{stream}> ({dom[0]} KiB tiles, "
                       f"peel {dom[1]})",
             "avg_launch_us": round(avg_ms * 1e3, 2),
             "timed_launches": len(kern),
