@@ -631,10 +631,18 @@ int64_t count_sync(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n, c
         SM_TRY(ring_commit(*d, u, s));
         return r < 0 ? fail((int)r, msg) : r;
     }
-    HIP_TRY(hipMemsetAsync(d->u64, 0, sizeof(unsigned long long), s));
-    SM_TRY(launch_count(*d, make_view(t, n), m, reinterpret_cast<const uint64_t *>(u.dev), tu, d->u64, nullptr, nullptr, s));
-    HIP_TRY(hipMemcpyAsync(d->hpin, d->u64, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-    SM_TRY(ring_commit(*d, u, s));
+    auto enqueue = [&]() -> int {
+        HIP_TRY(hipMemsetAsync(d->u64, 0, sizeof(unsigned long long), s));
+        SM_TRY(launch_count(*d, make_view(t, n), m, reinterpret_cast<const uint64_t *>(u.dev), tu, d->u64, nullptr,
+                            nullptr, s));
+        HIP_TRY(hipMemcpyAsync(d->hpin, d->u64, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+        return SM_OK;
+    };
+    const int rc = enqueue();
+    const std::string msg = g_err;
+    SM_TRY(ring_commit(*d, u, s));  // also after an error: the upload may still be in flight
+    if (rc < 0)
+        return fail(rc, msg);
     HIP_TRY(hipStreamSynchronize(s));
     return (int64_t)d->hpin[0];
 }
@@ -1616,9 +1624,11 @@ int32_t sm_count_async(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t 
     const Tune tu = resolve(params, m, n);
     Upload u;
     SM_TRY(upload_steps(*d, p, m, order, s, &u));
-    SM_TRY(launch_count(*d, make_view(t, n), m, reinterpret_cast<const uint64_t *>(u.dev), tu,
-                        reinterpret_cast<unsigned long long *>(count_dev), nullptr, nullptr, s));
-    return ring_commit(*d, u, s);
+    const int rc = launch_count(*d, make_view(t, n), m, reinterpret_cast<const uint64_t *>(u.dev), tu,
+                                reinterpret_cast<unsigned long long *>(count_dev), nullptr, nullptr, s);
+    const std::string msg = g_err;
+    const int rc2 = ring_commit(*d, u, s);  // also after an error: the upload may still be in flight
+    return rc < 0 ? fail(rc, msg) : rc2;
 }
 
 int64_t sm_report(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n, const int32_t *order,
