@@ -161,6 +161,28 @@ def test_unary_closed_forms(dev, n):
             assert sm.count(td, b"a" * (k - 1) + b"b", order=order) == 0
 
 
+@pytest.mark.parametrize("tile_kib", [4, 8, 16])
+def test_unary_tile_and_vector_edges(dev, tile_kib):
+    """On a^n every start of p = a^k matches, so a start masked wrongly at a tile or vector edge
+    changes the count: the last valid start is placed just before, on and after vector and tile
+    boundaries (coordinates from the 16-byte-aligned base), for misaligned text pointers."""
+    T = tile_kib * 1024
+    for offset in (0, 1, 15):
+        first = offset % 16
+        for last in (0, 1, 15, 1022, 1023, 1024, 1025, T - 2, T - 1, T, T + 1, 2 * T + 1023, 3 * T - 1):
+            if last < first:
+                continue
+            for k in (1, 2, 3, 17):
+                n = last - first + k
+                td = to_dev(np.full(n, ord("a"), dtype=np.uint8), dev, offset)
+                for peel in (1, 2, min(k, 8)):
+                    assert sm.count(td, b"a" * k, tile_kib=tile_kib, peel=peel) == n - k + 1, (offset, last, k, peel)
+                    assert sm.count(td, b"a" * (k - 1) + b"b", tile_kib=tile_kib, peel=peel) == 0
+                if k == 2:
+                    pos = sm.report(td, b"aa", tile_kib=tile_kib).cpu().numpy()
+                    assert pos.tolist() == list(range(n - 1)), (offset, last)
+
+
 @pytest.mark.parametrize("unit", [b"ab", b"abc", b"aab", b"GATTACA", b"abcabd"])
 def test_periodic_closed_forms(dev, unit):
     n = 123_457
