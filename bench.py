@@ -225,6 +225,7 @@ def run_zipf(args):
             "kernel": f"k_count_staged<{dom[0] // 4},{dom[1]},{stream}> ({dom[0]} KiB tiles, "
                       f"peel {dom[1]})",
             "avg_launch_us": round(avg_ms * 1e3, 2),
+            "median_launch_us": round(float(np.median(kern)) * 1e3, 2),
             "timed_launches": len(kern),
             "algorithmic_bytes_per_launch": n,
         },
