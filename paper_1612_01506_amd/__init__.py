@@ -306,7 +306,7 @@ def _marshal_batch(texts, queries, use_hist: bool):
         qarr["text_id"][:nq] = np.fromiter((q[0] for q in qs), dtype=np.int64, count=nq).astype(np.uint32)
         qarr["p"][:nq] = np.where(lens > 0, np.uint64(blob.ctypes.data) + offs, 0)
         qarr["m"][:nq] = lens
-        for i, q in enumerate(qs):
+        for i, q in (enumerate(qs) if max(map(len, qs)) > 2 else ()):   # queries with their own order
             if len(q) > 2 and q[2] is not None:
                 tid = int(q[0])
                 tx = texts[tid] if 0 <= tid < len(texts) else None
