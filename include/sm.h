@@ -108,9 +108,9 @@ int32_t sm_order(int32_t kind, const uint8_t *p, uint64_t m, const uint64_t *his
 
 /* Adjacent-pair counts, the statistics of the bigram-aware order below.
  * bigram_dev: device, 65536 x uint64, overwritten with [a * 256 + b] =
- * #{s : t[s] == a, t[s+1] == b}.  hist_host (optional, host 256 x uint64, the
- * text's histogram) lets the library skip the pass over first symbols that
- * do not occur (one pass per half of the byte range otherwise).
+ * #{s : t[s] == a, t[s+1] == b}, exactly, in two passes over t (one per
+ * half of the first symbol's byte range).  hist_host is accepted for
+ * compatibility and ignored: the table never depends on it.
  * Asynchronous on `stream`.  t: device, n bytes. */
 int32_t sm_bigram(const uint8_t *t, uint64_t n, const uint64_t *hist_host, uint64_t *bigram_dev, void *stream);
 
@@ -211,7 +211,10 @@ int32_t sm_patterns_report_async(const sm_patterns *ps, uint64_t i, const uint8_
 typedef struct sm_text {
     const uint8_t *t;      /* device, n bytes                                                  */
     uint64_t n;
-    const uint64_t *hist;  /* host 256 x uint64 symbol histogram, or NULL                      */
+    const uint64_t *hist;  /* host 256 x uint64 symbol frequencies, or NULL.  Any values are
+                              accepted -- the text's own histogram, one taken from another text
+                              of the same kind (Section 2.2), or an estimate: they choose the
+                              compare order, the peel and the kernel, never a count           */
 } sm_text;
 
 typedef struct sm_query {
@@ -224,7 +227,9 @@ typedef struct sm_query {
 } sm_query;
 
 /* Batched count: counts_dev[i] (device, nq x uint64) is overwritten with the
- * count of query i in its text, exactly as sm_count would return it.  All
+ * count of query i in its text, exactly as sm_count would return it, for any
+ * histogram values (an understated, stale or foreign histogram only costs
+ * speed).  All
  * queries run in one persistent launch that stages each text tile once and
  * runs every query of an m-bucket over it.  Validation is all-or-nothing
  * before anything is launched (the message names the first bad query).
@@ -253,9 +258,9 @@ int32_t sm_report_batch(const sm_query *q, uint64_t nq, const sm_text *texts, ui
  * lists) into one device buffer owned by the plan, synchronously on the null
  * stream.  The plan keeps the texts' device addresses and lengths, not their
  * contents: the texts must stay allocated, and may change contents between
- * runs.  For a text given with a histogram the plan keeps that histogram's
- * support (the symbols with a nonzero entry): its counts stay exact only while
- * the text's symbols stay within that support.  Host inputs (queries,
+ * runs, to any bytes: counts stay exact whatever symbols the texts hold then
+ * (the histograms given at creation only chose the compare orders, peels and
+ * kernels).  Host inputs (queries,
  * patterns, orders, histograms) are consumed before return.  nq = 0 gives a plan whose runs do nothing.  On error *out
  * is NULL.  The plan belongs to the device current at creation. */
 typedef struct sm_batch sm_batch;

@@ -129,7 +129,7 @@ def histogram(t, stream=None) -> torch.Tensor:
 
 def bigram(t, hist=None, stream=None) -> torch.Tensor:
     """Adjacent-pair counts: (256, 256) device int64 tensor, [a, b] = #{s : t[s] == a, t[s+1] == b}
-    (asynchronous).  hist (the text's host histogram), if given, lets empty passes be skipped."""
+    (asynchronous).  hist is accepted for compatibility and ignored: the table never depends on it."""
     ptr, n = _dev_text(t)
     dev = t.t.device if isinstance(t, Text) else t.device
     h = None if hist is None else np.ascontiguousarray(np.asarray(hist).astype(np.uint64))
@@ -242,7 +242,10 @@ _TEXT_DT = np.dtype([("t", "<u8"), ("n", "<u8"), ("hist", "<u8")])
 class PackedTexts:
     """Many texts stored back to back in one device uint8 buffer: text i is
     buf[offsets[i] : offsets[i] + lengths[i]].  hists (optional, host, shape
-    (ntexts, 256)) enables frequency orders and the bitmap mode."""
+    (ntexts, 256)) enables frequency orders and the bitmap mode.  They are
+    symbol frequencies of any provenance (each text's own, another text's of
+    the same kind, an estimate): they steer the compare order, the peel and
+    the kernel only, and counts stay exact whatever their values."""
 
     def __init__(self, buf: torch.Tensor, offsets, lengths, hists=None):
         _dev_text(buf)

@@ -1024,21 +1024,34 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
         if (texts[t].hist && q[i].m <= texts[t].n && q[i].m <= 4096)
             nbm[t]++;
     }
-    std::vector<std::vector<uint8_t>> smaps(nt);  // symbol -> bitmap slot, texts with enough queries only
+    // symbol -> bitmap slot, texts with enough queries only.  Slots go to the symbols the text's
+    // candidate queries use, whatever the histogram says: a text byte of any other symbol can never
+    // match, so it sets no bit, and a query symbol the text lacks keeps an all-zero bitmap.  The
+    // histogram therefore only steers the compare order and the mode, never a count.
+    std::vector<std::vector<uint8_t>> smaps(nt);
     std::vector<uint32_t> nslots(nt, 0);
-    for (uint64_t t = 0; t < nt; ++t) {
-        if (nbm[t] < kBmMinQueries)
+    for (uint64_t t = 0; t < nt; ++t)
+        if (nbm[t] >= kBmMinQueries)
+            smaps[t].assign(256, 0);
+    for (uint64_t i = 0; i < nq; ++i) {
+        const uint32_t t = q[i].text_id;
+        if (smaps[t].empty() || q[i].m > texts[t].n || q[i].m > 4096)
             continue;
-        smaps[t].assign(256, 0xFF);
+        uint8_t *seen = smaps[t].data();
+        for (uint64_t j = 0; j < q[i].m; ++j)
+            seen[q[i].p[j]] = 1;
+    }
+    for (uint64_t t = 0; t < nt; ++t) {
+        if (smaps[t].empty())
+            continue;
         for (int b = 0; b < 256; ++b)
-            if (texts[t].hist[b])
-                smaps[t][b] = (uint8_t)nslots[t]++;
+            smaps[t][b] = smaps[t][b] ? (uint8_t)nslots[t]++ : (uint8_t)0xFF;
         nbm[t] = 0;
     }
     // a text qualifies if enough of its queries fit the LDS next to their bucket's bitmaps
     for (uint64_t i = 0; i < nq; ++i) {
         const uint32_t t = q[i].text_id;
-        if (!smaps[t].empty() && q[i].m <= texts[t].n && q[i].m <= 4096 && nslots[t] > 0 &&
+        if (!smaps[t].empty() && q[i].m <= texts[t].n && q[i].m <= 4096 && nslots[t] > 0 && nslots[t] < 0xFF &&
             bm_lds(nslots[t], bm_wps(bm_bucket(q[i].m))) <= kBmMaxLds)
             nbm[t]++;
     }
@@ -1069,11 +1082,6 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
         if (q[i].m > n)
             continue;  // count stays 0
         if (text_bm[t] && q[i].m <= 4096 && bm_lds(nslots[t], bm_wps(bm_bucket(q[i].m))) <= kBmMaxLds) {
-            bool absent = false;
-            for (uint64_t j = 0; j < q[i].m && !absent; ++j)
-                absent = smaps[t][q[i].p[j]] == 0xFF;
-            if (absent)
-                continue;  // a symbol the text lacks: count 0
             bmq.push_back({i, t, q[i].m, bm_bucket(q[i].m)});
             total_bm_steps += q[i].m;
             continue;
@@ -1538,16 +1546,11 @@ int32_t sm_bigram(const uint8_t *t, uint64_t n, const uint64_t *hist_host, uint6
     const uint64_t nchunks = tv.end16 / 16;
     const unsigned grid =
         (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(nchunks, kBgWG), (uint64_t)std::max(d->cus, 1)));
-    for (uint32_t half = 0; half < 2; ++half) {
-        if (hist_host) {  // skip a half whose first symbols do not occur
-            uint64_t c = 0;
-            for (int b = 128 * (int)half; b < 128 * (int)half + 128; ++b)
-                c += hist_host[b];
-            if (c == 0)
-                continue;
-        }
+    // Both halves always run: a pass whose first symbols do not occur adds nothing, and skipping it
+    // on the strength of a caller's histogram would make the table depend on that histogram.
+    (void)hist_host;
+    for (uint32_t half = 0; half < 2; ++half)
         HIP_TRY(launch_bigram(tv, half, out, grid, s));
-    }
     return SM_OK;
 }
 
