@@ -206,6 +206,25 @@ int32_t sm_patterns_report_async(const sm_patterns *ps, uint64_t i, const uint8_
                                  const sm_params *params, uint64_t *pos_dev, uint64_t cap, uint64_t *total_dev,
                                  void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * report as sm_patterns_report_async -- the same kernels, the same positions
+ * in pos_dev and full count in total_dev -- with its scratch (per-vector
+ * counts, group sums and offsets) in a fixed array of the library's device
+ * code instead of library-allocated memory.  The call allocates and frees
+ * nothing and issues no host-device copy; it only launches kernels on
+ * `stream` (a fill kernel clears the scratch first).  Limit: n - m + 1 <=
+ * 1,074,790,385 starts (a 1 GiB text with any pattern); longer texts give
+ * SM_EINVAL.  Each device holds its own 4 MiB copy of the array until the
+ * process ends.  All calls on one device share that array: calls that
+ * overlap on one device (different streams, or threads without ordering)
+ * race and give wrong results; calls on one stream are ordered.  The pattern
+ * set's creation must have initialised the device (SM_EINVAL after
+ * sm_shutdown).  Errors as sm_patterns_report_async. */
+int32_t sm_patterns_report_noalloc(const sm_patterns *ps, uint64_t i, const uint8_t *t, uint64_t n,
+                                   const sm_params *params, uint64_t *pos_dev, uint64_t cap, uint64_t *total_dev,
+                                   void *stream);
+
 /* -------------------------------------------------------------- batches */
 
 typedef struct sm_text {

@@ -482,3 +482,12 @@ class Patterns:
         ptr, n = _dev_text(t)
         check(load().sm_patterns_report_async(self._h, i, ptr, n, _params(peel, tile_kib, wgs_per_cu, t, self.m[i]),
                                               out.data_ptr(), out.numel(), total.data_ptr(), _stream(stream)))
+
+    def report_noalloc(self, i: int, t, out: torch.Tensor, total: torch.Tensor, peel=None, tile_kib=None,
+                       wgs_per_cu=None, stream=None) -> None:
+        """As report_async, with the library's fixed device scratch: allocates nothing (usable under
+        graph capture).  Texts up to 1 GiB; calls overlapping on one device race."""
+        ptr, n = _dev_text(t)
+        check(load().sm_patterns_report_noalloc(self._h, i, ptr, n,
+                                                _params(peel, tile_kib, wgs_per_cu, t, self.m[i]),
+                                                out.data_ptr(), out.numel(), total.data_ptr(), _stream(stream)))

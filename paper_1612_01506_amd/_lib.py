@@ -22,7 +22,7 @@ EXPORTS = (
     "sm_patterns_create", "sm_patterns_destroy", "sm_patterns_count", "sm_patterns_report",
     "sm_report_async", "sm_patterns_report_async", "sm_patterns_create_ordered",
     "sm_batch_create", "sm_batch_run", "sm_batch_destroy", "sm_bigram", "sm_order_bigram",
-    "sm_report_batch",
+    "sm_report_batch", "sm_patterns_report_noalloc",
 )
 
 
@@ -85,6 +85,7 @@ def load() -> ctypes.CDLL:
         "sm_patterns_report": ([vp, u64, vp, u64, P(sm_params), vp, u64, vp], i64),
         "sm_report_async": ([vp, u64, vp, u64, vp, P(sm_params), vp, u64, vp, vp], i32),
         "sm_patterns_report_async": ([vp, u64, vp, u64, P(sm_params), vp, u64, vp, vp], i32),
+        "sm_patterns_report_noalloc": ([vp, u64, vp, u64, P(sm_params), vp, u64, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)

@@ -88,7 +88,24 @@ struct Dev {
     hipEvent_t rb_ev = nullptr;  // recorded after each reporting batch's last kernel
     hipStream_t rb_stream = nullptr;  // ... on this stream
     bool rb_pending = false;
+    // device address of this device's copy of `scratch` (the allocation-free report), or null if
+    // the lookup failed at initialisation (that entry point then fails; the others are unaffected)
+    uint8_t *na_scratch = nullptr;
 };
+
+// Scratch of the allocation-free report (sm_patterns_report_noalloc): the
+// per-vector counts (uint32, one per 1024-start vector) of texts up to 1 GiB
+// plus the group sums and offsets (uint64, one each per 1024 vectors).  Every
+// device holds its own copy until the process ends.  Host code never uses the
+// name itself as an address: it takes the device address from
+// hipGetSymbolAddress once per device (get_dev) and passes that on.
+constexpr uint64_t kNaMaxBlocks = (1ull << 20) + kGroupBlocks;  // 1 GiB text at any alignment, any m
+constexpr uint64_t kNaMaxGroups = kNaMaxBlocks / kGroupBlocks;
+constexpr uint64_t kNaMaxStarts = kNaMaxBlocks * kBlock - 15;
+constexpr size_t kNaBcBytes = kNaMaxBlocks * sizeof(uint32_t);
+constexpr size_t kNaBytes = kNaBcBytes + 2 * kNaMaxGroups * sizeof(unsigned long long);
+static_assert(kNaBcBytes % 256 == 0, "group sums start 256-byte aligned");
+__device__ __align__(256) uint8_t scratch[kNaBytes];
 
 constexpr int kMaxDev = 64;
 Dev *g_devs[kMaxDev];
@@ -123,6 +140,13 @@ int get_dev(Dev **out)
                               hipHostMallocDefault);
         if (e == hipSuccess)
             e = prime_kernel_attrs();
+        if (e == hipSuccess) {  // this device's copy of the allocation-free report's scratch
+            void *na = nullptr;
+            if (hipGetSymbolAddress(&na, HIP_SYMBOL(scratch)) == hipSuccess)
+                d->na_scratch = static_cast<uint8_t *>(na);
+            else
+                (void)hipGetLastError();  // only sm_patterns_report_noalloc depends on it
+        }
         if (e != hipSuccess) {
             if (d->rh) (void)hipHostFree(d->rh);
             if (d->rd) (void)hipFree(d->rd);
@@ -571,6 +595,15 @@ int upload_steps(Dev &d, const uint8_t *p, uint64_t m, const int32_t *order, hip
     return ring_copy(*u, bytes, s);
 }
 
+// The state of an already initialised device, or null.
+Dev *find_dev(int id)
+{
+    if (id < 0 || id >= kMaxDev)
+        return nullptr;
+    std::lock_guard<std::mutex> lk(g_devs_mu);
+    return g_devs[id];
+}
+
 int ensure_report_scratch(Dev &d, uint64_t nblocks, uint64_t ngroups)
 {
     if ((d.bc_cap < nblocks || d.g_cap < ngroups) && d.rep_pending)
@@ -672,8 +705,9 @@ int report_count_pass(Dev &d, const TextView &tv, uint64_t m, const uint64_t *st
     return SM_OK;
 }
 
-int report_write_pass(Dev &d, const TextView &tv, uint64_t m, const uint64_t *steps_dev, const Tune &tu,
-                      uint64_t *pos, uint64_t cap, hipStream_t s)
+// The ordered write of a report whose count pass filled bc and gs and whose scan filled go.
+int launch_write(Dev &d, const TextView &tv, uint64_t m, const uint64_t *steps_dev, const Tune &tu, uint32_t *bc,
+                 unsigned long long *gs, const unsigned long long *go, uint64_t *pos, uint64_t cap, hipStream_t s)
 {
     const uint64_t last = tv.first + tv.n - m;
     const uint64_t nblocks = ceil_div(last + 1, kBlock);
@@ -689,8 +723,15 @@ int report_write_pass(Dev &d, const TextView &tv, uint64_t m, const uint64_t *st
     uint64_t win = kBlock + halo_for(m);
     if (kWaves * win + kGroupBlocks * sizeof(uint32_t) + 64 > kMaxLds)
         win = 0;  // long pattern: read the text from global memory
-    HIP_TRY(launch_report_write(a, d.bc, d.gs, d.go, ngroups,
-                                reinterpret_cast<unsigned long long *>(pos), cap, (uint32_t)win, ggrid, s));
+    HIP_TRY(launch_report_write(a, bc, gs, go, ngroups, reinterpret_cast<unsigned long long *>(pos), cap,
+                                (uint32_t)win, ggrid, s));
+    return SM_OK;
+}
+
+int report_write_pass(Dev &d, const TextView &tv, uint64_t m, const uint64_t *steps_dev, const Tune &tu,
+                      uint64_t *pos, uint64_t cap, hipStream_t s)
+{
+    SM_TRY(launch_write(d, tv, m, steps_dev, tu, d.bc, d.gs, d.go, pos, cap, s));
     HIP_TRY(hipEventRecord(d.rep_ev, s));
     d.rep_stream = s;
     d.rep_pending = true;
@@ -703,6 +744,31 @@ int report_core(Dev &d, const TextView &tv, uint64_t m, const uint64_t *steps_de
 {
     SM_TRY(report_count_pass(d, tv, m, steps_dev, tu, total_dev, s));
     return report_write_pass(d, tv, m, steps_dev, tu, pos, cap, s);
+}
+
+// report_core on the device's static scratch: the same kernels, no allocation,
+// no event, no host-device copy.  The used part of the per-vector counts and
+// group sums is cleared first by a fill kernel, since the array keeps whatever
+// the previous call on this device left in it.
+int report_core_noalloc(Dev &d, const TextView &tv, uint64_t m, const uint64_t *steps_dev, const Tune &tu,
+                        uint64_t *pos, uint64_t cap, unsigned long long *total_dev, hipStream_t s)
+{
+    // at most kNaMaxStarts starts, whatever the text's alignment (tv.first <= 15)
+    if (tv.n - m + 1 > kNaMaxStarts)
+        return fail(SM_EINVAL, "text too long for the allocation-free report: n - m + 1 = " +
+                                   std::to_string(tv.n - m + 1) + " starts, at most " +
+                                   std::to_string(kNaMaxStarts) + " are supported");
+    const uint64_t nblocks = ceil_div(tv.first + tv.n - m + 1, kBlock);
+    const uint64_t ngroups = ceil_div(nblocks, kGroupBlocks);
+    if (!d.na_scratch)
+        return fail(SM_EDEVICE, "the allocation-free report's scratch has no device address on this device");
+    uint32_t *bc = reinterpret_cast<uint32_t *>(d.na_scratch);
+    unsigned long long *gs = reinterpret_cast<unsigned long long *>(d.na_scratch + kNaBcBytes);
+    unsigned long long *go = gs + kNaMaxGroups;
+    HIP_TRY(launch_fill_report(bc, nblocks, gs, ngroups, s));
+    SM_TRY(launch_count(d, tv, m, steps_dev, tu, nullptr, bc, gs, s));
+    HIP_TRY(launch_scan_groups(gs, ngroups, go, total_dev, s));
+    return launch_write(d, tv, m, steps_dev, tu, bc, gs, go, pos, cap, s);
 }
 
 // Non-overlapping mode (greedy leftmost disjoint occurrences, see the
@@ -1819,6 +1885,35 @@ int32_t sm_patterns_report_async(const sm_patterns *ps, uint64_t i, const uint8_
     std::lock_guard<std::mutex> lk(d->mu);
     const Tune tu = resolve(params, m, n);
     return report_core(*d, make_view(t, n), m, ps->steps + ps->off[i], tu, cap ? pos_dev : nullptr, cap, tot, s);
+}
+
+int32_t sm_patterns_report_noalloc(const sm_patterns *ps, uint64_t i, const uint8_t *t, uint64_t n,
+                                   const sm_params *params, uint64_t *pos_dev, uint64_t cap, uint64_t *total_dev,
+                                   void *stream)
+{
+    g_err.clear();
+    SM_TRY(check_set(ps, i));
+    SM_TRY(check_text(t, n));
+    SM_TRY(check_flags(params, false));
+    if (cap > 0 && !pos_dev)
+        return fail(SM_EINVAL, "pos is NULL with cap > 0");
+    if (!total_dev)
+        return fail(SM_EINVAL, "total_dev is NULL");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    unsigned long long *tot = reinterpret_cast<unsigned long long *>(total_dev);
+    const uint64_t m = ps->m[i];
+    if (m > n) {
+        HIP_TRY(launch_fill_u64(tot, 1, 0ull, s));
+        return SM_OK;
+    }
+    // the pattern set's creation initialised this device; never initialise (allocate) here
+    Dev *d = find_dev(ps->dev);
+    if (!d)
+        return fail(SM_EINVAL, "the pattern set's device is not initialised (was sm_shutdown called?)");
+    std::lock_guard<std::mutex> lk(d->mu);
+    const Tune tu = resolve(params, m, n);
+    return report_core_noalloc(*d, make_view(t, n), m, ps->steps + ps->off[i], tu, cap ? pos_dev : nullptr, cap,
+                               tot, s);
 }
 
 int32_t sm_count_batch(const sm_query *q, uint64_t nq, const sm_text *texts, uint64_t nt,
