@@ -928,6 +928,8 @@ constexpr uint64_t kRepScratchMax = 8ull << 30;
 
 // A text runs in bitmap mode when it has a histogram and at least this many queries.
 constexpr uint64_t kBmMinQueries = 32;
+// ... and when a work item's LDS holds its bitmaps and the records of at least this many queries.
+constexpr uint64_t kBmMinCap = 128;
 
 }  // namespace
 
@@ -969,7 +971,7 @@ struct LaunchPlan {
     uint64_t nq = 0;
     // bitmap launch
     uint64_t n_bitems = 0;
-    uint32_t bm_words = 0;
+    uint32_t bm_lds = 0;  // dynamic LDS bytes: the largest item's bitmaps, symbol map, records and counters
     uint64_t bm_grid = 0;
     bool bm_two = false;  // two workgroups per CU fit the bitmaps' LDS
     // byte-tile launch
@@ -1080,8 +1082,10 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
 
     // ---- per-text alphabets (bitmap mode needs the histogram and kBmMinQueries queries)
     auto bm_wps = [](uint64_t m_max) { return (uint32_t)round_up(kBmT / 32 + 2 + ceil_div(m_max, 32), 4); };
-    auto bm_lds = [&](uint32_t slots, uint32_t wps) {
-        return (uint64_t)slots * wps * 4 + 256 + kBmQChunk * sizeof(uint32_t);
+    // queries per bitmap work item that fit the LDS beside the bitmaps of `slots` symbols
+    auto bm_cap = [](uint32_t slots, uint32_t wps) -> uint64_t {
+        const uint64_t fixed = bm_item_lds(slots, wps, 0);
+        return fixed >= kBmMaxLds ? 0 : std::min<uint64_t>(kBmQChunk, (kBmMaxLds - fixed) / kBmPerQueryLds);
     };
     auto bm_bucket = [](uint64_t m) -> uint32_t { return m <= 256 ? 256 : (m <= 1024 ? 1024 : 4096); };
     std::vector<uint64_t> nbm(nt, 0);
@@ -1118,7 +1122,7 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
     for (uint64_t i = 0; i < nq; ++i) {
         const uint32_t t = q[i].text_id;
         if (!smaps[t].empty() && q[i].m <= texts[t].n && q[i].m <= 4096 && nslots[t] > 0 && nslots[t] < 0xFF &&
-            bm_lds(nslots[t], bm_wps(bm_bucket(q[i].m))) <= kBmMaxLds)
+            bm_cap(nslots[t], bm_wps(bm_bucket(q[i].m))) >= kBmMinCap)
             nbm[t]++;
     }
     std::vector<uint8_t> text_bm(nt, 0);
@@ -1135,7 +1139,7 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
     for (uint64_t i = 0; i < nq; ++i) {
         const uint32_t t = q[i].text_id;
         if (q[i].m <= texts[t].n &&
-            !(text_bm[t] && q[i].m <= 4096 && bm_lds(nslots[t], bm_wps(bm_bucket(q[i].m))) <= kBmMaxLds))
+            !(text_bm[t] && q[i].m <= 4096 && bm_cap(nslots[t], bm_wps(bm_bucket(q[i].m))) >= kBmMinCap))
             nstaged[t]++;
     }
 
@@ -1147,7 +1151,7 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
         const uint64_t n = texts[t].n;
         if (q[i].m > n)
             continue;  // count stays 0
-        if (text_bm[t] && q[i].m <= 4096 && bm_lds(nslots[t], bm_wps(bm_bucket(q[i].m))) <= kBmMaxLds) {
+        if (text_bm[t] && q[i].m <= 4096 && bm_cap(nslots[t], bm_wps(bm_bucket(q[i].m))) >= kBmMinCap) {
             bmq.push_back({i, t, q[i].m, bm_bucket(q[i].m)});
             total_bm_steps += q[i].m;
             continue;
@@ -1180,11 +1184,12 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
         uint32_t q0, q1;
         uint64_t m_min, m_max;
     };
-    auto make_chunks = [](const std::vector<PlanQuery> &v, uint32_t cap) {
+    auto make_chunks = [](const std::vector<PlanQuery> &v, const std::function<uint32_t(const PlanQuery &)> &cap_of) {
         std::vector<Chunk> out;
         for (uint32_t i = 0; i < v.size();) {
             uint32_t j = i;
             uint64_t mn = v[i].m, mx = v[i].m;
+            const uint32_t cap = cap_of(v[i]);
             while (j < v.size() && j - i < cap && v[j].text == v[i].text && v[j].bucket == v[i].bucket) {
                 mn = std::min(mn, v[j].m);
                 mx = std::max(mx, v[j].m);
@@ -1195,8 +1200,10 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
         }
         return out;
     };
-    const std::vector<Chunk> chunks = make_chunks(staged, kQChunk);
-    const std::vector<Chunk> bchunks = make_chunks(bmq, kBmQChunk);
+    const std::vector<Chunk> chunks = make_chunks(staged, [](const PlanQuery &) { return kQChunk; });
+    const std::vector<Chunk> bchunks = make_chunks(bmq, [&](const PlanQuery &pq) {
+        return (uint32_t)bm_cap(nslots[pq.text], bm_wps(pq.bucket));
+    });
 
     // ---- byte-tile chunks in one global tile space
     std::vector<BatchChunk> bchunks_t;
@@ -1228,18 +1235,20 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
     }
     const uint64_t bspan = std::max<uint64_t>(1, bm_work / (bm_grid_target * 4));
     std::vector<BmItem> bitems;
-    uint32_t bm_words = 0;
+    uint64_t bm_lds_max = 0;
     for (auto &c : bchunks) {
         const sm_text &tx = texts[c.text];
         const TextView tv = make_view(tx.t, tx.n);
         const uint64_t ntiles = ceil_div(tv.first + tx.n - c.m_min + 1, kBmT);
+        // at most the bucket's bitmap width, which the chunk's capacity was computed for
         const uint32_t wps = bm_wps(c.m_max);
-        bm_words = std::max(bm_words, nslots[c.text] * wps);
+        bm_lds_max = std::max(bm_lds_max, bm_item_lds(nslots[c.text], wps, c.q1 - c.q0));
         for (uint64_t t0 = 0; t0 < ntiles; t0 += bspan) {
             BmItem it{};
             it.tv = tv;
             it.tile_begin = t0;
             it.tile_end = std::min(ntiles, t0 + bspan);
+            it.last_min = tv.first + tx.n - c.m_max;
             it.q_begin = c.q0;
             it.q_end = c.q1;
             it.wps = wps;
@@ -1257,7 +1266,7 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
     const size_t o_steps = o_queries + round_up(std::max<size_t>(staged.size(), 1) * sizeof(BatchQuery), 256);
     const size_t o_bitems = o_steps + round_up(total_steps * sizeof(uint64_t), 256);
     const size_t o_bq = o_bitems + round_up(bitems.size() * sizeof(BmItem), 256);
-    const size_t o_bout = o_bq + round_up(bmq.size() * sizeof(BmQuery), 256);
+    const size_t o_bout = o_bq + round_up(bmq.size() * kBmRecWords * sizeof(uint32_t), 256);
     const size_t o_smap = o_bout + round_up(bmq.size() * sizeof(uint32_t), 256);
     const size_t o_bsteps = o_smap + round_up((uint64_t)n_smaps * 256, 256);
     if (total_bm_steps >= (1ull << 32))
@@ -1273,7 +1282,7 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
     BatchReport *hrep = rep ? reinterpret_cast<BatchReport *>(uhost + o_reports) : nullptr;
     uint64_t *hs = reinterpret_cast<uint64_t *>(uhost + o_steps);
     BmItem *hbi = reinterpret_cast<BmItem *>(uhost + o_bitems);
-    BmQuery *hbq = reinterpret_cast<BmQuery *>(uhost + o_bq);
+    uint32_t *hbq = reinterpret_cast<uint32_t *>(uhost + o_bq);
     uint32_t *hbout = reinterpret_cast<uint32_t *>(uhost + o_bout);
     uint8_t *hsm = uhost + o_smap;
     uint32_t *hbs = reinterpret_cast<uint32_t *>(uhost + o_bsteps);
@@ -1317,7 +1326,7 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
         }
         for (auto &c : bchunks)
             for (uint32_t i = c.q0; i < c.q1; ++i)
-                bm_wps_of[i] = bm_wps(c.m_max);
+                bm_wps_of[i] = bm_wps(c.m_max);  // as the chunk's items
     }
     std::vector<uint32_t> long_peel(n_lg);
 
@@ -1382,14 +1391,14 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
         for (uint64_t l = 0; l < Q.m; ++l) {
             const uint32_t j = (uint32_t)o[l];
             const uint32_t slot = smaps[pq.text][Q.p[j]];
-            e[l] = ((slot * wps + (j >> 5)) << 5) | (j & 31u);
+            e[l] = ((slot * wps + (j >> 5)) << 7) | (j & 31u);
         }
-        BmQuery bq{};
-        bq.e0 = e[0];
-        bq.e1 = Q.m > 1 ? e[1] : e[0];
-        bq.steps_off = (uint32_t)bm_off[i];
-        bq.mr = (uint32_t)pq.m | (peel_of(pq.idx, o, (double)kBmT) << 24);
-        hbq[i] = bq;
+        // record: m | r << 24, the step table's index, its first entries (past m: entry m - 1)
+        uint32_t *rq = hbq + (size_t)i * kBmRecWords;
+        rq[0] = (uint32_t)pq.m | (peel_of(pq.idx, o, (double)kBmT) << 24);
+        rq[1] = (uint32_t)bm_off[i];
+        for (uint32_t l = 0; l < kBmRecSteps; ++l)
+            rq[2 + l] = e[std::min<uint64_t>(l, Q.m - 1)];
         hbout[i] = (uint32_t)pq.idx;
     };
     const bool planned = parallel_for(n_st + n_lg + n_bm, [&](size_t k0, size_t k1) {
@@ -1423,10 +1432,9 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
     lp->o_bsteps = o_bsteps;
     lp->o_reports = rep ? o_reports : 0;
     lp->n_bitems = bitems.size();
-    lp->bm_words = (uint32_t)round_up(bm_words, 4);
+    lp->bm_lds = (uint32_t)bm_lds_max;
     {
-        const uint32_t lds = lp->bm_words * 4 + 256 + kBmQChunk * sizeof(uint32_t);
-        const uint64_t per_cu = std::max<uint64_t>(1, kBmMaxLds / lds);
+        const uint64_t per_cu = std::max<uint64_t>(1, kBmMaxLds / std::max<uint64_t>(bm_lds_max, 1));
         lp->bm_two = per_cu >= 2;
         lp->bm_grid = std::min<uint64_t>(bitems.size(), (uint64_t)std::max(d.cus, 1) * std::min<uint64_t>(per_cu, 2));
     }
@@ -1463,13 +1471,11 @@ int launch_plan(Dev &d, const LaunchPlan &lp, const uint8_t *dev, unsigned long 
         BmArgs a{};
         a.items = reinterpret_cast<const BmItem *>(dev + lp.o_bitems);
         a.nitems = lp.n_bitems;
-        a.queries = reinterpret_cast<const BmQuery *>(dev + lp.o_bq);
+        a.recs = reinterpret_cast<const uint32_t *>(dev + lp.o_bq);
         a.outs = reinterpret_cast<const uint32_t *>(dev + lp.o_bout);
         a.steps = reinterpret_cast<const uint32_t *>(dev + lp.o_bsteps);
         a.counts = counts;
-        a.bm_words = lp.bm_words;
-        const uint32_t lds = a.bm_words * 4 + 256 + kBmQChunk * sizeof(uint32_t);
-        HIP_TRY(launch_batch_bitmap(a, (unsigned)lp.bm_grid, lds, lp.bm_two, s));
+        HIP_TRY(launch_batch_bitmap(a, (unsigned)lp.bm_grid, lp.bm_lds, lp.bm_two, s));
     }
     if (lp.ntiles) {
         BatchArgs a{};

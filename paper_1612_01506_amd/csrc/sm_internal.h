@@ -103,43 +103,52 @@ struct BatchArgs {
     uint32_t chunk_log2;         // tiles are dealt in chunks of 2^chunk_log2
 };
 
-// Batched bitmap mode: per tile, one bitmap per symbol of the text's alphabet
-// (bit i of word w of slot c: the byte at tile position 32w + i is the
+// Batched bitmap mode: per tile, one bitmap per symbol the chunk's queries
+// use (bit i of word w of slot c: the byte at tile position 32w + i is the
 // symbol of slot c), then every query of a chunk runs over the tile with one
 // funnel shift + AND per compare.
 constexpr uint32_t kBmWG = 1024;             // threads per bitmap workgroup: 16 waves
 constexpr uint32_t kBmWaves = kBmWG / 64;
 constexpr uint32_t kBmT = 8192;              // starts per bitmap tile: kBmV vectors of 64 lanes x 32 bits
 constexpr int kBmV = (int)(kBmT / 2048);
-constexpr uint32_t kBmQChunk = 1024;         // queries per bitmap work item
+constexpr uint32_t kBmQChunk = 1024;         // largest number of queries per bitmap work item
 constexpr uint32_t kBmMaxLds = 163840;       // LDS per workgroup on gfx950
+// Per query, a record of kBmRecWords dwords: [0] m | r << 24, [1] index of its full step table
+// in the step pool, [2 .. 2 + kBmRecSteps) its first step entries (entries past m repeat entry m-1).
+constexpr uint32_t kBmRecWords = 8;
+constexpr uint32_t kBmRecSteps = kBmRecWords - 2;
+// LDS bytes of a work item besides its bitmaps: the symbol map plus, per query, the record and a counter
+constexpr uint32_t kBmSmapBytes = 256 * 4;
+constexpr uint32_t kBmPerQueryLds = kBmRecWords * 4 + 4;
 
 struct BmItem {
     TextView tv;
     uint64_t tile_begin, tile_end;  // tiles of kBmT starts
-    uint32_t q_begin, q_end;        // into the BmQuery array, at most kBmQChunk
+    uint64_t last_min;              // coordinate of the last valid start of the chunk's longest query
+    uint32_t q_begin, q_end;        // into the query records
     uint32_t wps;                   // bitmap words per slot (multiple of 4) >= kBmT / 32 + 2 + ceil(m_max / 32)
-    uint32_t nslots;                // slots of the text's alphabet
-    const uint8_t *smap;            // 256 bytes: symbol -> slot, 0xFF if the symbol is absent
+    uint32_t nslots;                // bitmap slots (symbols the chunk's text's queries use)
+    const uint8_t *smap;            // 256 bytes: symbol -> slot, 0xFF if no query uses the symbol
 };
 
-// Bitmap step entry (uint32): ((slot * wps + (j >> 5)) << 5) | (j & 31), j = pi(l).
-struct BmQuery {
-    uint32_t e0, e1;     // the first two step entries (e1 = e0 when m == 1)
-    uint32_t steps_off;  // index of the query's full step table in the bitmap step pool
-    uint32_t mr;         // m | r << 24 (m <= 4096, peel r in 1..min(8, m))
-};
+// Bitmap step entry (uint32), for compare l of a query with j = pi(l):
+//   ((slot * wps + (j >> 5)) << 7) | (j & 31)
+// i.e. the LDS byte offset of the slot's word holding bit j, shifted left by 5, and j mod 32.
 
 struct BmArgs {
     const BmItem *items;
     uint64_t nitems;
-    const BmQuery *queries;
-    const uint32_t *outs;  // output slot of each query
-    const uint32_t *steps;
+    const uint32_t *recs;   // kBmRecWords per query
+    const uint32_t *outs;   // output slot of each query
+    const uint32_t *steps;  // full step tables
     unsigned long long *counts;
-    uint32_t bm_words;  // LDS words reserved for bitmaps (max nslots * wps over the items)
-    uint32_t pad;
 };
+
+// LDS bytes a bitmap work item needs: bitmaps, symbol map, records, counters and the group counter.
+inline uint64_t bm_item_lds(uint32_t nslots, uint32_t wps, uint32_t nq)
+{
+    return (uint64_t)nslots * wps * 4 + kBmSmapBytes + (uint64_t)nq * kBmPerQueryLds + 16;
+}
 
 // Host-side launchers (sm_kernels.hip).  Each returns a hipError_t.
 // stream_loads: tile loads with the non-temporal cache policy (texts far larger than the last-level cache)

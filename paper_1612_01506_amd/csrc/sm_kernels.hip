@@ -1214,32 +1214,20 @@ __global__ __launch_bounds__(kWG) void k_no_compact(const unsigned long long *po
 
 // ----------------------------------------------------- batch bitmap kernel
 
-// Valid-start bits of the 32 starts p0 .. p0 + 31: first <= p <= last.
-__device__ __forceinline__ uint32_t valid_bits(uint64_t p0, uint64_t first, uint64_t last)
-{
-    if (p0 >= first && p0 + 31u <= last)
-        return 0xFFFFFFFFu;
-    const int64_t lo = (int64_t)first - (int64_t)p0, hi = (int64_t)last - (int64_t)p0 + 1;
-    const uint32_t a = (uint32_t)min(max(lo, (int64_t)0), (int64_t)32);
-    const uint32_t b = (uint32_t)min(max(hi, (int64_t)0), (int64_t)32);
-    if (a >= b)
-        return 0u;
-    const uint32_t upto_b = b >= 32u ? 0xFFFFFFFFu : (1u << b) - 1u;
-    const uint32_t below_a = a >= 32u ? 0xFFFFFFFFu : (1u << a) - 1u;
-    return upto_b & ~below_a;
-}
-
 // One compare on the bitmaps for the kBmV 2048-start vectors of the tile:
-// bits of the window at offset j are a funnel shift of two bitmap words.
-__device__ __forceinline__ void bm_step(const uint32_t *bm, uint32_t e, uint32_t lane, uint32_t (&f)[kBmV])
+// bits of the window at offset j are a funnel shift of two bitmap words.  e is
+// a bitmap step entry: e >> 5 is the LDS byte offset of the slot word holding
+// bit j, and alignbit uses only the low five bits of its shift operand, which
+// are j mod 32.  lane4 = 4 * lane.
+__device__ __forceinline__ void bm_step(const uint8_t *bmb, uint32_t e, uint32_t lane4, uint32_t (&f)[kBmV])
 {
-    const uint32_t base = (e >> 5) + lane, sh = e & 31u;
+    const uint32_t *w = reinterpret_cast<const uint32_t *>(bmb + (e >> 5) + lane4);
 #pragma unroll
     for (int v = 0; v < kBmV; ++v)
-        f[v] &= __builtin_amdgcn_alignbit(bm[base + 64u * v + 1u], bm[base + 64u * v], sh);
+        f[v] &= __builtin_amdgcn_alignbit(w[64 * v + 1], w[64 * v], e);
 }
 
-// Wave-uniform: any start of the tile still alive?  And how many.
+// Wave-uniform: any start of the tile still alive?
 __device__ __forceinline__ bool bm_any(const uint32_t (&f)[kBmV])
 {
     uint32_t o = 0;
@@ -1258,110 +1246,179 @@ __device__ __forceinline__ uint32_t bm_popc(const uint32_t (&f)[kBmV])
     return c;
 }
 
+// Bits of the 32 tile offsets o .. o + 31 that lie in [a, b) (tile offsets, all below 2^31).
+__device__ __forceinline__ uint32_t range_bits(uint32_t o, uint32_t a, uint32_t b)
+{
+    const uint32_t lo = a > o ? min(a - o, 32u) : 0u, hi = b > o ? min(b - o, 32u) : 0u;
+    if (lo >= hi)
+        return 0u;
+    return (hi >= 32u ? 0xFFFFFFFFu : (1u << hi) - 1u) & ~((1u << lo) - 1u);
+}
+
+// Coordinate c as a tile offset from ts, clamped to [0, 2^20].
+__device__ __forceinline__ uint32_t tile_off(uint64_t c, uint64_t ts)
+{
+    return c > ts ? (uint32_t)min(c - ts, (uint64_t)1 << 20) : 0u;
+}
+
+__device__ __forceinline__ uint32_t readlane(uint32_t v, uint32_t l)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)l);
+}
+
 // Persistent batched count over bitmap tiles.  Work item = (text, tile range,
-// chunk of <= kBmQChunk queries).  Per tile: zero the bitmaps, set one bit per
-// text byte (LDS atomic OR), then wave w runs queries w, w + 16, ... over the
-// kBmT starts of the tile: the first r compares unconditionally, then one zero
-// test (a wave-wide ballot) after each further compare (Algorithm 4).  A wave
-// takes its queries in pairs and issues the two peels' compares side by side,
-// so the LDS reads of both are in flight together.  Each query's count for the
-// item gathers in an LDS counter owned by one wave.
+// chunk of queries).  The item's query records go to LDS once.  Per tile:
+// zero the bitmaps, set one bit per text byte of a symbol some query uses (LDS
+// atomic OR; the bytes were loaded into registers while the previous tile was
+// searched), then each wave runs groups of K queries over the kBmT starts of
+// the tile: the first min(r) compares of the K queries in lock step, so that
+// the LDS reads of all K are in flight together, then per query its remaining
+// peeled compares and one zero test (a wave-wide ballot) after each further
+// compare (Algorithm 4).  A group's records are read from LDS by K * 8 lanes
+// and their fields taken with readlane, so the loop issues no scalar memory
+// loads, whose out-of-order returns would make every LDS wait a full one (only
+// compares past the record's first entries read the step pool).  Each query's
+// count for the item gathers in an LDS counter owned by one wave.
+template <int K>
 __device__ __forceinline__ void batch_bitmap(const BmArgs &a)
 {
-    extern __shared__ __align__(16) uint32_t bm[];
-    uint8_t *smap = reinterpret_cast<uint8_t *>(bm + a.bm_words);
-    uint32_t *qc = reinterpret_cast<uint32_t *>(smap + 256);
-    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = wave_id();
+    static_assert(K * kBmRecWords <= 64, "a group's records fit one wave");
+    extern __shared__ __align__(16) uint32_t bmlds[];
+    uint32_t *lds = bmlds;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = wave_id(), lane4 = 4u * lane;
+    const uint8_t *bmb = reinterpret_cast<const uint8_t *>(lds);
     for (uint64_t it = blockIdx.x; it < a.nitems; it += gridDim.x) {
         const BmItem I = ldc(&a.items[it]);
-        const uint32_t nq = I.q_end - I.q_begin, wps = I.wps, nw4 = I.nslots * wps / 4u;
+        const uint32_t nq = I.q_end - I.q_begin, wps = I.wps, bm_words = I.nslots * wps;
+        uint32_t *bm = lds;
+        uint32_t *smap = lds + bm_words;          // symbol -> first word of its slot, or ~0
+        uint32_t *rec = smap + 256;               // kBmRecWords per query
+        uint32_t *qc = rec + nq * kBmRecWords;    // per-query counts of the item
+        uint32_t *next = qc + nq;                 // next query group of the tile
         const uint64_t lo = I.tv.first, hi = I.tv.first + I.tv.n;
-        __syncthreads();  // previous item done with smap and counters
-        if (tid < 64u)
-            reinterpret_cast<uint32_t *>(smap)[tid] = reinterpret_cast<const uint32_t *>(I.smap)[tid];
+        __syncthreads();  // the previous item is done with the LDS
+        if (tid < 256u) {
+            const uint32_t sl = I.smap[tid];
+            smap[tid] = sl == 0xFFu ? 0xFFFFFFFFu : sl * wps;
+        }
+        for (uint32_t i = tid; i < nq * kBmRecWords; i += kBmWG)
+            rec[i] = a.recs[(uint64_t)I.q_begin * kBmRecWords + i];
         for (uint32_t i = tid; i < nq; i += kBmWG)
             qc[i] = 0u;
+        // thread c < wps holds the bytes of tile positions [32c, 32c + 32) (zero past the text's chunks)
+        uint4 tb0 = make_uint4(0, 0, 0, 0), tb1 = make_uint4(0, 0, 0, 0);
+        auto load_tile = [&](uint64_t tile) {
+            const uint64_t u = tile * kBmT + 32ull * tid;
+            tb0 = u < I.tv.end16 ? *reinterpret_cast<const uint4 *>(I.tv.base + u) : make_uint4(0, 0, 0, 0);
+            tb1 = u + 16u < I.tv.end16 ? *reinterpret_cast<const uint4 *>(I.tv.base + u + 16u)
+                                       : make_uint4(0, 0, 0, 0);
+        };
+        if (tid < wps)
+            load_tile(I.tile_begin);
         for (uint64_t tile = I.tile_begin; tile < I.tile_end; ++tile) {
             const uint64_t ts = tile * kBmT;
-            for (uint32_t i = tid; i < nw4; i += kBmWG)
+            for (uint32_t i = tid; i < bm_words / 4u; i += kBmWG)
                 reinterpret_cast<uint4 *>(bm)[i] = make_uint4(0, 0, 0, 0);
+            if (tid == 0)
+                *next = 0u;
             __syncthreads();
-            for (uint32_t c = tid; c < 2u * wps; c += kBmWG) {
-                const uint64_t u = ts + 16ull * c;
-                if (u >= I.tv.end16)
-                    continue;
-                const uint4 v = *reinterpret_cast<const uint4 *>(I.tv.base + u);
-                const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
-                const bool inner = u >= lo && u + 16u <= hi;
+            // text bytes lie at tile offsets [blo, bhi)
+            const uint32_t blo = tile_off(lo, ts), bhi = tile_off(hi, ts);
+            if (tid < wps) {
+                const uint32_t w[8] = {tb0.x, tb0.y, tb0.z, tb0.w, tb1.x, tb1.y, tb1.z, tb1.w};
+                const uint32_t valid = range_bits(32u * tid, blo, bhi);
 #pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    if (!inner && (u + i < lo || u + i >= hi))
-                        continue;
-                    const uint32_t slot = smap[(w4[i >> 2] >> (8 * (i & 3))) & 0xFFu];
-                    const uint32_t pos = 16u * c + (uint32_t)i;
-                    if (slot != 0xFFu)
-                        atomicOr(&bm[slot * wps + (pos >> 5)], 1u << (pos & 31u));
+                for (int h = 0; h < 4; ++h) {  // eight symbol lookups in flight, then their bits
+                    uint32_t base[8];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i)
+                        base[i] = smap[(w[2 * h + (i >> 2)] >> (8 * (i & 3))) & 0xFFu];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i)
+                        if (base[i] != 0xFFFFFFFFu && ((valid >> (8 * h + i)) & 1u))
+                            atomicOr(&bm[base[i] + tid], 1u << (8 * h + i));
                 }
             }
             __syncthreads();
-            const uint64_t tile_end = ts + kBmT - 1u;
-            auto init_f = [&](const BmQuery &Q, uint32_t (&f)[kBmV]) {
-                const uint64_t last = hi - (Q.mr & 0xFFFFFFu);
-                if (ts >= lo && tile_end <= last) {
-                    if constexpr (kBmV == 4) {
-                        f[0] = f[1] = f[2] = f[3] = 0xFFFFFFFFu;
-                    } else {
+            if (tid < wps && tile + 1u < I.tile_end)
+                load_tile(tile + 1u);  // in flight while this tile is searched
+            const bool inner = ts >= lo && ts + (kBmT - 1u) <= I.last_min;  // every start valid for every query
+            const uint32_t ngroups = (nq + (uint32_t)K - 1u) / (uint32_t)K;
+            // groups are taken from a counter, so that waves whose queries end early take more;
+            // a group's records are read one group ahead
+            auto take = [&]() -> uint32_t {
+                uint32_t g = 0;
+                if (lane == 0)
+                    g = atomicAdd(next, 1u);
+                return readlane(g, 0);
+            };
+            auto load_rec = [&](uint32_t g) -> uint32_t {
+                // lanes 8i .. 8i + 7 hold query gK + i's record; past the chunk, the last query's
+                const uint32_t qi = min(g * (uint32_t)K + lane / kBmRecWords, nq - 1u);
+                return (g < ngroups && lane < (uint32_t)K * kBmRecWords) ? rec[qi * kBmRecWords + lane % kBmRecWords]
+                                                                          : 0u;
+            };
+            uint32_t g = take();
+            uint32_t rv_next = load_rec(g);
+            while (g < ngroups) {
+                const uint32_t q0 = g * (uint32_t)K;
+                const uint32_t rv = rv_next;
+                g = take();
+                rv_next = load_rec(g);
+                uint32_t mr[K], f[K][kBmV];
+                uint32_t rmin = kMaxPeel;
 #pragma unroll
-                        for (int v = 0; v < kBmV; ++v)
-                            f[v] = 0xFFFFFFFFu;
-                    }
-                } else {
+                for (int i = 0; i < K; ++i) {
+                    mr[i] = readlane(rv, (uint32_t)i * kBmRecWords);
+                    rmin = min(rmin, mr[i] >> 24);
+                }
+                // the first compare sets f; on edge tiles it is then masked to the query's valid starts
+#pragma unroll
+                for (int i = 0; i < K; ++i) {
+                    const uint32_t e = readlane(rv, (uint32_t)i * kBmRecWords + 2u);
+                    const uint32_t *w = reinterpret_cast<const uint32_t *>(bmb + (e >> 5) + lane4);
 #pragma unroll
                     for (int v = 0; v < kBmV; ++v)
-                        f[v] = valid_bits(ts + 2048u * v + 32u * lane, lo, last);
+                        f[i][v] = __builtin_amdgcn_alignbit(w[64 * v + 1], w[64 * v], e);
                 }
-            };
-            // the rest of one query from compare l0 on, and its count
-            auto finish = [&](const BmQuery &Q, uint32_t (&f)[kBmV], uint32_t l0, uint32_t q) {
-                const uint32_t m = Q.mr & 0xFFFFFFu, r = Q.mr >> 24;
-                const uint32_t *st = a.steps + Q.steps_off;
-                for (uint32_t l = l0; l < r; ++l)
-                    bm_step(bm, ldc(&st[l]), lane, f);
-                bool alive = bm_any(f);
-                for (uint32_t l = r; alive && l < m; ++l) {
-                    bm_step(bm, l == 1u ? Q.e1 : ldc(&st[l]), lane, f);
-                    alive = bm_any(f);
+                if (!inner) {
+#pragma unroll
+                    for (int i = 0; i < K; ++i) {  // valid starts at tile offsets [blo, last + 1)
+                        const uint32_t shi = tile_off(hi - (mr[i] & 0xFFFFFFu) + 1u, ts);
+#pragma unroll
+                        for (int v = 0; v < kBmV; ++v)
+                            f[i][v] &= range_bits(2048u * v + 32u * lane, blo, shi);
+                    }
                 }
-                if (alive) {
-                    const uint32_t c = wave_sum32(bm_popc(f));
-                    if (lane == 0)
-                        qc[q - I.q_begin] += c;
+                const uint32_t rl = min(rmin, kBmRecSteps);
+                for (uint32_t l = 1; l < rl; ++l) {
+#pragma unroll
+                    for (int i = 0; i < K; ++i)
+                        bm_step(bmb, readlane(rv, (uint32_t)i * kBmRecWords + 2u + l), lane4, f[i]);
                 }
-            };
-            // queries q and q + kBmWaves: the peeled compares both have (the smaller r) go side by
-            // side; a lone last query is paired with itself and the copy's result dropped
-            for (uint32_t q = I.q_begin + wave; q < I.q_end; q += 2u * kBmWaves) {
-                const bool two = q + kBmWaves < I.q_end;
-                const BmQuery A = ldc(&a.queries[q]);
-                const BmQuery B = ldc(&a.queries[two ? q + kBmWaves : q]);
-                uint32_t fa[kBmV], fb[kBmV];
-                init_f(A, fa);
-                init_f(B, fb);
-                const uint32_t rj = min(A.mr >> 24, B.mr >> 24);
-                bm_step(bm, A.e0, lane, fa);
-                bm_step(bm, B.e0, lane, fb);
-                if (rj >= 2u) {
-                    bm_step(bm, A.e1, lane, fa);
-                    bm_step(bm, B.e1, lane, fb);
+#pragma unroll
+                for (int i = 0; i < K; ++i) {
+                    if (q0 + (uint32_t)i >= nq)
+                        continue;
+                    const uint32_t m = mr[i] & 0xFFFFFFu, r = mr[i] >> 24;
+                    const uint32_t rb = (uint32_t)i * kBmRecWords;
+                    auto entry = [&](uint32_t l) -> uint32_t {
+                        return l < kBmRecSteps ? readlane(rv, rb + 2u + l) : ldc(&a.steps[readlane(rv, rb + 1u) + l]);
+                    };
+                    uint32_t l = rl;
+                    for (; l < r; ++l)
+                        bm_step(bmb, entry(l), lane4, f[i]);
+                    bool alive = bm_any(f[i]);
+                    for (; alive && l < m; ++l) {
+                        bm_step(bmb, entry(l), lane4, f[i]);
+                        alive = bm_any(f[i]);
+                    }
+                    if (alive) {
+                        const uint32_t c = wave_sum32(bm_popc(f[i]));
+                        if (lane == 0)
+                            qc[q0 + (uint32_t)i] += c;
+                    }
                 }
-                for (uint32_t l = 2; l < rj; ++l) {
-                    const uint32_t ea = ldc(&a.steps[A.steps_off + l]), eb = ldc(&a.steps[B.steps_off + l]);
-                    bm_step(bm, ea, lane, fa);
-                    bm_step(bm, eb, lane, fb);
-                }
-                finish(A, fa, rj, q);
-                if (two)
-                    finish(B, fb, rj, q + kBmWaves);
             }
             __syncthreads();
         }
@@ -1375,15 +1432,16 @@ __device__ __forceinline__ void batch_bitmap(const BmArgs &a)
 
 __global__ __launch_bounds__(kBmWG) void k_batch_bitmap(BmArgs a)
 {
-    batch_bitmap(a);
+    batch_bitmap<4>(a);
 }
 
-// The same for alphabets whose bitmaps leave room for two workgroups per CU:
-// registers capped at 64 per lane so that both are resident (8 waves per
-// SIMD), which hides more of the latency of small alphabets' long tails.
+// The same for items whose LDS leaves room for two workgroups per CU (small
+// alphabets): registers capped at 64 per lane so that both are resident (8
+// waves per SIMD), which hides more of the latency of small alphabets' long
+// tails; groups of two queries keep the peel's reads within the cap.
 __global__ __launch_bounds__(kBmWG) __attribute__((amdgpu_waves_per_eu(8))) void k_batch_bitmap2(BmArgs a)
 {
-    batch_bitmap(a);
+    batch_bitmap<2>(a);
 }
 
 // ---------------------------------------------------------------- launchers
