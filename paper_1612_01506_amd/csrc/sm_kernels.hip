@@ -1305,16 +1305,17 @@ __device__ __forceinline__ void batch_bitmap(const BmArgs &a)
             rec[i] = a.recs[(uint64_t)I.q_begin * kBmRecWords + i];
         for (uint32_t i = tid; i < nq; i += kBmWG)
             qc[i] = 0u;
-        // thread c < wps holds the bytes of tile positions [32c, 32c + 32) (zero past the text's chunks)
-        uint4 tb0 = make_uint4(0, 0, 0, 0), tb1 = make_uint4(0, 0, 0, 0);
+        // the tile window's bytes in 8-byte pieces: piece c (window bytes [8c, 8c + 8)) for c = tid and
+        // c = tid + kBmWG, held in registers (zero past the text's chunks); 4 * wps pieces in all
+        const uint32_t npieces = 4u * wps;
+        uint2 tb0 = make_uint2(0, 0), tb1 = make_uint2(0, 0);
         auto load_tile = [&](uint64_t tile) {
-            const uint64_t u = tile * kBmT + 32ull * tid;
-            tb0 = u < I.tv.end16 ? *reinterpret_cast<const uint4 *>(I.tv.base + u) : make_uint4(0, 0, 0, 0);
-            tb1 = u + 16u < I.tv.end16 ? *reinterpret_cast<const uint4 *>(I.tv.base + u + 16u)
-                                       : make_uint4(0, 0, 0, 0);
+            const uint64_t u0 = tile * kBmT + 8ull * tid, u1 = u0 + 8ull * kBmWG;
+            tb0 = (tid < npieces && u0 < I.tv.end16) ? *reinterpret_cast<const uint2 *>(I.tv.base + u0) : make_uint2(0, 0);
+            tb1 = (tid + kBmWG < npieces && u1 < I.tv.end16) ? *reinterpret_cast<const uint2 *>(I.tv.base + u1)
+                                                              : make_uint2(0, 0);
         };
-        if (tid < wps)
-            load_tile(I.tile_begin);
+        load_tile(I.tile_begin);
         for (uint64_t tile = I.tile_begin; tile < I.tile_end; ++tile) {
             const uint64_t ts = tile * kBmT;
             for (uint32_t i = tid; i < bm_words / 4u; i += kBmWG)
@@ -1324,23 +1325,24 @@ __device__ __forceinline__ void batch_bitmap(const BmArgs &a)
             __syncthreads();
             // text bytes lie at tile offsets [blo, bhi)
             const uint32_t blo = tile_off(lo, ts), bhi = tile_off(hi, ts);
-            if (tid < wps) {
-                const uint32_t w[8] = {tb0.x, tb0.y, tb0.z, tb0.w, tb1.x, tb1.y, tb1.z, tb1.w};
-                const uint32_t valid = range_bits(32u * tid, blo, bhi);
+            auto build = [&](uint32_t c, uint2 v) {  // piece c: eight lookups in flight, then their bits
+                const uint32_t valid = range_bits(32u * (c >> 2), blo, bhi) >> (8u * (c & 3u));
+                const uint32_t w[2] = {v.x, v.y};
+                uint32_t base[8];
 #pragma unroll
-                for (int h = 0; h < 4; ++h) {  // eight symbol lookups in flight, then their bits
-                    uint32_t base[8];
+                for (int i = 0; i < 8; ++i)
+                    base[i] = smap[(w[i >> 2] >> (8 * (i & 3))) & 0xFFu];
 #pragma unroll
-                    for (int i = 0; i < 8; ++i)
-                        base[i] = smap[(w[2 * h + (i >> 2)] >> (8 * (i & 3))) & 0xFFu];
-#pragma unroll
-                    for (int i = 0; i < 8; ++i)
-                        if (base[i] != 0xFFFFFFFFu && ((valid >> (8 * h + i)) & 1u))
-                            atomicOr(&bm[base[i] + tid], 1u << (8 * h + i));
-                }
-            }
+                for (int i = 0; i < 8; ++i)
+                    if (base[i] != 0xFFFFFFFFu && ((valid >> i) & 1u))
+                        atomicOr(&bm[base[i] + (c >> 2)], 1u << (8u * (c & 3u) + i));
+            };
+            if (tid < npieces)
+                build(tid, tb0);
+            if (tid + kBmWG < npieces)
+                build(tid + kBmWG, tb1);
             __syncthreads();
-            if (tid < wps && tile + 1u < I.tile_end)
+            if (tile + 1u < I.tile_end)
                 load_tile(tile + 1u);  // in flight while this tile is searched
             const bool inner = ts >= lo && ts + (kBmT - 1u) <= I.last_min;  // every start valid for every query
             const uint32_t ngroups = (nq + (uint32_t)K - 1u) / (uint32_t)K;
@@ -1432,7 +1434,7 @@ __device__ __forceinline__ void batch_bitmap(const BmArgs &a)
 
 __global__ __launch_bounds__(kBmWG) void k_batch_bitmap(BmArgs a)
 {
-    batch_bitmap<4>(a);
+    batch_bitmap<8>(a);
 }
 
 // The same for items whose LDS leaves room for two workgroups per CU (small
