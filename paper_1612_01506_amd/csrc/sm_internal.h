@@ -67,6 +67,32 @@ struct BatchQuery {
     uint32_t pad;
 };
 
+// Byte-tile batch, single-query chunks.  A deal is up to 2^chunk_log2 consecutive tiles of one
+// query's text: (its query's record, first tile << 3 | number of tiles).
+struct BatchSolo {
+    TextView tv;
+    uint64_t last;         // coordinate of the query's last valid start
+    const uint64_t *steps; // the query's step table
+    uint32_t halo;         // LDS halo bytes (multiple of 16, >= m + 4)
+    uint32_t m;
+    uint32_t r;            // peel factor, 1..min(kMaxPeel, m)
+    uint32_t out;          // output slot
+};
+
+struct BatchDeal {
+    uint32_t solo;         // index of the query's record
+    uint32_t tiles;        // first tile within the text << 3 | number of tiles (1..2^chunk_log2 <= 7)
+};
+
+struct DealArgs {
+    const BatchDeal *deals;
+    const BatchSolo *solos;
+    uint64_t ndeals;
+    unsigned long long *counts;
+    uint32_t halo_max;     // largest halo (LDS buffer size)
+    uint32_t pad;
+};
+
 // Reporting batches, per query (same index as BatchQuery): nonzero per-vector
 // counts (array zeroed before) and their sums per kGroupBlocks group, as the
 // single-search report pass writes them.
@@ -164,6 +190,7 @@ hipError_t launch_fill_report(uint32_t *bc, uint64_t nblocks, unsigned long long
 hipError_t launch_hist(const TextView &tv, unsigned long long *hist, bool stream_loads, unsigned grid, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_batch_staged(const BatchArgs &a, int cpl, bool stream_loads, unsigned grid, hipStream_t s);
+hipError_t launch_batch_deals(const DealArgs &a, int cpl, bool stream_loads, unsigned grid, hipStream_t s);
 // two_per_cu: lds_bytes lets two workgroups share a CU (the register-capped instance runs)
 hipError_t launch_batch_bitmap(const BmArgs &a, unsigned grid, uint32_t lds_bytes, bool two_per_cu, hipStream_t s);
 // Non-overlapping selection over the ascending occurrence list (c entries).

@@ -1079,6 +1079,121 @@ __global__ __launch_bounds__(kWG) void k_batch_staged(BatchArgs a)
         flush(cur);
 }
 
+// The vectors of wave `wave` in a staged tile with valid tile offsets lo..hi, searched with a
+// compile-time peel R; returns the lane's count.
+template <int CPL, int R>
+__device__ __forceinline__ uint32_t search_tile(const uint64_t *steps, uint32_t m, const uint8_t *cur, uint32_t wave,
+                                                uint32_t lane, uint32_t lo, uint32_t hi)
+{
+    uint64_t pk[R];
+#pragma unroll
+    for (int l = 0; l < R; ++l)
+        pk[l] = ldc(&steps[l]);
+    uint32_t acc = 0;
+#pragma unroll
+    for (int b = 0; b < CPL; ++b) {
+        const uint32_t boff = (wave * CPL + b) * kBlock;
+        if (boff > hi)
+            break;
+        uint32_t d[4];
+        const bool edge = boff < lo || boff + (kBlock - 1u) > hi;
+        const LdsText tx{cur + boff, cur + boff + 4u * lane};
+        if (search_vector_tile<R>(steps, pk, m, lane, d, tx, edge, boff, lo, hi))
+            acc += count_alive(d);
+    }
+    return acc;
+}
+
+// Persistent batched count of single-query chunks.  Deal k (up to 2^chunk_log2
+// consecutive tiles of one query's text) goes to workgroup k mod G; the deal
+// names its query's record (text, step table, peel, bounds, output slot).  The
+// tiles are staged by the same double-buffered LDS DMA as the single search,
+// the next tile (possibly the next deal's first) in flight while one is
+// searched, with the peel compiled in (a switch on the query's r).  The next
+// deal's records are loaded one deal ahead.  The count stays in registers over
+// a deal and is added to its output once per wave.
+struct DealView {
+    BatchSolo S;
+    uint64_t ts0;  // coordinate of the deal's first tile
+    uint32_t ntiles;
+};
+
+template <int CPL>
+__device__ __forceinline__ DealView load_deal(const DealArgs &a, uint64_t k)
+{
+    constexpr uint32_t T = kWG * 16u * CPL;
+    const BatchDeal D = ldc(&a.deals[k]);
+    DealView v;
+    v.S = ldc(&a.solos[D.solo]);
+    v.ts0 = (uint64_t)(D.tiles >> 3) * T;
+    v.ntiles = D.tiles & 7u;
+    return v;
+}
+
+template <int CPL, bool STREAM>
+__global__ __launch_bounds__(kWG) void k_batch_deals(DealArgs a)
+{
+    extern __shared__ __align__(16) uint8_t lds[];
+    constexpr uint32_t T = kWG * 16u * CPL;
+    constexpr int kPolicy = STREAM ? kLoadStream : kLoadDefault;
+    const uint32_t TB = T + a.halo_max;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = wave_id();
+    uint64_t k = blockIdx.x;
+    if (k >= a.ndeals)
+        return;
+    DealView D = load_deal<CPL>(a, k);
+    DealView N = k + gridDim.x < a.ndeals ? load_deal<CPL>(a, k + gridDim.x) : D;
+    dma_tile<CPL, kPolicy>(D.S.tv, D.ts0, tid, D.S.halo >> 4, lds);
+    uint32_t acc = 0;
+    uint32_t t = 0;  // tile of the deal
+    for (uint64_t i = 0;; ++i) {
+        uint8_t *cur = lds + (i & 1u) * TB;
+        const bool more = t + 1u < D.ntiles;
+        const bool next_deal = k + gridDim.x < a.ndeals;
+        wait_dma();
+        __syncthreads();  // tile visible to all waves; the other buffer is free
+        if (more)
+            dma_tile<CPL, kPolicy>(D.S.tv, D.ts0 + (uint64_t)(t + 1u) * T, tid, D.S.halo >> 4,
+                                   lds + ((i + 1) & 1u) * TB);
+        else if (next_deal)
+            dma_tile<CPL, kPolicy>(N.S.tv, N.ts0, tid, N.S.halo >> 4, lds + ((i + 1) & 1u) * TB);
+        // the tile's valid starts as 32-bit tile offsets lo..hi (the deal's tiles all hold one)
+        const uint64_t ts = D.ts0 + (uint64_t)t * T;
+        const uint64_t rem = D.S.last - ts;
+        const uint32_t hi = rem >= T ? T - 1u : (uint32_t)rem;
+        const uint32_t lo = ts < D.S.tv.first ? (uint32_t)(D.S.tv.first - ts) : 0u;
+        const uint64_t *st = D.S.steps;
+        const uint32_t m = D.S.m;
+        switch (D.S.r) {
+        case 1: acc += search_tile<CPL, 1>(st, m, cur, wave, lane, lo, hi); break;
+        case 2: acc += search_tile<CPL, 2>(st, m, cur, wave, lane, lo, hi); break;
+        case 3: acc += search_tile<CPL, 3>(st, m, cur, wave, lane, lo, hi); break;
+        case 4: acc += search_tile<CPL, 4>(st, m, cur, wave, lane, lo, hi); break;
+        case 5: acc += search_tile<CPL, 5>(st, m, cur, wave, lane, lo, hi); break;
+        case 6: acc += search_tile<CPL, 6>(st, m, cur, wave, lane, lo, hi); break;
+        case 7: acc += search_tile<CPL, 7>(st, m, cur, wave, lane, lo, hi); break;
+        default: acc += search_tile<CPL, 8>(st, m, cur, wave, lane, lo, hi); break;
+        }
+        if (more) {
+            ++t;
+            continue;
+        }
+        if (__any(acc != 0u)) {  // end of the deal: its count (< 2^32 starts) once per wave
+            const uint32_t c = wave_sum32(acc);
+            if (lane == 0)
+                atomicAdd(&a.counts[D.S.out], (unsigned long long)c);
+        }
+        acc = 0;
+        if (!next_deal)
+            break;
+        k += gridDim.x;
+        D = N;
+        if (k + gridDim.x < a.ndeals)
+            N = load_deal<CPL>(a, k + gridDim.x);
+        t = 0;
+    }
+}
+
 // ----------------------------------------------------- non-overlapping mode
 //
 // Disjoint occurrences by greedy leftmost selection over the ascending list of
@@ -1580,6 +1695,24 @@ static hipError_t launch_batch_t(const BatchArgs &a, unsigned grid, hipStream_t 
 }
 
 template <bool STREAM>
+static hipError_t launch_deals_c(const DealArgs &a, int cpl, unsigned grid, hipStream_t s)
+{
+    const uint32_t lds = 2u * (kWG * 16u * (uint32_t)cpl + a.halo_max);
+    switch (cpl) {
+    case 1: hipLaunchKernelGGL((k_batch_deals<1, STREAM>), dim3(grid), dim3(kWG), lds, s, a); break;
+    case 2: hipLaunchKernelGGL((k_batch_deals<2, STREAM>), dim3(grid), dim3(kWG), lds, s, a); break;
+    case 4: hipLaunchKernelGGL((k_batch_deals<4, STREAM>), dim3(grid), dim3(kWG), lds, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_deals(const DealArgs &a, int cpl, bool stream_loads, unsigned grid, hipStream_t s)
+{
+    return stream_loads ? launch_deals_c<true>(a, cpl, grid, s) : launch_deals_c<false>(a, cpl, grid, s);
+}
+
+template <bool STREAM>
 static hipError_t launch_batch_c(const BatchArgs &a, int cpl, unsigned grid, hipStream_t s)
 {
     switch (cpl) {
@@ -1682,7 +1815,9 @@ static hipError_t prime_cpl()
                         reinterpret_cast<const void *>(&k_batch_staged<CPL, false, false>),
                         reinterpret_cast<const void *>(&k_batch_staged<CPL, true, false>),
                         reinterpret_cast<const void *>(&k_batch_staged<CPL, false, true>),
-                        reinterpret_cast<const void *>(&k_batch_staged<CPL, true, true>)};
+                        reinterpret_cast<const void *>(&k_batch_staged<CPL, true, true>),
+                        reinterpret_cast<const void *>(&k_batch_deals<CPL, false>),
+                        reinterpret_cast<const void *>(&k_batch_deals<CPL, true>)};
     for (const void *k : ks) {
         hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
         if (e != hipSuccess)
