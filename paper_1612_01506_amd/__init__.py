@@ -15,6 +15,7 @@ tensors, patterns are host bytes.
 """
 from __future__ import annotations
 
+import array
 import ctypes
 from typing import Iterable, Sequence
 
@@ -262,11 +263,14 @@ class PackedTexts:
         return int(self.offsets.size)
 
     def table(self) -> np.ndarray:
+        if getattr(self, "_table", None) is not None:
+            return self._table
         t = np.zeros(max(len(self), 1), dtype=_TEXT_DT)
         t["t"][:len(self)] = np.uint64(self.buf.data_ptr()) + self.offsets
         t["n"][:len(self)] = self.lengths
         if self.hists is not None:
             t["hist"][:len(self)] = np.uint64(self.hists.ctypes.data) + 2048 * np.arange(len(self), dtype=np.uint64)
+        self._table = t  # the buffer, offsets, lengths and histograms are fixed at construction
         return t
 
 
@@ -295,10 +299,13 @@ def _marshal_batch(texts, queries, use_hist: bool):
     nq = len(qs)
     qarr = np.zeros(max(nq, 1), dtype=_QUERY_DT)
     if nq:
-        raw = [q[1] for q in qs]
-        if all(type(p) is bytes for p in raw):       # fast path: one join, no per-pattern arrays
+        sizes = set(map(len, qs))
+        cols = list(zip(*qs)) if len(sizes) == 1 else None   # column-wise in C when all queries agree
+        tids = cols[0] if cols else [q[0] for q in qs]
+        raw = cols[1] if cols else [q[1] for q in qs]
+        if set(map(type, raw)) == {bytes}:          # fast path: one join, no per-pattern arrays
             blob = np.frombuffer(b"".join(raw) or b"\0", dtype=np.uint8)
-            lens = np.fromiter(map(len, raw), dtype=np.uint64, count=nq)
+            lens = np.frombuffer(array.array("Q", map(len, raw)), dtype=np.uint64)
         else:
             pats = [_pat(p) for p in raw]
             lens = np.fromiter((p.size for p in pats), dtype=np.uint64, count=nq)
@@ -306,10 +313,10 @@ def _marshal_batch(texts, queries, use_hist: bool):
         keep.append(blob)
         offs = np.zeros(nq, dtype=np.uint64)
         np.cumsum(lens[:-1], out=offs[1:])
-        qarr["text_id"][:nq] = np.fromiter((q[0] for q in qs), dtype=np.int64, count=nq).astype(np.uint32)
+        qarr["text_id"][:nq] = np.frombuffer(array.array("q", tids), dtype=np.int64).astype(np.uint32)
         qarr["p"][:nq] = np.where(lens > 0, np.uint64(blob.ctypes.data) + offs, 0)
         qarr["m"][:nq] = lens
-        for i, q in (enumerate(qs) if max(map(len, qs)) > 2 else ()):   # queries with their own order
+        for i, q in (enumerate(qs) if max(sizes) > 2 else ()):   # queries with their own order
             if len(q) > 2 and q[2] is not None:
                 tid = int(q[0])
                 tx = texts[tid] if 0 <= tid < len(texts) else None

@@ -1310,6 +1310,14 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
     // record per deal); the rest form one global tile space
     std::vector<uint32_t> solo_q;     // per single-query chunk: its index in `staged`
     std::vector<BatchDeal> solo;      // deals (tiles of one single-query chunk)
+    if (!rep) {
+        uint64_t est = 0;
+        for (auto &c : chunks)
+            if (c.q1 - c.q0 == 1)
+                est += ceil_div(texts[c.text].n + 16, T << kChunkLog2);
+        solo.reserve(est);
+        solo_q.reserve(chunks.size());
+    }
     uint32_t deal_halo = 16;
     uint64_t deal_bytes = 0;
     // ---- byte-tile chunks in one global tile space
