@@ -8,6 +8,12 @@ symbol histogram of the text, frequency compare order of every pattern, one
 count search per pattern and, for m >= 64, the reporting search (positions).
 `value` is whole-job text throughput: bytes of text scanned by all searches
 of a step divided by the step time (GB/s, 1e9 B/s), inputs resident in HBM.
+After the timed steps the same line also reports, each measured on its own:
+the count kernel's roofline, the CPU baselines (the oracle on this GPU's host
+threads and on one thread, the paper's Algorithm 4 with AVX2), the batched
+forms (10,000 patterns on a 2 GiB text; 4,096 texts) against the sequential
+single-search form, and the serving loop's p50/p99 latency at a few offered
+loads (--no-extras skips the last two).
 
 Other workloads (--workload) print their own JSON line: single (8 MiB ACGT),
 small (sigma 2/4 and periodic texts), batched (10,000 patterns on a 2 GiB
@@ -177,26 +183,63 @@ def run_zipf(args):
         torch.cuda.synchronize()
         del dst
 
+    import cpu_alg4
     import oracle  # CPU baseline and sampled parity: the oracle as it stands
-    ncores = oracle.default_threads()
+    # the host threads of this GPU's share of the box (OMP_NUM_THREADS when set), and all it has
+    nproc = os.cpu_count() or 1
+    ncores = max(1, min(nproc, int(os.environ.get("OMP_NUM_THREADS") or nproc)))
     # one pattern of each length in turn (the first of each, then the second, ...) until the time
     # budget is spent: a bounded sample of the same workload
     nlen = len(patterns) // args.per_m
     sample_idx = [k * args.per_m + j for j in range(args.per_m) for k in range(nlen)]
-    cpu_bytes, cpu_t = 0, 0.0
-    for i in sample_idx:
-        if cpu_t >= args.cpu_seconds:
-            break
-        t2 = time.perf_counter()
-        want = oracle.count(patterns[i], t_host, ncores)
-        cpu_t += time.perf_counter() - t2
-        cpu_bytes += n
-        assert want == counts[i], ("parity", i, len(patterns[i]), want, counts[i])
-    checked = cpu_bytes // n
+
+    def cpu_leg(fn, seconds):
+        nb, tt, nchk = 0, 0.0, 0
+        for i in sample_idx:
+            if tt >= seconds:
+                break
+            t2 = time.perf_counter()
+            want = fn(i)
+            tt += time.perf_counter() - t2
+            nb += n
+            nchk += 1
+            assert want == counts[i], ("parity", i, len(patterns[i]), want, counts[i])
+        return (round(nb / tt / 1e9, 3) if tt else None), nchk, tt
+
+    cpu_gbs, checked, cpu_t = cpu_leg(lambda i: oracle.count(patterns[i], t_host, ncores), args.cpu_seconds)
+    cpu1_gbs, checked1, cpu1_t = cpu_leg(lambda i: oracle.count(patterns[i], t_host, 1), args.cpu_seconds / 3)
+    alg4 = None
+    if cpu_alg4.available() and args.cpu_seconds > 0:
+        orders = {}
+
+        def a4(i, th):
+            if i not in orders:
+                orders[i] = cpu_alg4.freq_order(patterns[i], state["hist"])
+            return cpu_alg4.count(patterns[i], t_host, orders[i], min(2, len(patterns[i])), th)
+
+        a1, c1, s1 = cpu_leg(lambda i: a4(i, 1), args.cpu_seconds / 3)
+        an, cn, sn = cpu_leg(lambda i: a4(i, ncores), args.cpu_seconds / 3)
+        alg4 = {"value_1_thread": a1, "value_all_threads": an, "threads": ncores, "unit": "GB/s",
+                "method": "Algorithm 4 with AVX2 (32 starts per vector), frequency order from the text's "
+                          "histogram, peel r = 2 (Section 3's value for large alphabets)",
+                "sample": f"{c1} patterns on 1 thread ({s1:.1f} s) and {cn} on {ncores} threads ({sn:.1f} s), "
+                          "lengths taken in turn, full text; every count equal to the GPU's"}
     if args.cpu_seconds > 0:
         i0 = rep_idx[0]
         assert np.array_equal(state["plist"][0].cpu().numpy().astype(np.uint64), oracle.report(patterns[i0], t_host))
-    log(f"[bench] sampled parity vs oracle OK on {checked} patterns; report lists verified")
+    log(f"[bench] sampled parity vs oracle OK on {checked} + {checked1} patterns; report lists verified")
+
+    extras = {}
+    if not args.no_extras:
+        del t_dev, posbuf, totals_dev
+        state.clear()
+        torch.cuda.empty_cache()
+        extras["batched"] = {
+            "one_text": batched_one_text(args, args.nq, 2),
+            "many_texts": batched_many_texts(args, args.ntexts, 3),
+        }
+        points, info = serve_points(args, args.serve_rates, args.serve_seconds, args.max_requests)
+        extras["serve"] = dict(info, points=points)
 
     return {
         "metric": "text GB/s per search (% HBM peak)",
@@ -232,11 +275,16 @@ def run_zipf(args):
         "histogram": {"avg_us": round(hist_ms * 1e3, 1), "GBps": round(n / (hist_ms * 1e-3) / 1e9, 1),
                       "kernel": "k_hist (per-lane LDS bin copies)"},
         "cpu_baseline": {
-            "value": round(cpu_bytes / cpu_t / 1e9, 3) if cpu_t else None, "unit": "GB/s",
-            "cores": ncores, "kind": "oracle",
+            "value": cpu_gbs, "unit": "GB/s", "cores": ncores, "kind": "oracle",
             "sample": f"oracle count (Algorithm 1, OpenMP over starts) of {checked} patterns "
-                      f"(lengths taken in turn) over the full {n}-byte text, {cpu_t:.1f} s; host: {cpu_info()}",
+                      f"(lengths taken in turn) over the full {n}-byte text, {cpu_t:.1f} s on {ncores} threads "
+                      f"(this GPU's share of the host, OMP_NUM_THREADS); host: {cpu_info()}, {nproc} hardware threads",
+            "host_nproc": nproc,
+            "single_thread": {"value": cpu1_gbs, "unit": "GB/s",
+                              "sample": f"{checked1} patterns, {cpu1_t:.1f} s, 1 thread"},
+            "alg4_avx2": alg4,
         },
+        **extras,
     }
 
 
@@ -279,20 +327,18 @@ def _plan_times(sm, texts, queries, out_len, reps, want):
     return t_create, t_run, t_graph
 
 
-def run_batched(args):
-    """10,000 patterns on one 2 GiB text, and 4,096 texts with one pattern each: the sequential
-    single-search form (one count launch per query, one final sync) against one sm_count_batch."""
+def batched_one_text(args, nq: int, reps: int):
+    """10,000 patterns on one 2 GiB Zipf text: the sequential single-search form (one count launch
+    per query, one final sync) against one sm_count_batch call, a plan run and a graph replay."""
     import torch
 
     import paper_1612_01506_amd as sm
     import synth
 
     dev = torch.device("cuda:0")
-    lines = []
-    # ---- one text, many patterns
     n = args.n if args.n != (1 << 30) else (2 << 30)
     t0 = time.time()
-    t_host, pats = synth.batched_one_text_workload(n=n, nq=args.nq)
+    t_host, pats = synth.batched_one_text_workload(n=n, nq=nq)
     log(f"[bench] batched: {n} B text, {len(pats)} patterns in {time.time() - t0:.1f}s")
     t_dev = torch.from_numpy(t_host).to(dev)
     text = sm.Text(t_dev)
@@ -317,32 +363,33 @@ def run_batched(args):
         return out
 
     batched()
-    tb, cb = min((_timed(batched) for _ in range(args.steps)), key=lambda x: x[0])
+    tb, cb = min((_timed(batched) for _ in range(reps)), key=lambda x: x[0])
     sequential()
     ts, cs = _timed(sequential)
     assert torch.equal(cb, cs), "batched and sequential counts differ"
     cb = cb.cpu().numpy()
-    pc, pr, pg = _plan_times(sm, [text], queries, len(pats), max(args.steps, 3), torch.from_numpy(cb).to(dev))
-    mean_m = float(np.mean([len(p) for p in pats]))
-    lines.append({
-        "metric": "batched searches/s", "value": round(len(pats) / tb, 1), "unit": "searches/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": round(tb * 1e3, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
-        "data": "synthetic (seeded Zipf text; half substring, half random patterns)",
-        "config": {"workload": f"batched_one_text: {len(pats)} patterns, m log-uniform [2,1024] "
-                               f"(mean {mean_m:.0f}), {n}-byte Zipf(1.0) sigma=95 text",
-                   "sequential_s": round(ts, 4), "batched_s": round(tb, 4),
-                   "batched_host_enqueue_s": round(min(enq), 4),
-                   "plan_create_s": round(pc, 4), "plan_run_s": round(pr, 4), "plan_graph_replay_s": round(pg, 4),
-                   "speedup_vs_sequential": round(ts / tb, 2),
-                   "sequential_text_GBps": round(len(pats) * n / ts / 1e9, 1),
-                   "logical_text_GBps_batched": round(len(pats) * n / tb / 1e9, 1),
-                   "checked": "batched == sequential single searches (full-size oracle parity: tests/)"},
-    })
+    pc, pr, pg = _plan_times(sm, [text], queries, len(pats), max(reps, 3), torch.from_numpy(cb).to(dev))
     del t_dev, text
     torch.cuda.empty_cache()
-    # ---- many texts, one pattern each
-    texts_h, pats2 = synth.batched_many_texts_workload(ntexts=args.ntexts)
+    return {"patterns": len(pats), "text_bytes": n, "mean_m": round(float(np.mean([len(p) for p in pats])), 1),
+            "sequential_s": round(ts, 4), "batched_s": round(tb, 4), "batched_host_enqueue_s": round(min(enq), 4),
+            "plan_create_s": round(pc, 4), "plan_run_s": round(pr, 4), "plan_graph_replay_s": round(pg, 4),
+            "searches_per_s": round(len(pats) / tb, 1), "sequential_searches_per_s": round(len(pats) / ts, 1),
+            "speedup_vs_sequential": round(ts / tb, 2),
+            "sequential_text_GBps": round(len(pats) * n / ts / 1e9, 1),
+            "logical_text_GBps_batched": round(len(pats) * n / tb / 1e9, 1),
+            "checked": "batched == sequential single searches, every count (oracle parity at full size: tests/)"}
+
+
+def batched_many_texts(args, ntexts: int, reps: int):
+    """4,096 resident texts of 4 KiB - 4 MiB with one pattern each: sequential against one batch."""
+    import torch
+
+    import paper_1612_01506_amd as sm
+    import synth
+
+    dev = torch.device("cuda:0")
+    texts_h, pats2 = synth.batched_many_texts_workload(ntexts=ntexts)
     total = sum(t.size for t in texts_h)
     big = torch.empty(total + 16 * len(texts_h), dtype=torch.uint8, device=dev)
     views, off = [], 0
@@ -377,29 +424,39 @@ def run_batched(args):
         return out
 
     batched2()
-    tb2, cb2 = min((_timed(batched2) for _ in range(args.steps)), key=lambda x: x[0])
+    tb2, cb2 = min((_timed(batched2) for _ in range(reps)), key=lambda x: x[0])
     sequential2()
     ts2, cs2 = _timed(sequential2)
     assert torch.equal(cb2, cs2), "batched and sequential counts differ (many texts)"
     cb2 = cb2.cpu().numpy()
-    pc2, pr2, pg2 = _plan_times(sm, packed, q2, len(pats2), max(args.steps, 10), torch.from_numpy(cb2).to(dev))
-    lines.append({
-        "metric": "batched searches/s", "value": round(len(pats2) / tb2, 1), "unit": "searches/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": round(tb2 * 1e3, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
-        "data": "synthetic (seeded texts sigma 4/20/95, one substring pattern each)",
-        "config": {"workload": f"batched_many_texts: {len(pats2)} texts, {total} bytes in all, "
-                               "lengths log-uniform [4 KiB, 4 MiB], m log-uniform [4,256]",
-                   "sequential_s": round(ts2, 4), "batched_s": round(tb2, 4),
-                   "batched_host_enqueue_s": round(min(enq2), 4),
-                   "plan_create_s": round(pc2, 4), "plan_run_s": round(pr2, 5),
-                   "plan_graph_replay_s": round(pg2, 5),
-                   "text_GBps_plan_replay": round(total / pg2 / 1e9, 1),
-                   "histograms_once_s": round(hist_s, 4),
-                   "speedup_vs_sequential": round(ts2 / tb2, 2),
-                   "text_GBps_batched": round(total / tb2 / 1e9, 1)},
-    })
-    return lines
+    pc2, pr2, pg2 = _plan_times(sm, packed, q2, len(pats2), max(reps, 10), torch.from_numpy(cb2).to(dev))
+    del big, views, packed
+    torch.cuda.empty_cache()
+    return {"texts": len(pats2), "text_bytes": total, "sequential_s": round(ts2, 5), "batched_s": round(tb2, 5),
+            "batched_host_enqueue_s": round(min(enq2), 5), "plan_create_s": round(pc2, 4),
+            "plan_run_s": round(pr2, 5), "plan_graph_replay_s": round(pg2, 5),
+            "text_GBps_plan_replay": round(total / pg2 / 1e9, 1), "histograms_once_s": round(hist_s, 4),
+            "searches_per_s": round(len(pats2) / tb2, 1), "speedup_vs_sequential": round(ts2 / tb2, 2),
+            "text_GBps_batched": round(total / tb2 / 1e9, 1),
+            "checked": "batched == sequential single searches, every count"}
+
+
+def run_batched(args):
+    """Both batched workloads as JSON lines of their own."""
+    one = batched_one_text(args, args.nq, args.steps)
+    many = batched_many_texts(args, args.ntexts, args.steps)
+    common = {"n_gpus": 1, "steps": args.steps, "warmup": 1, "higher_is_better": True, "scaling": "weak",
+              "vs_baseline": None, "dtype": "u8", "metric": "batched searches/s", "unit": "searches/s"}
+    return [
+        dict(common, value=one["searches_per_s"], ms_per_step=round(one["batched_s"] * 1e3, 3),
+             data="synthetic (seeded Zipf text; half substring, half random patterns)",
+             config=dict(one, workload=f"batched_one_text: {one['patterns']} patterns, m log-uniform [2,1024], "
+                                       f"{one['text_bytes']}-byte Zipf(1.0) sigma=95 text")),
+        dict(common, value=many["searches_per_s"], ms_per_step=round(many["batched_s"] * 1e3, 3),
+             data="synthetic (seeded texts sigma 4/20/95, one substring pattern each)",
+             config=dict(many, workload=f"batched_many_texts: {many['texts']} texts, {many['text_bytes']} bytes "
+                                        "in all, lengths log-uniform [4 KiB, 4 MiB], m log-uniform [4,256]")),
+    ]
 
 
 # ---------------------------------------------------------------------- single
@@ -697,8 +754,10 @@ def run_nonoverlap(args):
 
 
 # ----------------------------------------------------------------------- serve
-def run_serve(args):
-    """Open-loop Poisson requests against 8 resident texts, swept offered load."""
+def serve_points(args, rates, seconds: float, max_requests: int):
+    """Open-loop Poisson requests against 8 resident 1 GiB texts at each offered load in `rates`;
+    returns one summary per load point.  Results are checked outside the clock: reported positions
+    are occurrences, and a sample of counts equals the same search alone."""
     import torch
 
     import paper_1612_01506_amd as sm
@@ -720,6 +779,7 @@ def run_serve(args):
     ex = GpuExecutor([torch.from_numpy(t).to(dev) for t in texts_h], nstreams=args.streams)
     alphabets = [bytes(np.unique(t[:1 << 20])) for t in texts_h]
     g = synth.rng(5, 100)
+    budget_us = args.batch_budget_ms * 1e3 if args.batch_budget_ms > 0 else None
 
     def make_requests(count):
         tid = g.integers(0, len(texts_h), size=count)
@@ -734,25 +794,27 @@ def run_serve(args):
         return out
 
     # warm-up (kernel attributes, allocator, histograms)
-    srv = Server(ex, hbm_budget=args.hbm_budget, on_done=lambda r: setattr(r, "positions", None))
+    adaptive = not args.fixed_budget
+    srv = Server(ex, hbm_budget=args.hbm_budget, on_done=lambda r: None, batch_budget_us=budget_us,
+                 adaptive=adaptive)
     for t, p, r in make_requests(256):
         srv.submit(t, p, r)
     srv.drain()
 
-    lines = []
+    points = []
     last = None
-    for rate in args.rates:
-        nreq = int(min(args.max_requests, max(1000, rate * args.seconds)))
+    for rate in rates:
+        nreq = int(min(max_requests, max(1000, rate * seconds)))
         reqs = make_requests(nreq)
         arrivals = np.cumsum(g.exponential(1.0 / rate, size=nreq))
         checks = []
 
-        def consume(r):  # the client takes the result; position buffers are dropped at once
+        def consume(r):  # the client takes the result; the server frees the positions after this
             if r.report and len(checks) < 20 and 0 < r.count < (1 << 20):
                 checks.append((r.text_id, r.pattern, r.positions[:64].cpu().numpy()))
-            r.positions = None
 
-        srv = Server(ex, hbm_budget=args.hbm_budget, on_done=consume)
+        srv = Server(ex, hbm_budget=args.hbm_budget, on_done=consume, batch_budget_us=budget_us,
+                     adaptive=adaptive)
         clock = srv.clock
         start = clock()
         k = 0
@@ -767,24 +829,18 @@ def run_serve(args):
         elapsed = clock() - start
         st = srv.stats()
         done = st["completed"]
-        rec = {"metric": "served p50/p99 latency", "value": round(st.get("p99_ms", float("nan")), 3),
-               "unit": "ms (p99)", "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": round(elapsed * 1e3, 1),
-               "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
-               "data": "synthetic (8 seeded texts; Poisson arrivals; half substring, half random patterns)",
-               "config": {"workload": f"serve: 8 resident texts of {n} B, m log-uniform [2,512], 5% report",
-                          "offered_req_per_s": rate, "achieved_req_per_s": round(done / elapsed, 1),
-                          "requests": nreq, "p50_ms": round(st.get("p50_ms", float("nan")), 3),
-                          "p99_ms": round(st.get("p99_ms", float("nan")), 3),
-                          "count_p50_ms": round(st.get("count_p50_ms", float("nan")), 3),
-                          "count_p99_ms": round(st.get("count_p99_ms", float("nan")), 3),
-                          "report_p50_ms": round(st.get("report_p50_ms", float("nan")), 3),
-                          "report_p99_ms": round(st.get("report_p99_ms", float("nan")), 3),
-                          "mean_batch": st.get("mean_batch"),
-                          "batches": st["batches"], "rejected": st["rejected"],
-                          "peak_reserved_bytes": st["peak_reserved_bytes"], "hbm_budget_bytes": args.hbm_budget,
-                          "streams": args.streams}}
-        log(f"[bench] serve rate {rate}/s: {json.dumps(rec['config'])}")
-        lines.append(rec)
+        pt = {"offered_req_per_s": rate, "achieved_req_per_s": round(done / elapsed, 1), "requests": nreq,
+              "p50_ms": round(st.get("p50_ms", float("nan")), 3), "p99_ms": round(st.get("p99_ms", float("nan")), 3),
+              "count_p50_ms": round(st.get("count_p50_ms", float("nan")), 3),
+              "count_p99_ms": round(st.get("count_p99_ms", float("nan")), 3),
+              "report_p50_ms": round(st.get("report_p50_ms", float("nan")), 3),
+              "report_p99_ms": round(st.get("report_p99_ms", float("nan")), 3),
+              "mean_batch": None if st.get("mean_batch") is None else round(st["mean_batch"], 1),
+              "max_batch_model_us": None if st.get("max_batch_cost_us") is None else round(st["max_batch_cost_us"], 1),
+              "batches": st["batches"], "rejected": st["rejected"],
+              "peak_reserved_bytes": st["peak_reserved_bytes"], "seconds": round(elapsed, 2)}
+        log(f"[bench] serve rate {rate}/s: {json.dumps(pt)}")
+        points.append(pt)
         last = handles
         for tid, p, pos in checks:   # the positions reported in the mix are occurrences of p
             for q in pos:
@@ -793,6 +849,29 @@ def run_serve(args):
     for r in last[:: max(1, len(last) // 200)]:
         if r.status == "done":
             assert r.count == sm.count(ex.texts[r.text_id], r.pattern), ("mix != alone", r.rid)
+    del ex
+    torch.cuda.empty_cache()
+    return points, {"texts": f"8 resident texts of {n} B (sigma 2/4/4/20/20/95/95/95, uniform or Zipf)",
+                    "patterns": "m log-uniform [2,512], half substring, half random", "report_fraction": 0.05,
+                    "hbm_budget_bytes": args.hbm_budget, "batch_budget_ms": args.batch_budget_ms,
+                    "batch_budget": "fixed" if args.fixed_budget else "adaptive (the budget or the oldest wait)",
+                    "streams": args.streams,
+                    "checked": "reported positions are occurrences; sampled counts equal the search alone"}
+
+
+def run_serve(args):
+    """Open-loop Poisson requests against 8 resident texts, swept offered load: one line per load."""
+    points, info = serve_points(args, args.rates, args.seconds, args.max_requests)
+    lines = []
+    for pt in points:
+        lines.append({"metric": "served p50/p99 latency", "value": pt["p99_ms"], "unit": "ms (p99)", "n_gpus": 1,
+                      "steps": 1, "warmup": 1, "ms_per_step": round(pt["seconds"] * 1e3, 1),
+                      "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+                      "data": "synthetic (8 seeded texts; Poisson arrivals; half substring, half random patterns)",
+                      "config": dict(pt, workload=f"serve: {info['texts']}, {info['patterns']}, 5% report",
+                                     hbm_budget_bytes=info["hbm_budget_bytes"],
+                                     batch_budget_ms=info["batch_budget_ms"], batch_budget=info["batch_budget"],
+                                     streams=info["streams"])})
     return lines
 
 
@@ -810,10 +889,18 @@ def main():
     ap.add_argument("--streams", type=int, default=2, help="serve: device streams (in-flight batches)")
     ap.add_argument("--hbm-budget", type=int, default=1 << 30, dest="hbm_budget",
                     help="serve: bytes of HBM for report position buffers")
+    ap.add_argument("--batch-budget-ms", type=float, default=10.0, dest="batch_budget_ms",
+                    help="serve: modelled device time per batch (0: no bound)")
+    ap.add_argument("--fixed-budget", action="store_true", dest="fixed_budget",
+                    help="serve: no batch exceeds --batch-budget-ms (default: adaptive, up to the oldest wait)")
+    ap.add_argument("--serve-rates", type=float, nargs="+", default=[1000, 5000, 12000], dest="serve_rates",
+                    help="default workload: offered loads of the serve object")
+    ap.add_argument("--serve-seconds", type=float, default=1.5, dest="serve_seconds",
+                    help="default workload: seconds of arrivals per serve load point")
+    ap.add_argument("--no-extras", action="store_true", dest="no_extras",
+                    help="default workload: skip the batched and serve objects")
     ap.add_argument("--nq", type=int, default=10_000, help="batched: patterns on the one text")
     ap.add_argument("--ntexts", type=int, default=4096, help="batched: texts with one pattern each")
-    ap.add_argument("--oracle-samples", type=int, default=4, dest="oracle_samples",
-                    help="accepted for compatibility; full-size oracle parity lives in tests/")
     ap.add_argument("--n", type=int, default=1 << 30, help="text bytes (default 1 GiB)")
     ap.add_argument("--per-m", type=int, default=100, dest="per_m")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, dest="cpu_seconds",

@@ -112,8 +112,14 @@ def test_continuous_batching_admits_while_busy():
 def test_report_memory_admission_and_rejection():
     t = np.frombuffer(b"a" * 1000, dtype=np.uint8)
     ex = FakeExecutor([t], nslots=2, delay=1)
+    seen = {}
+
+    def consume(r):  # positions are checked while the server still holds their reservation
+        assert srv.reserved >= 8 * r.count
+        seen[r.rid] = np.asarray(r.positions, dtype=np.uint64).copy()
+
     # budget fits one report of "a" (1000 positions = 8000 B) but not two at once
-    srv = Server(ex, hbm_budget=10_000)
+    srv = Server(ex, hbm_budget=10_000, on_done=consume)
     r1 = srv.submit(0, b"a", report=True)
     r2 = srv.submit(0, b"a", report=True)
     r3 = srv.submit(0, b"aa", report=True)  # 999 positions
@@ -122,10 +128,83 @@ def test_report_memory_admission_and_rejection():
     srv.drain()
     big.drain()
     for r in (r1, r2, r3):
-        assert r.status == "done"
-        assert np.array_equal(np.asarray(r.positions, dtype=np.uint64), oracle.report(r.pattern, t))
-    assert srv.peak_reserved <= 10_000
+        assert r.status == "done" and r.positions is None      # consumed and dropped
+        assert np.array_equal(seen[r.rid], oracle.report(r.pattern, t))
+    assert srv.peak_reserved <= 10_000 and srv.reserved == 0
     assert r4.status == "rejected" and "budget" in r4.error
+
+
+def test_report_reservation_held_until_released():
+    """Without on_done the positions stay with the request and keep their reservation until the
+    caller releases them; a report that does not fit waits for that."""
+    t = np.frombuffer(b"ab" * 500, dtype=np.uint8)
+    ex = FakeExecutor([t], nslots=2, delay=0)
+    srv = Server(ex, hbm_budget=6_000)                # one list of 500 positions (4000 B) at a time
+    r1 = srv.submit(0, b"ab", report=True)
+    r2 = srv.submit(0, b"ba", report=True)            # 499 positions
+    for _ in range(20):
+        srv.step()
+    assert r1.status == "done" and r2.status == "waiting_memory"
+    assert srv.reserved == 8 * r1.count
+    assert np.array_equal(np.asarray(r1.positions, dtype=np.uint64), oracle.report(b"ab", t))
+    srv.release(r1)
+    assert r1.positions is None
+    srv.drain()
+    assert r2.status == "done" and srv.reserved == 8 * r2.count
+    srv.release(r2)
+    srv.release(r2)                                   # a second release is a no-op
+    assert srv.reserved == 0
+
+
+class CostedExecutor(FakeExecutor):
+    """FakeExecutor with the GPU executor's cost model and per-text (GiB, alphabet class)."""
+
+    def __init__(self, texts, gib, cls=95, **kw):
+        super().__init__(texts, **kw)
+        from paper_1612_01506_amd.serve import CostModel
+        self.cost_model = CostModel()
+        self.gib = gib
+        self.cls = cls
+
+    def text_info(self, tid):
+        return self.gib[tid], self.cls
+
+
+def test_batches_bounded_by_device_time():
+    """A burst is split into batches whose modelled device time stays within the budget, counts and
+    reports alike; a request whose cost alone exceeds it still runs, alone."""
+    from paper_1612_01506_amd.serve import CostModel
+    texts = make_texts()
+    # pretend text 0 is 1 GiB and text 1 is 64 GiB: a byte-tile query on the 1 GiB text costs
+    # 175 + 80 us, a bitmap query 13.5 us; one query on the 64 GiB text exceeds a 10 ms budget
+    ex = CostedExecutor(texts, gib=[1.0, 64.0, 1.0, 1.0], nslots=1, delay=0)
+    budget = 10_000.0
+    srv = Server(ex, batch_budget_us=budget, adaptive=False)
+    g = np.random.default_rng(7)
+    reqs = [srv.submit(0, synth.substring_pattern(texts[0], 8, g)[0]) for _ in range(3000)]
+    huge = srv.submit(1, b"ab")
+    rep = [srv.submit(2, synth.substring_pattern(texts[2], 4, g)[0], report=True) for _ in range(200)]
+    srv.drain()
+    assert all(r.status == "done" for r in reqs + [huge] + rep)
+    for r in reqs[::97] + rep[::17]:
+        assert r.count == oracle.count(r.pattern, texts[r.text_id])
+    m = CostModel()
+    costs = srv.batch_costs_us
+    over = [c for c in costs if c > budget]
+    assert len(over) == 1 and abs(over[0] - m.text_cost(64.0, 95, 1)) < 1e-6   # the huge one, alone
+    assert len(srv.batch_sizes) >= 5 and max(srv.batch_sizes) < 3000
+    # bitmap-mode batches hold about (budget - builds) / 13.5 queries of the 1 GiB text
+    assert max(srv.batch_sizes) > 600
+    assert len(ex.report_batches) >= 2                                        # 200 reports > one batch
+
+
+def test_no_budget_admits_everything_queued():
+    texts = make_texts()
+    ex = CostedExecutor(texts, gib=[64.0] * 4, nslots=1, delay=0)
+    srv = Server(ex, batch_budget_us=None)
+    reqs = [srv.submit(k % 4, b"ab") for k in range(50)]
+    srv.drain()
+    assert srv.batch_sizes == [50] and all(r.status == "done" for r in reqs)
 
 
 def test_failures_stay_confined():
@@ -159,3 +238,39 @@ def test_reports_share_one_batch():
     assert ex.report_batches == [10]
     for r in reqs:
         assert np.array_equal(np.asarray(r.positions, dtype=np.uint64), oracle.report(r.pattern, texts[r.text_id]))
+
+
+def test_prefix_reaches_the_cheaper_bitmap_mode():
+    """On a 1 GiB binary text 21 byte-tile queries already exceed 10 ms, while 32 or more share a
+    bitmap pass for about 3 ms: the batch takes the longest prefix that fits, past the bump."""
+    from paper_1612_01506_amd.serve import CostModel
+    texts = make_texts()
+    ex = CostedExecutor(texts, gib=[1.0] * 4, cls=2, nslots=1, delay=0)
+    srv = Server(ex, batch_budget_us=10_000.0, adaptive=False)
+    reqs = [srv.submit(3, b"AC") for _ in range(400)]
+    srv.step()
+    m = CostModel()
+    k = max(k for k in range(1, 401) if m.text_cost(1.0, 2, k) <= 10_000.0)
+    assert k >= 100 and m.text_cost(1.0, 2, 21) > 10_000.0
+    assert srv.batch_sizes == [k] and srv.batch_costs_us[0] <= 10_000.0
+    srv.drain()
+    assert all(r.status == "done" and r.count == oracle.count(b"AC", texts[3]) for r in reqs)
+
+
+def test_adaptive_budget_grows_with_the_wait():
+    """With adaptive admission a batch may take as much modelled device time as its oldest request
+    has waited: fresh requests get the budget, a backlog that waited 50 ms gets about 50 ms."""
+    texts = make_texts()
+    now = [0.0]
+    ex = CostedExecutor(texts, gib=[1.0] * 4, nslots=1, delay=0)
+    srv = Server(ex, batch_budget_us=10_000.0, clock=lambda: now[0])
+    fresh = [srv.submit(k % 4, b"ab") for k in range(400)]
+    srv.step()
+    assert srv.batch_costs_us[-1] <= 10_000.0
+    srv.drain()
+    late = [srv.submit(k % 4, b"ab", t_submit=0.0) for k in range(4000)]
+    now[0] = 0.05                                     # the backlog has waited 50 ms
+    srv.step()
+    assert 10_000.0 < srv.batch_costs_us[-1] <= 50_000.0
+    srv.drain()
+    assert all(r.status == "done" for r in fresh + late)
