@@ -234,9 +234,12 @@ def run_zipf(args):
         del t_dev, posbuf, totals_dev
         state.clear()
         torch.cuda.empty_cache()
+        from paper_1612_01506_amd import autotune
+        bt = autotune.batch_tune() or {}
         extras["batched"] = {
             "one_text": batched_one_text(args, args.nq, 2),
             "many_texts": batched_many_texts(args, args.ntexts, 3),
+            "tuning": {k: v for k, v in bt.items() if k != "timings_us"} or "library defaults",
         }
         points, info = serve_points(args, args.serve_rates, args.serve_seconds, args.max_requests)
         extras["serve"] = dict(info, points=points)

@@ -69,11 +69,28 @@ extern "C" {
 
 /* Launch tuning and mode.  Any tuning field 0 selects the library default;
  * none of them changes a result. */
+/* Launch tuning of batched calls, per alphabet class of a text: class 0 = at most 2 distinct
+ * symbols in its histogram, 1 = at most 4, 2 = at most 32, 3 = more.  0 everywhere = the default.
+ * None of these changes a result. */
+typedef struct sm_batch_tune {
+    int32_t bm_min[4];   /* queries of a text (with a histogram) from which it runs in bitmap mode; default 32 */
+    int32_t bm_chunk[4]; /* queries per bitmap work item, 64..1024 (the LDS may hold fewer); default 1024 */
+    int32_t peel[4];     /* peel r of batched queries, 1..8; default: from the frequency model */
+    int32_t tile_kib;    /* byte-tile batches: 4, 8 or 16 KiB tiles; default 8                       */
+    int32_t wgs_per_cu;  /* byte-tile batches, chunks of several queries: 1..32; default 8           */
+    int32_t deal_wgs_per_cu; /* byte-tile batches, single-query chunks (deals): 1..64; default 16    */
+    int32_t pad;
+} sm_batch_tune;
+
+/* Launch parameters (NULL, or 0 in a field = the default).  Values outside the ranges below are
+ * rejected with SM_EINVAL.  None of them changes a result. */
 typedef struct sm_params {
     int32_t peel;       /* r: compares done before the first zero test, 1..8 (Section 2.3); default 2 */
     int32_t tile_kib;   /* text bytes staged per workgroup tile: 4, 8 or 16 KiB; default by n      */
     int32_t wgs_per_cu; /* workgroups per compute unit the grid is sized for, 1..32; default 6 (8 for batched byte tiles) */
     int32_t flags;      /* 0 or SM_NONOVERLAP; other bits are rejected (SM_EINVAL)                 */
+    const sm_batch_tune *batch; /* batched calls: per-class tuning, or NULL; peel, tile_kib and
+                                   wgs_per_cu above, when given, take precedence over it         */
 } sm_params;
 
 /* ---------------------------------------------------------------- info */

@@ -23,7 +23,7 @@ import numpy as np
 import torch
 
 from ._lib import (SM_NONOVERLAP, SM_ORDER_FREQ, SM_ORDER_H, SM_ORDER_HS, SM_ORDER_LTR, SmError, check, load,
-                   sm_params, sm_query, sm_text)
+                   sm_batch_tune, sm_params, sm_query, sm_text)
 
 __all__ = ["Text", "PackedTexts", "Patterns", "SmError", "histogram", "order", "count", "count_async", "report",
            "report_async", "count_batch", "report_batch", "BatchPlan", "bigram", "version", "device_cus"]
@@ -66,6 +66,34 @@ def _stream(stream) -> int | None:
     if isinstance(stream, torch.cuda.Stream):
         return stream.cuda_stream
     return int(stream)
+
+
+def _batch_params(peel=None, tile_kib=None, wgs_per_cu=None, tune=True):
+    """sm_params for a batched call: explicit values, else the tuning table's batch section for
+    this device (tune=True) or the given dict of the same form (bm_min, bm_chunk, peel: four
+    values per alphabet class; tile_kib, wgs_per_cu, deal_wgs_per_cu), passed as an
+    sm_batch_tune record, else the library's defaults."""
+    if peel is not None or tile_kib is not None or wgs_per_cu is not None or tune is False or tune is None:
+        return _params(peel, tile_kib, wgs_per_cu)
+    if isinstance(tune, dict):
+        bt = {"bm_min": [0] * 4, "bm_chunk": [0] * 4, "peel": [0] * 4, **tune}
+    else:
+        from . import autotune
+        bt = autotune.batch_tune()
+        if bt is None:
+            return None
+    rec = sm_batch_tune()
+    for c in range(4):
+        rec.bm_min[c] = int(bt["bm_min"][c])
+        rec.bm_chunk[c] = int(bt["bm_chunk"][c])
+        rec.peel[c] = int(bt["peel"][c])
+    rec.tile_kib = int(bt.get("tile_kib", 0))
+    rec.wgs_per_cu = int(bt.get("wgs_per_cu", 0))
+    rec.deal_wgs_per_cu = int(bt.get("deal_wgs_per_cu", 0))
+    p = sm_params(0, 0, 0, 0)
+    p.batch = ctypes.pointer(rec)
+    p._keep = rec
+    return ctypes.byref(p)
 
 
 def _params(peel=None, tile_kib=None, wgs_per_cu=None, text=None, m=None, overlap: bool = True):
@@ -328,25 +356,27 @@ def _marshal_batch(texts, queries, use_hist: bool):
 
 
 def count_batch(texts: Sequence, queries: Iterable, peel=None, tile_kib=None, wgs_per_cu=None,
-                stream=None, use_hist: bool = True) -> torch.Tensor:
+                stream=None, use_hist: bool = True, tune: bool = True) -> torch.Tensor:
     """Counts of many (text_id, pattern[, order]) queries in one persistent launch (asynchronous).
 
     Returns a device int64 tensor with one count per query.  Queries without an
     explicit order use the frequency order when the text's histogram is known
     (texts given as Text objects and use_hist), else left to right.  Texts with
-    a histogram and at least 32 queries run in the bitmap mode.
+    a histogram and at least 32 queries (or the tuned threshold of their alphabet
+    class) run in the bitmap mode.  With no explicit peel / tile_kib / wgs_per_cu
+    and tune, the tuning table's batch section for this device is passed.
     """
     qarr, tarr, nt, nq, dev, keep = _marshal_batch(texts, queries, use_hist)
     out = torch.empty(max(nq, 1), dtype=torch.int64, device=dev or "cuda")
     check(load().sm_count_batch(qarr.ctypes.data_as(ctypes.POINTER(sm_query)), nq,
                                 tarr.ctypes.data_as(ctypes.POINTER(sm_text)), nt, out.data_ptr(),
-                                _params(peel, tile_kib, wgs_per_cu), _stream(stream)))
+                                _batch_params(peel, tile_kib, wgs_per_cu, tune), _stream(stream)))
     del keep
     return out[:nq]
 
 
 def report_batch(texts: Sequence, queries: Iterable, caps, peel=None, tile_kib=None, wgs_per_cu=None,
-                 stream=None, use_hist: bool = True):
+                 stream=None, use_hist: bool = True, tune: bool = True):
     """Ordered start positions of many (text_id, pattern[, order]) queries, one pass per text
     (asynchronous).  caps[i] bounds query i's list.  Returns (positions, totals): positions is one
     device int64 tensor holding query i's min(total_i, caps[i]) smallest starts at offset
@@ -360,7 +390,7 @@ def report_batch(texts: Sequence, queries: Iterable, caps, peel=None, tile_kib=N
     totals = torch.empty(max(nq, 1), dtype=torch.int64, device=dev)
     check(load().sm_report_batch(qarr.ctypes.data_as(ctypes.POINTER(sm_query)), nq,
                                  tarr.ctypes.data_as(ctypes.POINTER(sm_text)), nt, _ptr(caps), pos.data_ptr(),
-                                 totals.data_ptr(), _params(peel, tile_kib, wgs_per_cu), _stream(stream)))
+                                 totals.data_ptr(), _batch_params(peel, tile_kib, wgs_per_cu, tune), _stream(stream)))
     del keep
     return pos, totals[:nq]
 
@@ -374,7 +404,7 @@ class BatchPlan:
     """
 
     def __init__(self, texts: Sequence, queries: Iterable, peel=None, tile_kib=None, wgs_per_cu=None,
-                 use_hist: bool = True):
+                 use_hist: bool = True, tune: bool = True):
         qarr, tarr, nt, nq, dev, keep = _marshal_batch(texts, queries, use_hist)
         self.nq = nq
         self.device = torch.device(dev) if dev is not None else torch.device("cuda", torch.cuda.current_device())
@@ -382,7 +412,7 @@ class BatchPlan:
         h = ctypes.c_void_p()
         check(load().sm_batch_create(qarr.ctypes.data_as(ctypes.POINTER(sm_query)), nq,
                                      tarr.ctypes.data_as(ctypes.POINTER(sm_text)), nt,
-                                     _params(peel, tile_kib, wgs_per_cu), ctypes.byref(h)))
+                                     _batch_params(peel, tile_kib, wgs_per_cu, tune), ctypes.byref(h)))
         del keep
         self._h = h
 

@@ -32,9 +32,16 @@ class SmError(RuntimeError):
         self.code = code
 
 
+class sm_batch_tune(ctypes.Structure):
+    _fields_ = [("bm_min", ctypes.c_int32 * 4), ("bm_chunk", ctypes.c_int32 * 4), ("peel", ctypes.c_int32 * 4),
+                ("tile_kib", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32), ("deal_wgs_per_cu", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
+
+
 class sm_params(ctypes.Structure):
     _fields_ = [("peel", ctypes.c_int32), ("tile_kib", ctypes.c_int32),
-                ("wgs_per_cu", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("wgs_per_cu", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("batch", ctypes.POINTER(sm_batch_tune))]
 
 
 class sm_text(ctypes.Structure):

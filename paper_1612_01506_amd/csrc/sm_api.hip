@@ -523,15 +523,16 @@ struct Tune {
 Tune resolve(const sm_params *p, uint64_t m, uint64_t n)
 {
     Tune t;
-    t.r = (p && p->peel > 0) ? std::min<int>(p->peel, (int)kMaxPeel) : 2;
+    // p has passed check_flags: every field is 0 (default) or in range
+    t.r = (p && p->peel > 0) ? p->peel : 2;
     t.r = (int)std::min<uint64_t>((uint64_t)t.r, m);
-    if (p && (p->tile_kib == 4 || p->tile_kib == 8 || p->tile_kib == 16))
+    if (p && p->tile_kib > 0)
         t.cpl = p->tile_kib / 4;
     else
         t.cpl = n >= (8ull << 20) ? 2 : 1;  // 8 KiB tiles measured best on 1 GiB texts
     // 6 workgroups per CU: a full 8 (the occupancy limit) starts every CU's
     // workgroups in lock step and measured ~15% slower on 1 GiB texts.
-    t.wpc = (p && p->wgs_per_cu > 0) ? std::min(p->wgs_per_cu, 32) : 6;
+    t.wpc = (p && p->wgs_per_cu > 0) ? p->wgs_per_cu : 6;
     t.chunk_log2 = kChunkLog2;
     return t;
 }
@@ -830,10 +831,34 @@ int64_t nonoverlap_core(Dev &d, const TextView &tv, uint64_t m, const uint64_t *
     return (int64_t)d.hpin[1];
 }
 
-// Flags of sm_params: SM_NONOVERLAP only where `nonoverlap_ok`.
+// sm_params: every field in its documented range (0 = default), SM_NONOVERLAP only where
+// `nonoverlap_ok`.
 int check_flags(const sm_params *params, bool nonoverlap_ok)
 {
-    if (!params || params->flags == 0)
+    if (!params)
+        return SM_OK;
+    auto tile_ok = [](int32_t v) { return v == 0 || v == 4 || v == 8 || v == 16; };
+    if (params->peel < 0 || params->peel > (int32_t)kMaxPeel)
+        return fail(SM_EINVAL, "sm_params.peel must be 0 (default) or 1..8");
+    if (!tile_ok(params->tile_kib))
+        return fail(SM_EINVAL, "sm_params.tile_kib must be 0 (default), 4, 8 or 16");
+    if (params->wgs_per_cu < 0 || params->wgs_per_cu > 32)
+        return fail(SM_EINVAL, "sm_params.wgs_per_cu must be 0 (default) or 1..32");
+    if (const sm_batch_tune *b = params->batch) {
+        for (int c = 0; c < 4; ++c) {
+            if (b->bm_min[c] < 0)
+                return fail(SM_EINVAL, "sm_batch_tune.bm_min must be >= 0");
+            if (b->bm_chunk[c] != 0 && (b->bm_chunk[c] < 64 || b->bm_chunk[c] > (int32_t)kBmQChunk))
+                return fail(SM_EINVAL, "sm_batch_tune.bm_chunk must be 0 (default) or 64..1024");
+            if (b->peel[c] < 0 || b->peel[c] > (int32_t)kMaxPeel)
+                return fail(SM_EINVAL, "sm_batch_tune.peel must be 0 (default) or 1..8");
+        }
+        if (!tile_ok(b->tile_kib))
+            return fail(SM_EINVAL, "sm_batch_tune.tile_kib must be 0 (default), 4, 8 or 16");
+        if (b->wgs_per_cu < 0 || b->wgs_per_cu > 32 || b->deal_wgs_per_cu < 0 || b->deal_wgs_per_cu > 64)
+            return fail(SM_EINVAL, "sm_batch_tune workgroups per CU out of range");
+    }
+    if (params->flags == 0)
         return SM_OK;
     if (params->flags & ~(int32_t)SM_NONOVERLAP)
         return fail(SM_EINVAL, "unknown sm_params flags");
@@ -1166,17 +1191,36 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
     lp->nq = nq;
     if (rep)
         lp->steps_of.assign(nq, ~0ull);
-    const int cpl = (params && (params->tile_kib == 4 || params->tile_kib == 8 || params->tile_kib == 16))
-                        ? params->tile_kib / 4
-                        : 2;
+    // params has passed check_flags.  Explicit peel / tile / workgroups take precedence over the
+    // per-class batch tuning, which takes precedence over the defaults.
+    const sm_batch_tune *bt = params ? params->batch : nullptr;
+    const int cpl = (params && params->tile_kib > 0) ? params->tile_kib / 4 : (bt && bt->tile_kib > 0) ? bt->tile_kib / 4 : 2;
     const uint64_t T = 4096ull * cpl;
     const bool peel_given = params && params->peel > 0;
-    const int rdef = peel_given ? std::min<int>(params->peel, (int)kMaxPeel) : 2;
+    const int rdef = peel_given ? params->peel : 2;
     // workgroups per CU: the byte-tile batch kernel measured best at 8 (short per-query work per
     // tile needs more waves in flight); long queries run the single-search kernel, best at 6
     const bool wpc_given = params && params->wgs_per_cu > 0;
-    const int wpc = wpc_given ? std::min(params->wgs_per_cu, 32) : 8;
+    const int wpc = wpc_given ? params->wgs_per_cu : (bt && bt->wgs_per_cu > 0) ? bt->wgs_per_cu : 8;
     const int wpc_long = wpc_given ? wpc : 6;
+    const uint64_t deal_wpc = wpc_given ? (uint64_t)wpc : (bt && bt->deal_wgs_per_cu > 0) ? (uint64_t)bt->deal_wgs_per_cu
+                                                                                             : kDealsPerCu;
+    // alphabet class of a text with a histogram (symbols with a nonzero entry: <= 2, <= 4, <= 32, more)
+    std::vector<uint8_t> text_cls(nt, 3);
+    for (uint64_t t = 0; t < nt; ++t) {
+        if (!texts[t].hist)
+            continue;
+        int nsym = 0;
+        for (int b = 0; b < 256; ++b)
+            nsym += texts[t].hist[b] != 0;
+        text_cls[t] = nsym <= 2 ? 0 : nsym <= 4 ? 1 : nsym <= 32 ? 2 : 3;
+    }
+    auto bm_min_of = [&](uint64_t t) -> uint64_t {
+        return (bt && bt->bm_min[text_cls[t]] > 0) ? (uint64_t)bt->bm_min[text_cls[t]] : kBmMinQueries;
+    };
+    auto bm_chunk_of = [&](uint64_t t) -> uint32_t {
+        return (bt && bt->bm_chunk[text_cls[t]] > 0) ? (uint32_t)bt->bm_chunk[text_cls[t]] : kBmQChunk;
+    };
     const uint64_t target = (uint64_t)std::max(d.cus, 1) * (uint64_t)wpc;
     // two LDS tile buffers of T + halo and the query counters must fit
     const uint64_t max_halo = (kMaxLds - kQChunk * sizeof(uint32_t)) / 2 - T;
@@ -1202,7 +1246,7 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
     std::vector<std::vector<uint8_t>> smaps(nt);
     std::vector<uint32_t> nslots(nt, 0);
     for (uint64_t t = 0; t < nt; ++t)
-        if (nbm[t] >= kBmMinQueries)
+        if (nbm[t] >= bm_min_of(t))
             smaps[t].assign(256, 0);
     for (uint64_t i = 0; i < nq; ++i) {
         const uint32_t t = q[i].text_id;
@@ -1230,7 +1274,7 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
     std::vector<uint32_t> smap_slot(nt, 0);
     uint32_t n_smaps = 0;
     for (uint64_t t = 0; t < nt; ++t) {
-        text_bm[t] = !rep && !smaps[t].empty() && nbm[t] >= kBmMinQueries;  // reports need byte tiles
+        text_bm[t] = !rep && !smaps[t].empty() && nbm[t] >= bm_min_of(t);  // reports need byte tiles
         if (text_bm[t])
             smap_slot[t] = n_smaps++;
     }
@@ -1303,7 +1347,7 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
     };
     const std::vector<Chunk> chunks = make_chunks(staged, [](const PlanQuery &) { return kQChunk; });
     const std::vector<Chunk> bchunks = make_chunks(bmq, [&](const PlanQuery &pq) {
-        return (uint32_t)bm_cap(nslots[pq.text], bm_wps(pq.bucket));
+        return (uint32_t)std::min<uint64_t>(bm_cap(nslots[pq.text], bm_wps(pq.bucket)), bm_chunk_of(pq.text));
     });
 
     // ---- single-query chunks of counting batches go to deals of up to 2^kChunkLog2 tiles (one
@@ -1489,6 +1533,8 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
         const uint64_t *h = texts[Q.text_id].hist;
         if (peel_given || !h)
             return (uint32_t)std::min<uint64_t>((uint64_t)rdef, Q.m);
+        if (bt && bt->peel[text_cls[Q.text_id]] > 0)
+            return (uint32_t)std::min<uint64_t>((uint64_t)bt->peel[text_cls[Q.text_id]], Q.m);
         return model_peel(Q.p, Q.m, o, h, hsum[Q.text_id], W);
     };
     auto fill = [&](size_t k, Scratch &w) {
@@ -1601,7 +1647,7 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
     // round robin, let the ones that finish early take over the rest (measured 0.58 -> 0.51 ms on
     // 4,096 texts of 4 KiB - 4 MiB)
     lp->deal_grid = std::max<uint64_t>(
-        1, std::min<uint64_t>(solo.size(), (uint64_t)std::max(d.cus, 1) * (wpc_given ? (uint64_t)wpc : kDealsPerCu)));
+        1, std::min<uint64_t>(solo.size(), (uint64_t)std::max(d.cus, 1) * deal_wpc));
     lp->deal_stream = deal_bytes >= kStreamLoadBytes;
     for (size_t i = 0; i < longq.size(); ++i) {
         const PlanQuery &pq = longq[i];
@@ -1703,7 +1749,7 @@ int check_set(const sm_patterns *ps, uint64_t i)
 
 extern "C" {
 
-int32_t sm_version(void) { return 10000; }
+int32_t sm_version(void) { return 10100; }
 
 const char *sm_last_error(void) { return g_err.c_str(); }
 

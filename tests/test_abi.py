@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_version():
-    assert sm.version() == 10000
+    assert sm.version() == 10100
 
 
 def _err(rc):
@@ -66,6 +66,25 @@ def test_validation_before_any_device_call():
     assert lib.sm_batch_create(None, 0, None, 0, None, None) == _lib.SM_EINVAL
     assert "NULL" in _err(lib.sm_batch_run(None, None, None))
     assert lib.sm_batch_destroy(None) == _lib.SM_OK
+    # sm_params fields out of range are rejected, never replaced by defaults
+    for fields, word in (((0, 32, 0, 0), "tile_kib"), ((0, 3, 0, 0), "tile_kib"), ((9, 0, 0, 0), "peel"),
+                         ((-1, 0, 0, 0), "peel"), ((0, 0, 33, 0), "wgs_per_cu"), ((0, 0, -2, 0), "wgs_per_cu")):
+        bad = _lib.sm_params(*fields)
+        assert word in _err(lib.sm_count_ex(p.ctypes.data, 3, None, 0, None, ctypes.byref(bad), None)), fields
+    for field, val in (("bm_chunk", 32), ("bm_chunk", 2048), ("peel", 9), ("bm_min", -1)):
+        bt = _lib.sm_batch_tune()
+        getattr(bt, field)[2] = val
+        bad = _lib.sm_params(0, 0, 0, 0)
+        bad.batch = ctypes.pointer(bt)
+        assert "sm_batch_tune" in _err(lib.sm_count_ex(p.ctypes.data, 3, None, 0, None, ctypes.byref(bad), None))
+    for field, val in (("tile_kib", 12), ("deal_wgs_per_cu", 65), ("wgs_per_cu", 40)):
+        bt = _lib.sm_batch_tune()
+        setattr(bt, field, val)
+        bad = _lib.sm_params(0, 0, 0, 0)
+        bad.batch = ctypes.pointer(bt)
+        assert "sm_batch_tune" in _err(lib.sm_count_ex(p.ctypes.data, 3, None, 0, None, ctypes.byref(bad), None))
+    good = _lib.sm_params(8, 16, 32, 0)
+    assert lib.sm_count_ex(p.ctypes.data, 3, None, 0, None, ctypes.byref(good), None) == 0
     # sm_params.flags: unknown bits everywhere, SM_NONOVERLAP outside the synchronous calls
     bad_flags = _lib.sm_params(0, 0, 0, 2)
     assert "flags" in _err(lib.sm_count_ex(p.ctypes.data, 3, None, 0, None, ctypes.byref(bad_flags), None))

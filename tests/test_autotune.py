@@ -49,3 +49,35 @@ def test_params_for_reads_the_device_table(monkeypatch):
     assert got == {"tile_kib": e["tile_kib"], "wgs_per_cu": e["wgs_per_cu"], "peel": e["peel"]}
     monkeypatch.setattr(autotune, "_device_key", lambda: ("gfx000", "test"))   # no table for this device
     assert autotune.params_for(h, 100, 1 << 30) is None
+
+
+def test_committed_batch_section_is_complete_and_its_choices_are_the_fastest():
+    b = json.load(open(TABLE))["batch"]
+    tm = b["timings_us"]
+    for ci, c in enumerate(autotune.CLASSES):
+        # bitmap threshold: the first tried query count at which the bitmap mode was not slower
+        ks = [k for k in autotune.BM_KS if tm[f"{c}/threshold/{k}"]["bitmap"] <= tm[f"{c}/threshold/{k}"]["byte_tiles"]]
+        assert b["bm_min"][ci] == (ks[0] if ks else 2 * autotune.BM_KS[-1])
+        chunk = tm[f"{c}/chunk"]
+        assert b["bm_chunk"][ci] == int(min(chunk, key=chunk.get))
+        peel = tm[f"{c}/peel"]
+        assert b["peel"][ci] == int(min(peel, key=peel.get)) and 0 <= b["peel"][ci] <= 8
+    deals = tm["deals"]
+    assert f"{b['tile_kib']}/{b['deal_wgs_per_cu']}" == min(deals, key=deals.get)
+    chunks = tm["chunks"]
+    assert f"{b['tile_kib']}/{b['wgs_per_cu']}" == min(chunks, key=chunks.get)
+
+
+def test_batch_params_record(monkeypatch):
+    """The binding turns the table's batch section into the sm_batch_tune record it passes."""
+    import paper_1612_01506_amd as sm
+    monkeypatch.setattr(autotune, "_device_key", lambda: ("gfx950", "test"))
+    monkeypatch.setattr(autotune, "_table_key", None)
+    b = json.load(open(TABLE))["batch"]
+    p = sm._batch_params()._obj          # the sm_params behind the byref handed to the library
+    rec = p.batch.contents
+    assert list(rec.bm_min) == b["bm_min"] and list(rec.bm_chunk) == b["bm_chunk"] and list(rec.peel) == b["peel"]
+    assert (rec.tile_kib, rec.wgs_per_cu, rec.deal_wgs_per_cu) == (b["tile_kib"], b["wgs_per_cu"], b["deal_wgs_per_cu"])
+    assert sm._batch_params(peel=3) is not None and sm._batch_params(tune=False) is None
+    custom = sm._batch_params(tune={"bm_min": [1] * 4})._obj
+    assert list(custom.batch.contents.bm_min) == [1] * 4 and list(custom.batch.contents.peel) == [0] * 4
