@@ -22,12 +22,18 @@
 //   * popcount(found) counts exactly-zero bytes:
 //     ~(((d & 0x7F..7F) + 0x7F..7F) | d | 0x7F..7F) has 0x80 in each zero byte.
 //   * Text tiles (4, 8 or 16 KiB) plus an (m + 4)-byte halo are staged in LDS
-//     with coalesced 16-byte loads; the next tile is prefetched into VGPRs
-//     while the current one is searched.  Each workgroup owns a contiguous
-//     range of tiles, so a halo is the start of the tile it loads next (an L2
-//     hit, not a second HBM read).
-//   * Counts: per-lane 64-bit accumulators, a wave shuffle reduction, one LDS
+//     by DMA (global_load_lds_dwordx4) into two buffers: the next tile's loads
+//     are in flight while the current one is searched.  Tiles are dealt to
+//     workgroups in chunks of contiguous tiles, so a halo is mostly the start
+//     of the tile the same workgroup loads next (an L2 hit, not a second HBM
+//     read).  Texts far larger than the last-level cache are read with the
+//     non-temporal policy.
+//   * Counts: 32-bit lane accumulators, DPP wave reductions, one LDS
 //     reduction and one 64-bit atomicAdd per workgroup.
+//   * Batches: byte-tile kernels run many queries over one staged tile (or one
+//     query over runs of tiles, with a record per run), and the bitmap kernel
+//     turns every compare of every query into a funnel shift and AND over
+//     per-tile symbol bitmaps (one SIMDcompare per symbol and tile, shared).
 #include "sm_internal.h"
 
 namespace smk {
@@ -411,45 +417,6 @@ __device__ __forceinline__ void search_known(const uint64_t *steps, uint32_t m, 
 }
 
 // ------------------------------------------------------------- tile staging
-
-template <int CPL>
-__device__ __forceinline__ void fetch_tile(const TextView &tv, uint64_t ts, uint32_t tid, uint32_t hch,
-                                           uint4 (&pre)[CPL], uint4 &hpre)
-{
-    constexpr uint32_t T = kWG * 16u * CPL;
-#pragma unroll
-    for (int c = 0; c < CPL; ++c) {
-        const uint64_t u = ts + 16ull * (tid + kWG * c);
-        pre[c] = u < tv.end16 ? *reinterpret_cast<const uint4 *>(tv.base + u) : make_uint4(0, 0, 0, 0);
-    }
-    if (tid < hch) {
-        const uint64_t u = ts + T + 16ull * tid;
-        hpre = u < tv.end16 ? *reinterpret_cast<const uint4 *>(tv.base + u) : make_uint4(0, 0, 0, 0);
-    }
-}
-
-template <int CPL>
-__device__ __forceinline__ void put_tile(uint8_t *lds, uint32_t tid, uint32_t hch, const uint4 (&pre)[CPL],
-                                         const uint4 &hpre)
-{
-    constexpr uint32_t T = kWG * 16u * CPL;
-#pragma unroll
-    for (int c = 0; c < CPL; ++c)
-        *reinterpret_cast<uint4 *>(lds + 16u * (tid + kWG * c)) = pre[c];
-    if (tid < hch)
-        *reinterpret_cast<uint4 *>(lds + T + 16u * tid) = hpre;
-}
-
-// Halo chunks past the first kWG are loaded synchronously (long patterns only).
-__device__ __forceinline__ void put_halo_rest(uint8_t *halo_lds, const TextView &tv, uint64_t hs, uint32_t tid,
-                                              uint32_t hch)
-{
-    for (uint32_t ch = kWG + tid; ch < hch; ch += kWG) {
-        const uint64_t u = hs + 16ull * ch;
-        const uint4 v = u < tv.end16 ? *reinterpret_cast<const uint4 *>(tv.base + u) : make_uint4(0, 0, 0, 0);
-        *reinterpret_cast<uint4 *>(halo_lds + 16u * ch) = v;
-    }
-}
 
 __device__ __forceinline__ void wg_add_count(unsigned long long acc, unsigned long long *dst, uint32_t tid)
 {
