@@ -1,9 +1,11 @@
 """Parity at the benchmark workloads' full sizes, in the launch configurations bench.py times.
 
-Outputs the oracle can compute one by one are sampled (a pattern per length, a few
-batch queries); the rest are checked through properties that hold at any size
-(batched == single searches, count == report length, closed forms, order and
-peel invariance).
+Outputs the oracle can compute one by one are compared with it: every count of the
+1 GiB Zipf step and 50 of its lists, 100 batched queries spanning the length range
+on the 2 GiB text, every count of the 4,096-text batch, and a sample of served
+counts and lists at the serving workload's size.  The rest are checked through
+properties that hold at any size (batched == single searches, count == report
+length, closed forms, order and peel invariance).
 """
 import numpy as np
 import pytest
@@ -60,15 +62,16 @@ def test_zipf_1gib_bench_configuration(dev):
     assert (counts >= 1).all()                      # every pattern is a substring of the text
     for k, i in enumerate(rep):
         assert tot[k] == counts[i]
-    for i in range(0, len(patterns), 100):          # one pattern per length against the oracle
-        assert counts[i] == oracle.count(patterns[i], t), len(patterns[i])
+    want_all = [oracle.count(p, t) for p in patterns]   # every count against the oracle (~1 min of host time)
+    bad = [(len(patterns[i]), counts[i], want_all[i]) for i in range(len(patterns)) if counts[i] != want_all[i]]
+    assert not bad, bad[:5]
     # the default launch (no tuning table: 8 KiB tiles, 6 workgroups per CU) gives the same counts
     plain = torch.zeros(len(patterns), dtype=torch.int64, device=dev)
     for i in range(len(patterns)):
         ps.count_async(i, td, plain[i:i + 1])
     torch.cuda.synchronize()
     assert plain.cpu().numpy().tolist() == counts.tolist()
-    for k in range(0, len(rep), 100):                # one reported list per length against the oracle
+    for k in range(0, len(rep), 10):                 # 50 reported lists (10 per length) against the oracle
         want = oracle.report(patterns[rep[k]], t)
         got = pos[k, :min(int(tot[k]), cap)].cpu().numpy().astype(np.uint64)
         assert got.tolist() == want[:cap].tolist(), len(patterns[rep[k]])
@@ -76,15 +79,25 @@ def test_zipf_1gib_bench_configuration(dev):
 
 
 def test_batched_one_text_2gib(dev):
-    """10,000 patterns on a 2 GiB Zipf text in one launch (bitmap mode)."""
+    """10,000 patterns on a 2 GiB Zipf text in one launch (bitmap mode): 200 counts against single
+    searches, and 100 against the oracle -- 10 per decade-spaced length band over [2, 1024], each
+    band half substrings (even indices) and half random patterns (odd)."""
     t, pats = synth.batched_one_text_workload()
     text = sm.Text(torch.from_numpy(t).to(dev))
     got = sm.count_batch([text], [(0, p) for p in pats]).cpu().numpy()
     g = np.random.default_rng(5)
     for i in g.choice(len(pats), size=200, replace=False):   # batched == single searches
         assert got[i] == sm.count(text, pats[i]), i
-    for i in g.choice(len(pats), size=4, replace=False):     # and the oracle on a few
-        assert got[i] == oracle.count(pats[i], t), i
+    edges = np.geomspace(2, 1025, 11)
+    picked = []
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        band = [i for i in range(len(pats)) if lo <= len(pats[i]) < hi]
+        for parity in (0, 1):
+            idx = [i for i in band if i % 2 == parity]
+            picked += list(g.choice(idx, size=min(5, len(idx)), replace=False))
+    assert len(picked) >= 100 and min(len(pats[i]) for i in picked) <= 3 and max(len(pats[i]) for i in picked) >= 700
+    for i in picked:
+        assert got[i] == oracle.count(pats[i], t), (i, len(pats[i]))
 
 
 def test_batched_many_texts(dev):
@@ -167,3 +180,47 @@ def test_report_batch_over_512mib(dev):
         assert totals[i] == total, (i, len(p))
         assert pos[off:off + min(total, cap)].tolist() == want.tolist(), (i, len(p))
         off += cap
+
+
+def test_serving_8_texts_of_1gib_against_oracle(dev):
+    """The serving workload's shape (8 resident 1 GiB texts of 2-95 symbols, m log-uniform in
+    [2, 512], half substrings, 5% reports): requests submitted in bursts while batches are in
+    flight; a sample of the served counts and every served list of moderate length against the
+    oracle."""
+    from paper_1612_01506_amd.serve import GpuExecutor, Server
+    n = 1 << 30
+    mixes = [("uniform", 2), ("uniform", 4), ("zipf", 4), ("uniform", 20), ("zipf", 20), ("uniform", 95),
+             ("zipf", 95), ("zipf", 95)]
+    texts_h = [synth.zipf_text(n, s_, 1.0, family=5, stream=i) if kind == "zipf" else
+               synth.uniform_text(n, s_, family=5, stream=i) for i, (kind, s_) in enumerate(mixes)]
+    ex = GpuExecutor([torch.from_numpy(x).to(dev) for x in texts_h], nstreams=2)
+    seen = {}
+
+    def consume(r):
+        if r.report and r.count <= 100_000:
+            pos = r.positions.cpu().numpy() if isinstance(r.positions, torch.Tensor) else np.asarray(r.positions)
+            seen[r.rid] = pos.astype(np.uint64)
+
+    srv = Server(ex, hbm_budget=1 << 28, on_done=consume)
+    g = synth.rng(5, 777)
+    alphabets = [bytes(np.unique(x[:1 << 20])) for x in texts_h]
+    reqs = []
+    for k in range(600):
+        ti = int(g.integers(0, 8))
+        m = int(synth.loguniform_ints(2, 512, 1, g)[0])
+        p = synth.substring_pattern(texts_h[ti], m, g)[0] if k % 2 else synth.random_pattern(alphabets[ti], m, g)
+        reqs.append(srv.submit(ti, p, report=bool(g.random() < 0.05)))
+        if k % 37 == 0:
+            srv.step()
+    srv.drain()
+    assert all(r.status in ("done", "rejected") for r in reqs)
+    done = [r for r in reqs if r.status == "done"]
+    assert len(done) >= 590
+    for r in done[::10]:
+        assert r.count == oracle.count(r.pattern, texts_h[r.text_id]), (r.text_id, len(r.pattern))
+    assert len(seen) >= 5
+    for rid, pos in seen.items():
+        r = reqs[rid]
+        assert pos.tolist() == oracle.report(r.pattern, texts_h[r.text_id]).tolist(), (r.text_id, len(r.pattern))
+    del ex
+    torch.cuda.empty_cache()
