@@ -559,6 +559,12 @@ def run_small(args):
         t_host, pats = synth.small_alphabet_workload(n=n, sigma=sigma)
         t_dev = torch.from_numpy(t_host).to(dev)
         text = sm.Text(t_dev)
+        if args.copy_probe and sigma == 2:
+            # plain copy of known size (n bytes read, n written) for scaling the HBM counters
+            dst = torch.empty_like(t_dev)
+            dst.copy_(t_dev)
+            torch.cuda.synchronize()
+            del dst
         res = {}
         per_peel = []
         # peel 2 and 5 (the paper's values for large and DNA alphabets) as given, then the launch
