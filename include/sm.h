@@ -67,6 +67,17 @@ extern "C" {
  * occurrences is rejected (SM_EINVAL) and scratch exhaustion gives SM_ENOMEM. */
 #define SM_NONOVERLAP 1
 
+/* Count calls (sm_count, sm_count_ex, sm_count_async, sm_patterns_count): compare through per-tile
+ * symbol bitmaps when the pattern has at most 4 distinct symbols.  Section 2.1's SIMDcompare of a
+ * symbol against every start of a tile is done once per tile and symbol, as one bit per text
+ * byte, and each compare of pattern position j is then a shift of those bits by j and an AND over
+ * 32 starts.  Faster where compares per start are many (texts over 2 or 3 symbols); the count is
+ * the same.  Patterns with more distinct symbols, report calls and batched calls ignore the flag.
+ * tile_kib then selects 8, 16 (default) or 32 KiB bitmap tiles; a pattern too long for the tile
+ * (its halo of (m - 1) / 32 + 1 words over half the tile) takes the next larger, and above 32 KiB
+ * the byte compares.  Also accepted by the calls that take SM_NONOVERLAP (there it is ignored). */
+#define SM_BITMAP 2
+
 /* Launch tuning and mode.  Any tuning field 0 selects the library default;
  * none of them changes a result. */
 /* Launch tuning of batched calls, per alphabet class of a text: class 0 = at most 2 distinct
@@ -86,9 +97,10 @@ typedef struct sm_batch_tune {
  * rejected with SM_EINVAL.  None of them changes a result. */
 typedef struct sm_params {
     int32_t peel;       /* r: compares done before the first zero test, 1..8 (Section 2.3); default 2 */
-    int32_t tile_kib;   /* text bytes staged per workgroup tile: 4, 8 or 16 KiB; default by n      */
+    int32_t tile_kib;   /* text bytes staged per workgroup tile: 4, 8 or 16 KiB; default by n;
+                           with SM_BITMAP 8, 16 or 32 KiB, default 16                             */
     int32_t wgs_per_cu; /* workgroups per compute unit the grid is sized for, 1..32; default 6 (8 for batched byte tiles) */
-    int32_t flags;      /* 0 or SM_NONOVERLAP; other bits are rejected (SM_EINVAL)                 */
+    int32_t flags;      /* SM_NONOVERLAP and/or SM_BITMAP; other bits are rejected (SM_EINVAL)    */
     const sm_batch_tune *batch; /* batched calls: per-class tuning, or NULL; peel, tile_kib and
                                    wgs_per_cu above, when given, take precedence over it         */
 } sm_params;

@@ -22,7 +22,7 @@ from typing import Iterable, Sequence
 import numpy as np
 import torch
 
-from ._lib import (SM_NONOVERLAP, SM_ORDER_FREQ, SM_ORDER_H, SM_ORDER_HS, SM_ORDER_LTR, SmError, check, load,
+from ._lib import (SM_BITMAP, SM_NONOVERLAP, SM_ORDER_FREQ, SM_ORDER_H, SM_ORDER_HS, SM_ORDER_LTR, SmError, check, load,
                    sm_batch_tune, sm_params, sm_query, sm_text)
 
 __all__ = ["Text", "PackedTexts", "Patterns", "SmError", "histogram", "order", "count", "count_async", "report",
@@ -96,17 +96,25 @@ def _batch_params(peel=None, tile_kib=None, wgs_per_cu=None, tune=True):
     return ctypes.byref(p)
 
 
-def _params(peel=None, tile_kib=None, wgs_per_cu=None, text=None, m=None, overlap: bool = True):
+def _params(peel=None, tile_kib=None, wgs_per_cu=None, text=None, m=None, overlap: bool = True, bitmap=None):
     """sm_params for a call; with no tuning given and a Text whose histogram is known, the
-    autotuner's table (if one exists for this device) supplies it.  overlap=False selects the
-    non-overlapping mode (SM_NONOVERLAP)."""
+    autotuner's table (if one exists for this device) supplies it, the compare mode included.
+    overlap=False selects the non-overlapping mode (SM_NONOVERLAP); bitmap=True / False asks for
+    or declines the bitmap compares of count calls (SM_BITMAP; None: the table's choice)."""
     flags = 0 if overlap else SM_NONOVERLAP
+    if bitmap:
+        flags |= SM_BITMAP
     if peel is None and tile_kib is None and wgs_per_cu is None:
         if isinstance(text, Text) and text._hist is not None and m:
             from . import autotune
             tp = autotune.params_for(text._hist, int(m), text.n)
             if tp:
-                return ctypes.byref(sm_params(tp["peel"], tp["tile_kib"], tp["wgs_per_cu"], flags))
+                cell_bm = bool(tp.get("bitmap"))
+                if bitmap is None and cell_bm:
+                    flags |= SM_BITMAP
+                # the cell's tile size is in the units of its own mode
+                tile = tp["tile_kib"] if cell_bm == bool(flags & SM_BITMAP) else 0
+                return ctypes.byref(sm_params(tp["peel"], tile, tp["wgs_per_cu"], flags))
         return ctypes.byref(sm_params(0, 0, 0, flags)) if flags else None
     return ctypes.byref(sm_params(int(peel or 0), int(tile_kib or 0), int(wgs_per_cu or 0), flags))
 
@@ -209,25 +217,30 @@ def _resolve_order(order_arg, p: np.ndarray, text) -> np.ndarray | None:
 
 
 # -------------------------------------------------------------------- searches
-def count(t, p, order=None, peel=None, tile_kib=None, wgs_per_cu=None, stream=None, overlap: bool = True) -> int:
+def count(t, p, order=None, peel=None, tile_kib=None, wgs_per_cu=None, stream=None, overlap: bool = True,
+          bitmap=None) -> int:
     """Number of occurrences of p in t; synchronous.  All starts are counted (overlapping
-    occurrences included); overlap=False counts disjoint occurrences taken greedily from the left."""
+    occurrences included); overlap=False counts disjoint occurrences taken greedily from the left.
+    bitmap=True compares through per-tile symbol bitmaps (patterns of at most 4 distinct symbols;
+    tile_kib is then 8, 16 or 32)."""
     a = _pat(p)
     ptr, n = _dev_text(t)
     o = _resolve_order(order, a, t)
     return check(load().sm_count_ex(_ptr(a), a.size, ptr, n, _ptr(o),
-                                    _params(peel, tile_kib, wgs_per_cu, t, a.size, overlap), _stream(stream)))
+                                    _params(peel, tile_kib, wgs_per_cu, t, a.size, overlap, bitmap),
+                                    _stream(stream)))
 
 
 def count_async(t, p, out: torch.Tensor, order=None, peel=None, tile_kib=None, wgs_per_cu=None,
-                stream=None) -> None:
+                stream=None, bitmap=None) -> None:
     """ADD the count of p in t to out[0] (device int64) without waiting."""
     a = _pat(p)
     ptr, n = _dev_text(t)
     if out.dtype != torch.int64 or not out.is_cuda:
         raise TypeError("out must be a CUDA int64 tensor")
     o = _resolve_order(order, a, t)
-    check(load().sm_count_async(_ptr(a), a.size, ptr, n, _ptr(o), _params(peel, tile_kib, wgs_per_cu, t, a.size),
+    check(load().sm_count_async(_ptr(a), a.size, ptr, n, _ptr(o),
+                                _params(peel, tile_kib, wgs_per_cu, t, a.size, bitmap=bitmap),
                                 out.data_ptr(), _stream(stream)))
 
 
@@ -492,10 +505,11 @@ class Patterns:
             pass
 
     def count_async(self, i: int, t, out: torch.Tensor, peel=None, tile_kib=None, wgs_per_cu=None,
-                    stream=None) -> None:
+                    stream=None, bitmap=None) -> None:
         """ADD the count of pattern i in t to out[0] (device int64), asynchronously."""
         ptr, n = _dev_text(t)
-        check(load().sm_patterns_count(self._h, i, ptr, n, _params(peel, tile_kib, wgs_per_cu, t, self.m[i]),
+        check(load().sm_patterns_count(self._h, i, ptr, n,
+                                       _params(peel, tile_kib, wgs_per_cu, t, self.m[i], bitmap=bitmap),
                                        out.data_ptr(), _stream(stream)))
 
     def count(self, i: int, t, **kw) -> int:

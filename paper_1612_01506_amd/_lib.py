@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(_PKG, "libsm.so")
 SM_OK, SM_EINVAL, SM_ENOMEM, SM_EDEVICE = 0, -1, -2, -3
 SM_ORDER_LTR, SM_ORDER_FREQ, SM_ORDER_H, SM_ORDER_HS = 0, 1, 2, 3
 SM_NONOVERLAP = 1
+SM_BITMAP = 2
 
 # Every symbol declared in include/sm.h.
 EXPORTS = (

@@ -518,7 +518,31 @@ struct Tune {
     int cpl;
     int wpc;
     int chunk_log2;
+    bool bitmap = false;  // count through symbol bitmaps where the pattern allows (SM_BITMAP)
+    int bm_cpw = 2;       // bitmap tile: kWG * bm_cpw words of 32 starts (8 KiB of text per unit)
 };
+
+// The distinct symbols of a pattern, up to kBcMaxSyms of them (ns = kBcMaxSyms + 1: more).
+struct PatSyms {
+    uint32_t packed = 0;  // byte c: symbol of slot c, in order of first appearance
+    uint32_t ns = 0;
+};
+
+PatSyms pattern_syms(const uint8_t *p, uint64_t m)
+{
+    PatSyms ps;
+    for (uint64_t j = 0; j < m && ps.ns <= kBcMaxSyms; ++j) {
+        bool seen = false;
+        for (uint32_t c = 0; c < ps.ns; ++c)
+            seen |= ((ps.packed >> (8 * c)) & 0xFFu) == p[j];
+        if (!seen) {
+            if (ps.ns < kBcMaxSyms)
+                ps.packed |= (uint32_t)p[j] << (8 * ps.ns);
+            ++ps.ns;
+        }
+    }
+    return ps;
+}
 
 Tune resolve(const sm_params *p, uint64_t m, uint64_t n)
 {
@@ -526,7 +550,10 @@ Tune resolve(const sm_params *p, uint64_t m, uint64_t n)
     // p has passed check_flags: every field is 0 (default) or in range
     t.r = (p && p->peel > 0) ? p->peel : 2;
     t.r = (int)std::min<uint64_t>((uint64_t)t.r, m);
-    if (p && p->tile_kib > 0)
+    t.bitmap = p && (p->flags & SM_BITMAP);
+    if (t.bitmap && p->tile_kib > 0)
+        t.bm_cpw = p->tile_kib / 8;
+    if (p && p->tile_kib > 0 && !t.bitmap)
         t.cpl = p->tile_kib / 4;
     else
         t.cpl = n >= (8ull << 20) ? 2 : 1;  // 8 KiB tiles measured best on 1 GiB texts
@@ -550,11 +577,51 @@ TextView make_view(const uint8_t *t, uint64_t n)
 
 uint32_t halo_for(uint64_t m) { return (uint32_t)round_up(m + 4, 16); }
 
-// Fills the geometry of a single search and launches the count kernel.
+// Bitmap tile words per thread for a pattern of length m: the requested size, doubled
+// (up to 4) while the halo words would exceed half the tile; 0 if even that is too small.
+int bitmap_cpw(int want, uint64_t m)
+{
+    const uint64_t h = ((m - 1) >> 5) + 1;
+    int cpw = want;
+    while (cpw < 4 && h > kWG * (uint64_t)cpw / 2)
+        cpw *= 2;
+    return h <= kWG * (uint64_t)cpw / 2 ? cpw : 0;
+}
+
+// Single search through symbol bitmaps (count only).
+int launch_count_bm(Dev &d, const TextView &tv, uint64_t m, const uint64_t *steps_dev, const Tune &tu,
+                    const PatSyms &sy, int cpw, unsigned long long *count_dev, hipStream_t s)
+{
+    BmCountArgs a{};
+    a.tv = tv;
+    a.last = tv.first + tv.n - m;
+    a.steps = steps_dev;
+    a.count = count_dev;
+    a.m = (uint32_t)m;
+    a.r = (uint32_t)tu.r;
+    a.syms = sy.packed;
+    a.halo_words = (uint32_t)(((m - 1) >> 5) + 1);
+    const uint64_t S = 32ull * (kWG * (uint64_t)cpw - a.halo_words);
+    a.ntiles = ceil_div(a.last + 1, S);
+    const uint64_t target = (uint64_t)std::max(d.cus, 1) * (uint64_t)tu.wpc;
+    uint32_t ck = (uint32_t)tu.chunk_log2;
+    while (ck > 0 && ceil_div(a.ntiles, 1ull << ck) < target)
+        --ck;
+    a.chunk_log2 = ck;
+    const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(a.ntiles, 1ull << ck), target));
+    HIP_TRY(launch_count_bitmap(a, (int)sy.ns, cpw, tv.n >= kStreamLoadBytes, (unsigned)grid, s));
+    return SM_OK;
+}
+
+// Fills the geometry of a single search and launches the count kernel.  sy: the
+// pattern's distinct symbols, for the bitmap kernel (counts only, SM_BITMAP).
 int launch_count(Dev &d, const TextView &tv, uint64_t m, const uint64_t *steps_dev, const Tune &tu,
                  unsigned long long *count_dev, uint32_t *block_counts, unsigned long long *group_sums,
-                 hipStream_t s)
+                 hipStream_t s, const PatSyms *sy = nullptr)
 {
+    if (tu.bitmap && sy && sy->ns >= 1 && sy->ns <= kBcMaxSyms && !block_counts && count_dev)
+        if (const int cpw = bitmap_cpw(tu.bm_cpw, m))
+            return launch_count_bm(d, tv, m, steps_dev, tu, *sy, cpw, count_dev, s);
     CountArgs a{};
     a.tv = tv;
     a.last = tv.first + tv.n - m;
@@ -668,8 +735,9 @@ int64_t count_sync(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t n, c
     }
     auto enqueue = [&]() -> int {
         HIP_TRY(hipMemsetAsync(d->u64, 0, sizeof(unsigned long long), s));
+        const PatSyms sy = pattern_syms(p, m);
         SM_TRY(launch_count(*d, make_view(t, n), m, reinterpret_cast<const uint64_t *>(u.dev), tu, d->u64, nullptr,
-                            nullptr, s));
+                            nullptr, s, &sy));
         HIP_TRY(hipMemcpyAsync(d->hpin, d->u64, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
         return SM_OK;
     };
@@ -840,8 +908,12 @@ int check_flags(const sm_params *params, bool nonoverlap_ok)
     auto tile_ok = [](int32_t v) { return v == 0 || v == 4 || v == 8 || v == 16; };
     if (params->peel < 0 || params->peel > (int32_t)kMaxPeel)
         return fail(SM_EINVAL, "sm_params.peel must be 0 (default) or 1..8");
-    if (!tile_ok(params->tile_kib))
+    if (params->flags & SM_BITMAP) {
+        if (params->tile_kib != 0 && params->tile_kib != 8 && params->tile_kib != 16 && params->tile_kib != 32)
+            return fail(SM_EINVAL, "sm_params.tile_kib must be 0 (default), 8, 16 or 32 with SM_BITMAP");
+    } else if (!tile_ok(params->tile_kib)) {
         return fail(SM_EINVAL, "sm_params.tile_kib must be 0 (default), 4, 8 or 16");
+    }
     if (params->wgs_per_cu < 0 || params->wgs_per_cu > 32)
         return fail(SM_EINVAL, "sm_params.wgs_per_cu must be 0 (default) or 1..32");
     if (const sm_batch_tune *b = params->batch) {
@@ -858,10 +930,10 @@ int check_flags(const sm_params *params, bool nonoverlap_ok)
         if (b->wgs_per_cu < 0 || b->wgs_per_cu > 32 || b->deal_wgs_per_cu < 0 || b->deal_wgs_per_cu > 64)
             return fail(SM_EINVAL, "sm_batch_tune workgroups per CU out of range");
     }
-    if (params->flags == 0)
-        return SM_OK;
-    if (params->flags & ~(int32_t)SM_NONOVERLAP)
+    if (params->flags & ~(int32_t)(SM_NONOVERLAP | SM_BITMAP))
         return fail(SM_EINVAL, "unknown sm_params flags");
+    if (!(params->flags & SM_NONOVERLAP))
+        return SM_OK;
     if (!nonoverlap_ok)
         return fail(SM_EINVAL, "SM_NONOVERLAP is supported by the synchronous calls only "
                                "(sm_count_ex, sm_report_ex, sm_patterns_report)");
@@ -1194,7 +1266,9 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
     // params has passed check_flags.  Explicit peel / tile / workgroups take precedence over the
     // per-class batch tuning, which takes precedence over the defaults.
     const sm_batch_tune *bt = params ? params->batch : nullptr;
-    const int cpl = (params && params->tile_kib > 0) ? params->tile_kib / 4 : (bt && bt->tile_kib > 0) ? bt->tile_kib / 4 : 2;
+    // (a tile size given with SM_BITMAP is a bitmap tile size, which batches do not use)
+    const bool tile_given = params && params->tile_kib > 0 && !(params->flags & SM_BITMAP);
+    const int cpl = tile_given ? params->tile_kib / 4 : (bt && bt->tile_kib > 0) ? bt->tile_kib / 4 : 2;
     const uint64_t T = 4096ull * cpl;
     const bool peel_given = params && params->peel > 0;
     const int rdef = peel_given ? params->peel : 2;
@@ -1728,6 +1802,7 @@ struct sm_patterns {
     int dev = -1;
     uint64_t *steps = nullptr;
     std::vector<uint64_t> off, m;
+    std::vector<PatSyms> syms;  // distinct symbols, for bitmap counts
 };
 
 namespace {
@@ -1749,7 +1824,7 @@ int check_set(const sm_patterns *ps, uint64_t i)
 
 extern "C" {
 
-int32_t sm_version(void) { return 10100; }
+int32_t sm_version(void) { return 10200; }
 
 const char *sm_last_error(void) { return g_err.c_str(); }
 
@@ -1915,8 +1990,9 @@ int32_t sm_count_async(const uint8_t *p, uint64_t m, const uint8_t *t, uint64_t 
     const Tune tu = resolve(params, m, n);
     Upload u;
     SM_TRY(upload_steps(*d, p, m, order, s, &u));
+    const PatSyms sy = pattern_syms(p, m);
     const int rc = launch_count(*d, make_view(t, n), m, reinterpret_cast<const uint64_t *>(u.dev), tu,
-                                reinterpret_cast<unsigned long long *>(count_dev), nullptr, nullptr, s);
+                                reinterpret_cast<unsigned long long *>(count_dev), nullptr, nullptr, s, &sy);
     const std::string msg = g_err;
     const int rc2 = ring_commit(*d, u, s);  // also after an error: the upload may still be in flight
     return rc < 0 ? fail(rc, msg) : rc2;
@@ -1977,6 +2053,7 @@ int32_t sm_patterns_create(uint64_t np, const uint8_t *const *p, const uint64_t 
             build_steps(p[i], m[i], order ? order[i] : nullptr, host + at);
             ps->off.push_back(at);
             ps->m.push_back(m[i]);
+            ps->syms.push_back(pattern_syms(p[i], m[i]));
             at += m[i] + kStepPad;
         }
         if ((e = hipMemcpyAsync(ps->steps, u.host, bytes, hipMemcpyHostToDevice, nullptr)) != hipSuccess)
@@ -2055,7 +2132,7 @@ int32_t sm_patterns_count(const sm_patterns *ps, uint64_t i, const uint8_t *t, u
     const Tune tu = resolve(params, m, n);
     return launch_count(*d, make_view(t, n), m, ps->steps + ps->off[i], tu,
                         reinterpret_cast<unsigned long long *>(count_dev), nullptr, nullptr,
-                        reinterpret_cast<hipStream_t>(stream));
+                        reinterpret_cast<hipStream_t>(stream), &ps->syms[i]);
 }
 
 int64_t sm_patterns_report(const sm_patterns *ps, uint64_t i, const uint8_t *t, uint64_t n, const sm_params *params,

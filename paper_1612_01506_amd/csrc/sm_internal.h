@@ -176,10 +176,31 @@ inline uint64_t bm_item_lds(uint32_t nslots, uint32_t wps, uint32_t nq)
     return (uint64_t)nslots * wps * 4 + kBmSmapBytes + (uint64_t)nq * kBmPerQueryLds + 16;
 }
 
+// Single search over per-tile symbol bitmaps (patterns of at most kBcMaxSyms distinct symbols).
+// A tile is W = kWG * CPW words of 32 coordinates per slot; its last halo_words words carry no
+// starts (they hold the bits the funnel shifts of the other words reach), so a tile has
+// 32 * (W - halo_words) starts.
+constexpr uint32_t kBcMaxSyms = 4;
+struct BmCountArgs {
+    TextView tv;
+    uint64_t last;             // coordinate of the last valid start: first + n - m
+    uint64_t ntiles;           // tiles covering coordinates [0, last]
+    const uint64_t *steps;     // device step table (m + kStepPad entries)
+    unsigned long long *count; // += total count
+    uint32_t m;
+    uint32_t r;                // peel factor, 1..min(kMaxPeel, m)
+    uint32_t syms;             // the pattern's distinct symbols: byte c is the symbol of slot c
+    uint32_t halo_words;       // ((m - 1) >> 5) + 1, at most half a tile's words
+    uint32_t chunk_log2;       // tiles are dealt in chunks of 2^chunk_log2 contiguous tiles
+    uint32_t pad;
+};
+
 // Host-side launchers (sm_kernels.hip).  Each returns a hipError_t.
 // stream_loads: tile loads with the non-temporal cache policy (texts far larger than the last-level cache)
 hipError_t launch_count_staged(const CountArgs &a, int cpl, int r, bool stream_loads, unsigned grid, hipStream_t s);
 hipError_t launch_count_global(const CountArgs &a, int r, unsigned grid, hipStream_t s);
+// ns: distinct pattern symbols (1..kBcMaxSyms); cpw: bitmap words per thread and tile (1, 2 or 4)
+hipError_t launch_count_bitmap(const BmCountArgs &a, int ns, int cpw, bool stream_loads, unsigned grid, hipStream_t s);
 hipError_t launch_scan_groups(const unsigned long long *gs, uint64_t ngroups, unsigned long long *go,
                               unsigned long long *total, hipStream_t s);
 hipError_t launch_report_write(const CountArgs &a, uint32_t *bc, unsigned long long *gs, const unsigned long long *go,

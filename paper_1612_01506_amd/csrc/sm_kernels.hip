@@ -1528,6 +1528,251 @@ __global__ __launch_bounds__(kBmWG) __attribute__((amdgpu_waves_per_eu(8))) void
     batch_bitmap<2>(a);
 }
 
+// ------------------------------------------------- bitmap single search
+
+// Section 2.1's SIMDcompare of one symbol against every start of a tile,
+// memoised: per tile, one bitmap per distinct pattern symbol (a slot), bit q of
+// slot c set when the text byte at tile offset q is that symbol; then a compare
+// of pattern position j over 32 starts is one funnel shift of two bitmap words
+// and an AND.  Pays off when compares per start are many (small alphabets) and
+// the pattern has few distinct symbols: the build costs about 2.9 VALU ops per
+// text byte for two slots, the compares about 0.13 per start and compare.
+
+// Slot of pattern symbol `sym` among the NS distinct symbols packed in syms.
+template <int NS>
+__device__ __forceinline__ uint32_t bc_slot(uint32_t syms, uint32_t sym)
+{
+    uint32_t c = 0;
+#pragma unroll
+    for (int s = 1; s < NS; ++s)
+        if (((syms >> (8 * s)) & 0xFFu) == sym)
+            c = (uint32_t)s;
+    return c;
+}
+
+// Bitmap step entries of compares 64k .. 64k + 63, entry of compare 64k + i in
+// lane i: ((slot * W + (j >> 5)) << 7) | (j & 31), i.e. the slot word holding
+// bit j (its word index shifted left by 7) and j mod 32.  Lanes past m hold 0
+// (never read: the compares stop at m).
+template <int NS, uint32_t W>
+__device__ __forceinline__ uint32_t bc_entries(const BmCountArgs &a, uint32_t k, uint32_t lane)
+{
+    const uint32_t l = 64u * k + lane;
+    if (l >= a.m)
+        return 0u;
+    const uint64_t st = a.steps[l];
+    const uint32_t j = step_pos(st), c = bc_slot<NS>(a.syms, step_rep(st) & 0xFFu);
+    return ((c * W + (j >> 5)) << 7) | (j & 31u);
+}
+
+// One bitmap word per slot from the 32 text bytes D (byte b of D[i] at offset
+// 4i + b): bit q set when byte q is the slot's symbol.  First the two 4 x 4
+// byte transposes of (D0, D2, D4, D6) and (D1, D3, D5, D7), so that byte k of
+// E[d] is the byte at offset 8k + d; then per slot an exact byte-equality test
+// of each E[d] (0x80 in each byte that differs) and a rotate that puts byte k's
+// flag at bit 8k + d.  dst: the word of slot 0; slots are `stride` words apart.
+template <int NS>
+__device__ __forceinline__ void bc_build_word(const uint32_t (&D)[8], uint32_t syms, uint32_t *dst, uint32_t stride)
+{
+    uint32_t E[8];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const uint32_t ablo = __builtin_amdgcn_perm(D[2 + h], D[h], 0x05010400u);
+        const uint32_t abhi = __builtin_amdgcn_perm(D[2 + h], D[h], 0x07030602u);
+        const uint32_t cdlo = __builtin_amdgcn_perm(D[6 + h], D[4 + h], 0x05010400u);
+        const uint32_t cdhi = __builtin_amdgcn_perm(D[6 + h], D[4 + h], 0x07030602u);
+        E[4 * h + 0] = __builtin_amdgcn_perm(cdlo, ablo, 0x05040100u);
+        E[4 * h + 1] = __builtin_amdgcn_perm(cdlo, ablo, 0x07060302u);
+        E[4 * h + 2] = __builtin_amdgcn_perm(cdhi, abhi, 0x05040100u);
+        E[4 * h + 3] = __builtin_amdgcn_perm(cdhi, abhi, 0x07060302u);
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const uint32_t rep = ((syms >> (8 * s)) & 0xFFu) * 0x01010101u;
+        uint32_t miss = 0;
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            const uint32_t x = E[d] ^ rep;
+            const uint32_t y = ((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x;  // bit 8k + 7: byte k differs
+            miss |= __builtin_amdgcn_alignbit(y, y, 7u - (uint32_t)d) & (0x01010101u << d);
+        }
+        dst[s * stride] = ~miss;
+    }
+}
+
+// One compare over the thread's CPW words (words tid + kWG * c of the tile):
+// bits j .. j + 31 past each word's first start, a funnel shift of two words.
+template <int CPW, bool FIRST>
+__device__ __forceinline__ void bc_step(const uint32_t *buf, uint32_t e, uint32_t tid, uint32_t (&f)[CPW])
+{
+    const uint32_t *w = buf + (e >> 7) + tid;
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+        const uint32_t v = __builtin_amdgcn_alignbit(w[kWG * c + 1], w[kWG * c], e);
+        f[c] = FIRST ? v : (f[c] & v);
+    }
+}
+
+template <int CPW>
+__device__ __forceinline__ bool bc_any(const uint32_t (&f)[CPW])
+{
+    uint32_t o = 0;
+#pragma unroll
+    for (int c = 0; c < CPW; ++c)
+        o |= f[c];
+    return __any(o != 0u);
+}
+
+// Verifies each start still alive in this wave on compares l..m-1, 64
+// compares at a time across the lanes (lane i tests compare l + i, then
+// l + 64 + i, ...: the bit of the start plus j in its symbol's bitmap), and
+// clears the starts that fail.  Only the grouping of the AND changes (by
+// start instead of by compare).  Starts are visited in increasing tile offset
+// through a wave-uniform cursor.
+template <int NS, int CPW, uint32_t W>
+__device__ __forceinline__ void bc_verify(const BmCountArgs &a, const uint32_t *buf, uint32_t l, uint32_t tid,
+                                          uint32_t (&f)[CPW])
+{
+    const uint32_t lane = tid & 63u;
+    uint32_t cursor = 0;
+    while (true) {
+        uint32_t best = 0xFFFFFFFFu;
+#pragma unroll
+        for (int c = CPW - 1; c >= 0; --c) {
+            const uint32_t q0 = 32u * (tid + kWG * c);
+            uint32_t z = f[c];
+            if (cursor > q0)
+                z = cursor - q0 >= 32u ? 0u : z & (0xFFFFFFFFu << (cursor - q0));
+            if (z)
+                best = q0 + (uint32_t)__builtin_ctz(z);
+        }
+        best = wave_min32(best);
+        if (best == 0xFFFFFFFFu)
+            break;
+        bool ok = true;
+        for (uint32_t b0 = l; ok && b0 < a.m; b0 += 64u) {
+            const uint32_t idx = b0 + lane;
+            bool bad = false;
+            if (idx < a.m) {
+                const uint64_t st = a.steps[idx];
+                const uint32_t q = best + step_pos(st);
+                const uint32_t c = bc_slot<NS>(a.syms, step_rep(st) & 0xFFu);
+                bad = ((buf[c * W + (q >> 5)] >> (q & 31u)) & 1u) == 0u;
+            }
+            ok = !__any(bad);
+        }
+        const uint32_t w = best >> 5;
+        if (!ok && (w & (kWG - 1u)) == tid) {
+#pragma unroll
+            for (int c = 0; c < CPW; ++c)
+                if ((uint32_t)c == w / kWG)
+                    f[c] &= ~(1u << (best & 31u));
+        }
+        cursor = best + 1u;
+    }
+}
+
+// Single search over bitmap tiles.  Tiles are dealt out as in the byte-tile
+// count kernel.  Thread tid owns words tid + kWG * c (c < CPW) of every tile:
+// it loads their 32 text bytes each into registers (the next tile's while the
+// current one is searched), builds their slot words into one of two LDS
+// buffers, and after the barrier runs Algorithm 4 on its 32 * CPW starts: the
+// first r compares unconditionally, then the zero test (wave-wide) after each
+// of the next kTestEach compares and after each group of kGroup later ones, as
+// in the byte-tile kernel; a handful of starts facing kVerifyMin or more
+// further compares are verified one at a time across the lanes.  Entries of
+// the first 64 compares stay in a register and are taken with readlane; later
+// ones are computed per block of 64 when reached.
+template <int NS, int CPW, bool STREAM>
+__global__ __launch_bounds__(kWG) void k_count_bitmap(BmCountArgs a)
+{
+    extern __shared__ __align__(16) uint32_t bml[];
+    constexpr uint32_t W = kWG * CPW;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u;
+    const uint32_t S = 32u * (W - a.halo_words);  // starts per tile
+    const uint64_t kmask = (1ull << a.chunk_log2) - 1u;
+    auto tile_of = [&](uint64_t i) {
+        return (((uint64_t)blockIdx.x + (i >> a.chunk_log2) * gridDim.x) << a.chunk_log2) + (i & kmask);
+    };
+    uint32_t X[CPW][8];
+    auto load_tile = [&](uint64_t ts) {
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) {
+            const uint64_t u = ts + 32ull * (tid + kWG * c);
+            const uint4 lo = u < a.tv.end16 ? load16<STREAM>(a.tv.base + u) : make_uint4(0, 0, 0, 0);
+            const uint4 hi = u + 16u < a.tv.end16 ? load16<STREAM>(a.tv.base + u + 16u) : make_uint4(0, 0, 0, 0);
+            X[c][0] = lo.x, X[c][1] = lo.y, X[c][2] = lo.z, X[c][3] = lo.w;
+            X[c][4] = hi.x, X[c][5] = hi.y, X[c][6] = hi.z, X[c][7] = hi.w;
+        }
+    };
+    const uint32_t ent0 = bc_entries<NS, W>(a, 0, lane);
+    const uint32_t r = min(a.r, a.m);
+    uint32_t acc = 0;
+    uint64_t tile = tile_of(0);
+    if (tile < a.ntiles)
+        load_tile(tile * S);
+    for (uint64_t i = 0; tile < a.ntiles; ++i) {
+        const uint64_t ts = tile * S;
+        uint32_t *buf = bml + (i & 1u) * (NS * W);
+#pragma unroll
+        for (int c = 0; c < CPW; ++c)
+            bc_build_word<NS>(X[c], a.syms, buf + tid + kWG * c, W);
+        const uint64_t next = tile_of(i + 1);
+        if (next < a.ntiles)
+            load_tile(next * S);
+        __syncthreads();  // the tile's bitmaps are complete; the other buffer is no longer read
+        // valid starts as tile offsets [lo, hi) (tile < ntiles, so last >= ts)
+        const uint64_t rem = a.last - ts;
+        const uint32_t hi = rem >= S ? S : (uint32_t)rem + 1u;
+        const uint32_t lo = ts < a.tv.first ? (uint32_t)(a.tv.first - ts) : 0u;
+        uint32_t f[CPW];
+        bc_step<CPW, true>(buf, readlane(ent0, 0), tid, f);
+#pragma unroll
+        for (int c = 0; c < CPW; ++c)
+            f[c] &= range_bits(32u * (tid + kWG * c), lo, hi);
+        uint32_t l = 1;
+        for (; l < r; ++l)
+            bc_step<CPW, false>(buf, readlane(ent0, l), tid, f);
+        uint32_t entx = 0, blk = 0;
+        auto entry = [&](uint32_t k) {
+            if (k < 64u)
+                return readlane(ent0, k);
+            if ((k >> 6) != blk) {
+                blk = k >> 6;
+                entx = bc_entries<NS, W>(a, blk, lane);
+            }
+            return readlane(entx, k & 63u);
+        };
+        const uint32_t l1 = min(a.m, l + kTestEach);
+        for (; l < l1 && bc_any(f); ++l)
+            bc_step<CPW, false>(buf, entry(l), tid, f);
+        bool grouped = false;
+        while (l < a.m && bc_any(f)) {
+            if (grouped && a.m - l >= kVerifyMin) {
+                uint32_t alive = 0;
+#pragma unroll
+                for (int c = 0; c < CPW; ++c)
+                    alive += __popc(f[c]);
+                if (wave_sum32(alive) <= kVerifyMax) {
+                    bc_verify<NS, CPW, W>(a, buf, l, tid, f);
+                    break;
+                }
+            }
+            const uint32_t g = min(kGroup, a.m - l);
+#pragma unroll 1
+            for (uint32_t u = 0; u < g; ++u)
+                bc_step<CPW, false>(buf, entry(l + u), tid, f);
+            l += g;
+            grouped = true;
+        }
+#pragma unroll
+        for (int c = 0; c < CPW; ++c)
+            acc += __popc(f[c]);
+        tile = next;
+    }
+    wg_add_count(acc, a.count, tid);
+}
+
 // ---------------------------------------------------------------- launchers
 
 template <int CPL, int R, bool STREAM>
@@ -1590,6 +1835,45 @@ hipError_t launch_count_global(const CountArgs &a, int r, unsigned grid, hipStre
     case 8: return launch_global_t<8>(a, grid, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+template <int NS, int CPW, bool STREAM>
+static hipError_t launch_bitmap_t(const BmCountArgs &a, unsigned grid, hipStream_t s)
+{
+    // two buffers of NS slots, plus the words a no-start thread's funnel shifts reach past the last slot
+    const uint32_t lds = (2u * NS * kWG * CPW + a.halo_words + 1u) * 4u;
+    hipLaunchKernelGGL((k_count_bitmap<NS, CPW, STREAM>), dim3(grid), dim3(kWG), lds, s, a);
+    return hipGetLastError();
+}
+
+template <int CPW, bool STREAM>
+static hipError_t launch_bitmap_n(const BmCountArgs &a, int ns, unsigned grid, hipStream_t s)
+{
+    switch (ns) {
+    case 1: return launch_bitmap_t<1, CPW, STREAM>(a, grid, s);
+    case 2: return launch_bitmap_t<2, CPW, STREAM>(a, grid, s);
+    case 3: return launch_bitmap_t<3, CPW, STREAM>(a, grid, s);
+    case 4: return launch_bitmap_t<4, CPW, STREAM>(a, grid, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <bool STREAM>
+static hipError_t launch_bitmap_c(const BmCountArgs &a, int ns, int cpw, unsigned grid, hipStream_t s)
+{
+    switch (cpw) {
+    case 1: return launch_bitmap_n<1, STREAM>(a, ns, grid, s);
+    case 2: return launch_bitmap_n<2, STREAM>(a, ns, grid, s);
+    case 4: return launch_bitmap_n<4, STREAM>(a, ns, grid, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_count_bitmap(const BmCountArgs &a, int ns, int cpw, bool stream_loads, unsigned grid, hipStream_t s)
+{
+    if (a.halo_words == 0 || a.halo_words > kWG * (uint32_t)cpw / 2u)
+        return hipErrorInvalidValue;
+    return stream_loads ? launch_bitmap_c<true>(a, ns, cpw, grid, s) : launch_bitmap_c<false>(a, ns, cpw, grid, s);
 }
 
 hipError_t launch_scan_groups(const unsigned long long *gs, uint64_t ngroups, unsigned long long *go,

@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_version():
-    assert sm.version() == 10100
+    assert sm.version() == 10200
 
 
 def _err(rc):
@@ -85,8 +85,17 @@ def test_validation_before_any_device_call():
         assert "sm_batch_tune" in _err(lib.sm_count_ex(p.ctypes.data, 3, None, 0, None, ctypes.byref(bad), None))
     good = _lib.sm_params(8, 16, 32, 0)
     assert lib.sm_count_ex(p.ctypes.data, 3, None, 0, None, ctypes.byref(good), None) == 0
+    # SM_BITMAP: bitmap tiles of 8, 16 or 32 KiB (32 only with the flag, 4 only without)
+    for tile in (8, 16, 32):
+        ok = _lib.sm_params(0, tile, 0, _lib.SM_BITMAP)
+        assert lib.sm_count_ex(p.ctypes.data, 3, None, 0, None, ctypes.byref(ok), None) == 0   # m > n
+    for tile in (4, 12, 64):
+        bad = _lib.sm_params(0, tile, 0, _lib.SM_BITMAP)
+        assert "SM_BITMAP" in _err(lib.sm_count_ex(p.ctypes.data, 3, None, 0, None, ctypes.byref(bad), None))
+    both = _lib.sm_params(0, 16, 0, _lib.SM_BITMAP | _lib.SM_NONOVERLAP)
+    assert lib.sm_count_ex(p.ctypes.data, 3, None, 0, None, ctypes.byref(both), None) == 0
     # sm_params.flags: unknown bits everywhere, SM_NONOVERLAP outside the synchronous calls
-    bad_flags = _lib.sm_params(0, 0, 0, 2)
+    bad_flags = _lib.sm_params(0, 0, 0, 4)
     assert "flags" in _err(lib.sm_count_ex(p.ctypes.data, 3, None, 0, None, ctypes.byref(bad_flags), None))
     no = _lib.sm_params(0, 0, 0, _lib.SM_NONOVERLAP)
     assert lib.sm_count_ex(p.ctypes.data, 3, None, 0, None, ctypes.byref(no), None) == 0   # m > n: no device work
