@@ -6,7 +6,9 @@ over a grid of tile size, workgroups per compute unit and peel factor r, and
 keeps the fastest setting.  None of these parameters changes a result.  The
 grid holds every compiled peel factor r = 1..8, which includes the paper's
 choices with frequency order: r = 2 for large alphabets, r = 3 for protein
-and r = 5 for DNA (Section 3).
+and r = 5 for DNA (Section 3).  Cells of texts over at most 4 symbols also
+time the bitmap compares (SM_BITMAP: bitmap tile size, workgroups per CU and
+r), and a cell records which mode won.
 
 The table is one JSON file per GPU architecture (`tuning/<arch>.json` next to
 this module), which records the HIP version it was measured with.  The
@@ -42,6 +44,11 @@ TILE_KIB = (4, 8, 16)
 WGS_PER_CU = (4, 5, 6, 8)
 PEELS = (1, 2, 3, 4, 5, 6, 7, 8)     # every compiled peel factor
 GRID = [(tk, w, r) for tk in TILE_KIB for w in WGS_PER_CU for r in PEELS]
+BM_CLASSES = (2, 4)                  # classes whose cells also time the bitmap compares
+BM_TILE_KIB = (8, 16, 32)
+BM_WGS_PER_CU = (4, 6, 8)
+BM_PEELS = (1, 2, 3, 4)
+BM_GRID = [(tk, w, r) for tk in BM_TILE_KIB for w in BM_WGS_PER_CU for r in BM_PEELS]
 
 _table = None
 _table_key = None
@@ -102,7 +109,8 @@ def params_for(hist, m: int, n: int) -> dict | None:
     e = tab["cells"].get(key)
     if e is None:
         return None
-    return {"tile_kib": e["tile_kib"], "wgs_per_cu": e["wgs_per_cu"], "peel": e["peel"]}
+    return {"tile_kib": e["tile_kib"], "wgs_per_cu": e["wgs_per_cu"], "peel": e["peel"],
+            "bitmap": bool(e.get("bitmap", False))}
 
 
 def batch_tune() -> dict | None:
@@ -114,9 +122,11 @@ def batch_tune() -> dict | None:
     return tab.get("batch")
 
 
-def tune(sizes=(8 << 20, 1 << 30), patterns_per_cell: int = 4, rounds: int = 3, log=print) -> dict:
+def tune(sizes=(8 << 20, 1 << 30), patterns_per_cell: int = 4, rounds: int = 3, log=print,
+         classes=CLASSES) -> dict:
     """Every setting of a cell is timed once per round, the rounds interleaved over the grid so that
-    slow drifts of the device hit all settings alike; a setting's time is its median over the rounds."""
+    slow drifts of the device hit all settings alike; a setting's time is its median over the rounds.
+    classes: the alphabet classes to tune (the others are left out of the result)."""
     import torch
 
     from . import Patterns, Text
@@ -127,7 +137,7 @@ def tune(sizes=(8 << 20, 1 << 30), patterns_per_cell: int = 4, rounds: int = 3, 
     cells = {}
     timings = {}
     for ni, n in enumerate(sizes):
-        for sigma in CLASSES:
+        for sigma in classes:
             if sigma == 95:
                 t_host = synth.zipf_text(n, 95, 1.0, family=7, stream=ni)
             else:
@@ -142,31 +152,36 @@ def tune(sizes=(8 << 20, 1 << 30), patterns_per_cell: int = 4, rounds: int = 3, 
                 ps = Patterns(pats, "freq", t.hist)
                 out = torch.zeros(1, dtype=torch.int64, device=dev)
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                samples = {cfg: [] for cfg in GRID}
+                grid = [(False,) + g for g in GRID]
+                if sigma in BM_CLASSES:
+                    grid += [(True,) + g for g in BM_GRID]
+                samples = {cfg: [] for cfg in grid}
                 for rnd in range(rounds + 1):          # round 0 warms up (attributes, caches) and is not kept
-                    for tk, w, r in GRID:
+                    for bm, tk, w, r in grid:
                         e0.record()
                         for i in range(len(pats)):
-                            ps.count_async(i, t.t, out, peel=r, tile_kib=tk, wgs_per_cu=w)
+                            ps.count_async(i, t.t, out, peel=r, tile_kib=tk, wgs_per_cu=w, bitmap=bm)
                         e1.record()
                         torch.cuda.synchronize()
                         if rnd:
-                            samples[(tk, w, r)].append(e0.elapsed_time(e1) * 1e3 / len(pats))
+                            samples[(bm, tk, w, r)].append(e0.elapsed_time(e1) * 1e3 / len(pats))
                 best = None
-                for (tk, w, r), v in samples.items():
+                for (bm, tk, w, r), v in samples.items():
                     us = float(np.median(v))
-                    timings[f"{sigma}/{mi}/{ni}/{tk}/{w}/{r}"] = round(us, 2)
+                    timings[f"{sigma}/{mi}/{ni}/{'bm/' if bm else ''}{tk}/{w}/{r}"] = round(us, 2)
                     if best is None or us < best[0]:
-                        best = (us, tk, w, r)
+                        best = (us, tk, w, r, bm)
                 ps.close()
                 key = f"{sigma}/{mi}/{ni}"
-                cells[key] = {"tile_kib": best[1], "wgs_per_cu": best[2], "peel": best[3],
+                cells[key] = {"tile_kib": best[1], "wgs_per_cu": best[2], "peel": best[3], "bitmap": best[4],
                               "us": round(best[0], 2), "text_bytes": n, "m": ms}
                 log(f"[autotune] class {sigma} m<={mhi} n={n}: {cells[key]}")
             del t
             torch.cuda.empty_cache()
     return {"arch": arch, "hip": hip, "created": time.strftime("%Y-%m-%d"),
-            "grid": {"tile_kib": list(TILE_KIB), "wgs_per_cu": list(WGS_PER_CU), "peel": list(PEELS)},
+            "grid": {"tile_kib": list(TILE_KIB), "wgs_per_cu": list(WGS_PER_CU), "peel": list(PEELS),
+                     "bitmap": {"classes": list(BM_CLASSES), "tile_kib": list(BM_TILE_KIB),
+                                "wgs_per_cu": list(BM_WGS_PER_CU), "peel": list(BM_PEELS)}},
             "classes": list(CLASSES), "m_buckets": list(M_BUCKETS), "n_buckets": list(N_BUCKETS),
             "cells": cells, "timings_us": timings}
 
@@ -301,11 +316,20 @@ def main():
     ap.add_argument("--out", required=True)
     ap.add_argument("--rounds", type=int, default=3)
     ap.add_argument("--only", choices=["single", "batch", "both"], default="both")
-    ap.add_argument("--base", help="table whose other section is kept (with --only)")
+    ap.add_argument("--base", help="table whose other section is kept (with --only), and whose cells of "
+                                   "the classes not tuned (with --classes)")
+    ap.add_argument("--classes", type=int, nargs="+", default=list(CLASSES),
+                    help="alphabet classes whose single-search cells are tuned")
     args = ap.parse_args()
     tab = json.load(open(args.base)) if args.base else {}
     if args.only in ("single", "both"):
-        tab.update(tune(rounds=args.rounds))
+        new = tune(rounds=args.rounds, classes=tuple(args.classes))
+        pre = tuple(f"{c}/" for c in args.classes)
+        cells = {k: v for k, v in tab.get("cells", {}).items() if not k.startswith(pre)}
+        timings = {k: v for k, v in tab.get("timings_us", {}).items() if not k.startswith(pre)}
+        cells.update(new.pop("cells"))
+        timings.update(new.pop("timings_us"))
+        tab.update(new, cells=cells, timings_us=timings)
     if args.only in ("batch", "both"):
         tab["batch"] = tune_batch(rounds=args.rounds)
         if "arch" not in tab:

@@ -25,16 +25,26 @@ def test_buckets():
 def test_committed_table_is_complete_and_inside_its_grid():
     tab = json.load(open(TABLE))
     grid = tab["grid"]
+    bm = grid["bitmap"]
+    assert bm["classes"] == list(autotune.BM_CLASSES)
     for c in autotune.CLASSES:
         for mi in range(len(autotune.M_BUCKETS)):
             for ni in range(len(autotune.N_BUCKETS)):
                 e = tab["cells"][f"{c}/{mi}/{ni}"]
-                assert e["tile_kib"] in grid["tile_kib"] and e["wgs_per_cu"] in grid["wgs_per_cu"]
-                assert e["peel"] in grid["peel"]
-                # the kept setting is the fastest timing of its cell
-                cell = {k: v for k, v in tab["timings_us"].items() if k.startswith(f"{c}/{mi}/{ni}/")}
-                assert len(cell) == len(grid["tile_kib"]) * len(grid["wgs_per_cu"]) * len(grid["peel"])
-                assert e["us"] == min(cell.values())
+                g = bm if e.get("bitmap") else grid
+                assert e["tile_kib"] in g["tile_kib"] and e["wgs_per_cu"] in g["wgs_per_cu"]
+                assert e["peel"] in g["peel"]
+                assert not e.get("bitmap") or c in bm["classes"]
+                # the kept setting is the fastest timing of its cell, over both compare modes
+                pre = f"{c}/{mi}/{ni}/"
+                byte_t = {k: v for k, v in tab["timings_us"].items() if k.startswith(pre) and "/bm/" not in k}
+                bm_t = {k: v for k, v in tab["timings_us"].items() if k.startswith(pre + "bm/")}
+                assert len(byte_t) == len(grid["tile_kib"]) * len(grid["wgs_per_cu"]) * len(grid["peel"])
+                want_bm = len(bm["tile_kib"]) * len(bm["wgs_per_cu"]) * len(bm["peel"]) if c in bm["classes"] else 0
+                assert len(bm_t) == want_bm
+                assert e["us"] == min(list(byte_t.values()) + list(bm_t.values()))
+                key = f"{pre}{'bm/' if e.get('bitmap') else ''}{e['tile_kib']}/{e['wgs_per_cu']}/{e['peel']}"
+                assert tab["timings_us"][key] == e["us"]
     assert grid["peel"] == list(autotune.PEELS)
 
 
@@ -46,7 +56,8 @@ def test_params_for_reads_the_device_table(monkeypatch):
     h[:4] = 1000
     got = autotune.params_for(h, 100, 1 << 30)
     e = tab["cells"]["4/2/1"]
-    assert got == {"tile_kib": e["tile_kib"], "wgs_per_cu": e["wgs_per_cu"], "peel": e["peel"]}
+    assert got == {"tile_kib": e["tile_kib"], "wgs_per_cu": e["wgs_per_cu"], "peel": e["peel"],
+                   "bitmap": bool(e.get("bitmap"))}
     monkeypatch.setattr(autotune, "_device_key", lambda: ("gfx000", "test"))   # no table for this device
     assert autotune.params_for(h, 100, 1 << 30) is None
 
@@ -81,3 +92,38 @@ def test_batch_params_record(monkeypatch):
     assert sm._batch_params(peel=3) is not None and sm._batch_params(tune=False) is None
     custom = sm._batch_params(tune={"bm_min": [1] * 4})._obj
     assert list(custom.batch.contents.bm_min) == [1] * 4 and list(custom.batch.contents.peel) == [0] * 4
+
+
+def test_tuned_params_carry_the_compare_mode(monkeypatch):
+    """A cell that chose the bitmap compares sets SM_BITMAP with its bitmap tile size; asking for the
+    other mode drops the cell's tile size (it is in the other mode's units)."""
+    import paper_1612_01506_amd as sm
+    from paper_1612_01506_amd import _lib
+
+    monkeypatch.setattr(autotune, "_device_key", lambda: ("gfx950", "test"))
+    monkeypatch.setattr(autotune, "_table_key", None)
+    tab = json.load(open(TABLE))
+    bm_cells = [k for k, e in tab["cells"].items() if e.get("bitmap")]
+    byte_cells = [k for k, e in tab["cells"].items() if not e.get("bitmap")]
+    assert bm_cells and byte_cells
+
+    class FakeText(sm.Text):
+        def __init__(self, hist, n):
+            self._hist, self._n = hist, n
+
+        @property
+        def n(self):
+            return self._n
+
+    for key in (bm_cells[0], byte_cells[0]):
+        c, mi, ni = (int(x) for x in key.split("/"))
+        e = tab["cells"][key]
+        h = np.zeros(256, dtype=np.uint64)
+        h[:c] = 1
+        m = autotune.M_BUCKETS[mi]
+        n = autotune.N_BUCKETS[0] if ni == 0 else 1 << 30
+        p = sm._params(text=FakeText(h, n), m=m)._obj
+        assert bool(p.flags & _lib.SM_BITMAP) == bool(e.get("bitmap"))
+        assert (p.peel, p.tile_kib, p.wgs_per_cu) == (e["peel"], e["tile_kib"], e["wgs_per_cu"])
+        flipped = sm._params(text=FakeText(h, n), m=m, bitmap=not e.get("bitmap"))._obj
+        assert bool(flipped.flags & _lib.SM_BITMAP) != bool(e.get("bitmap")) and flipped.tile_kib == 0
