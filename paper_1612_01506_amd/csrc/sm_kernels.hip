@@ -1695,7 +1695,19 @@ __global__ __launch_bounds__(kWG) void k_count_bitmap(BmCountArgs a)
         return (((uint64_t)blockIdx.x + (i >> a.chunk_log2) * gridDim.x) << a.chunk_log2) + (i & kmask);
     };
     uint32_t X[CPW][8];
+    // a tile wholly inside the text loads without per-chunk bound tests (a wave-uniform branch)
     auto load_tile = [&](uint64_t ts) {
+        const uint8_t *tb = a.tv.base + ts;
+        if (ts + 32ull * W <= a.tv.end16) {
+#pragma unroll
+            for (int c = 0; c < CPW; ++c) {
+                const uint8_t *q = tb + 32u * (tid + kWG * c);
+                const uint4 lo = load16<STREAM>(q), hi = load16<STREAM>(q + 16);
+                X[c][0] = lo.x, X[c][1] = lo.y, X[c][2] = lo.z, X[c][3] = lo.w;
+                X[c][4] = hi.x, X[c][5] = hi.y, X[c][6] = hi.z, X[c][7] = hi.w;
+            }
+            return;
+        }
 #pragma unroll
         for (int c = 0; c < CPW; ++c) {
             const uint64_t u = ts + 32ull * (tid + kWG * c);
@@ -1705,6 +1717,11 @@ __global__ __launch_bounds__(kWG) void k_count_bitmap(BmCountArgs a)
             X[c][4] = hi.x, X[c][5] = hi.y, X[c][6] = hi.z, X[c][7] = hi.w;
         }
     };
+    // inner tiles: every start of the words below W - halo_words is valid
+    uint32_t inner[CPW];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c)
+        inner[c] = tid + kWG * c < W - a.halo_words ? 0xFFFFFFFFu : 0u;
     const uint32_t ent0 = bc_entries<NS, W>(a, 0, lane);
     const uint32_t r = min(a.r, a.m);
     uint32_t acc = 0;
@@ -1727,9 +1744,15 @@ __global__ __launch_bounds__(kWG) void k_count_bitmap(BmCountArgs a)
         const uint32_t lo = ts < a.tv.first ? (uint32_t)(a.tv.first - ts) : 0u;
         uint32_t f[CPW];
         bc_step<CPW, true>(buf, readlane(ent0, 0), tid, f);
+        if (lo == 0u && hi == S) {
 #pragma unroll
-        for (int c = 0; c < CPW; ++c)
-            f[c] &= range_bits(32u * (tid + kWG * c), lo, hi);
+            for (int c = 0; c < CPW; ++c)
+                f[c] &= inner[c];
+        } else {
+#pragma unroll
+            for (int c = 0; c < CPW; ++c)
+                f[c] &= range_bits(32u * (tid + kWG * c), lo, hi);
+        }
         uint32_t l = 1;
         for (; l < r; ++l)
             bc_step<CPW, false>(buf, readlane(ent0, l), tid, f);
