@@ -243,6 +243,12 @@ def run_zipf(args):
         }
         points, info = serve_points(args, args.serve_rates, args.serve_seconds, args.max_requests)
         extras["serve"] = dict(info, points=points)
+        torch.cuda.empty_cache()
+        small = run_small(args)
+        extras["small_alphabets"] = {
+            ln["config"]["workload"].split(",")[0]: {k: v for k, v in ln["config"].items() if k.endswith("_by_m")}
+            for ln in small[:2]}
+        extras["small_alphabets"]["periodic_a^255b_freq_us"] = small[2]["config"]["results"]["a^255b/freq"]["us"]
 
     return {
         "metric": "text GB/s per search (% HBM peak)",

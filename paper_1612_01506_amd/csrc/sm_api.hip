@@ -1091,6 +1091,7 @@ struct LaunchPlan {
         TextView tv;
         uint64_t m, steps_off, out;
         Tune tu;
+        PatSyms sy;  // the pattern's distinct symbols (bitmap compares on small-alphabet texts)
         uint32_t *bc = nullptr;  // reporting: per-vector counts and group sums
         unsigned long long *gs = nullptr;
     };
@@ -1734,6 +1735,15 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
         const bool fits8 = 2 * (8192 + halo_for(pq.m)) <= kMaxLds;
         L.tu = Tune{(int)long_peel[i], (texts[pq.text].n >= (8ull << 20) && fits8) ? 2 : 1, wpc_long,
                     (int)kChunkLog2};
+        // a counted query on a text whose histogram shows at most 4 symbols takes the bitmap
+        // compares (32 KiB tiles, 6 workgroups per CU: the single-search tuning's choice on 1 GiB
+        // texts of 2 and 4 symbols); the pattern's own symbols decide whether it can
+        if (!rep && text_cls[pq.text] <= 1 && !wpc_given) {
+            L.tu.bitmap = true;
+            L.tu.bm_cpw = 4;
+            L.tu.wpc = 6;
+            L.sy = pattern_syms(q[pq.idx].p, pq.m);
+        }
         if (rep) {
             L.bc = rep->bc[pq.idx];
             L.gs = rep->gs[pq.idx];
@@ -1784,7 +1794,7 @@ int launch_plan(Dev &d, const LaunchPlan &lp, const uint8_t *dev, unsigned long 
     }
     for (const auto &L : lp.longs)
         SM_TRY(launch_count(d, L.tv, L.m, reinterpret_cast<const uint64_t *>(dev + lp.o_steps) + L.steps_off, L.tu,
-                            counts + L.out, L.bc, L.gs, s));
+                            counts + L.out, L.bc, L.gs, s, &L.sy));
     return SM_OK;
 }
 

@@ -167,3 +167,34 @@ def test_lone_candidates_verified_across_lanes(dev):
                 for peel in (1, 4):
                     got = sm.count(td, p, order=order, bitmap=True, tile_kib=tile, peel=peel)
                     assert got == want, (m, tile, order, peel, got, want)
+
+
+def test_batch_single_search_launches_on_small_alphabet_texts(dev):
+    """Inside a batch, a text of 64 MiB or more with one or two queries runs them as single searches,
+    with the bitmap compares when its histogram shows at most 4 symbols.  Counts equal the oracle
+    under the text's own histogram, a histogram claiming 2 symbols for a 95-letter text (patterns of
+    5 or more distinct symbols fall back to byte compares), and no histogram."""
+    g = np.random.default_rng(9105)
+    texts_h = [synth.uniform_text((72 << 20) + 5, 2, family=3, stream=11),
+               synth.uniform_text((72 << 20) + 77, 4, family=3, stream=12),
+               synth.zipf_text((76 << 20) + 3, 95, 1.0, family=3, stream=13)]
+    texts_d = [torch.from_numpy(t).to(dev) for t in texts_h]
+    queries = [(ti, synth.substring_pattern(texts_h[ti], m, g)[0]) for ti in (0, 1) for m in (7, 300)]
+    queries.append((2, synth.substring_pattern(texts_h[2], 40, g)[0]))
+    queries.append((2, b"eeee"))                    # at most 4 distinct symbols on the 95-letter text
+    want = [oracle.count(p, texts_h[ti]) for ti, p in queries]
+    own = [oracle.hist(t) for t in texts_h]
+    claims_two = np.zeros(256, dtype=np.uint64)
+    claims_two[[ord("e"), ord("t")]] = 1
+    for hists in (own, [own[0], own[1], claims_two], None):
+        offs, pos = [], 0
+        buf = torch.zeros(sum(t.size for t in texts_h) + 64, dtype=torch.uint8, device=dev)
+        for t in texts_h:
+            pos += 7
+            offs.append(pos)
+            buf[pos:pos + t.size].copy_(torch.from_numpy(t))
+            pos += t.size
+        pt = sm.PackedTexts(buf, offs, [t.size for t in texts_h],
+                            None if hists is None else np.stack(hists))
+        assert sm.count_batch(pt, queries).cpu().tolist() == want
+        del buf, pt
