@@ -1568,11 +1568,55 @@ __device__ __forceinline__ uint32_t bc_entries(const BmCountArgs &a, uint32_t k,
 // One bitmap word per slot from the 32 text bytes D (byte b of D[i] at offset
 // 4i + b): bit q set when byte q is the slot's symbol.  First the two 4 x 4
 // byte transposes of (D0, D2, D4, D6) and (D1, D3, D5, D7), so that byte k of
-// E[d] is the byte at offset 8k + d; then per slot an exact byte-equality test
-// of each E[d] (0x80 in each byte that differs) and a rotate that puts byte k's
-// flag at bit 8k + d.  dst: the word of slot 0; slots are `stride` words apart.
+// E[d] is the byte at offset 8k + d; then, for one or two slots, per slot an
+// exact byte-equality test of each E[d] (0x80 in each byte that differs) and a
+// rotate that puts byte k's flag at bit 8k + d (about 41 VALU ops per slot);
+// for three or four slots, bit planes of the 32 bytes (about 60 ops once) and
+// 8 ops per slot.  out: the word of each slot.  With D[0..3] and D[4..7] two
+// separate 16-byte pieces, bits 0..15 of a word are the first piece's offsets
+// and bits 16..31 the second's.
+// One stage of the 8 x 8 bit transposes: rows d and d + SH (d without the SH bit) exchange the
+// bit columns b + SH of row d and b of row d + SH (b without the SH bit), in every byte lane.
+template <int SH>
+__device__ __forceinline__ void bc_butterfly(uint32_t (&E)[8], uint32_t msk)
+{
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+        if (d & SH)
+            continue;
+        const uint32_t t = ((E[d] >> SH) ^ E[d + SH]) & msk;
+        E[d + SH] ^= t;
+        E[d] ^= t << SH;
+    }
+}
+
+// Per slot and bit b, all ones when bit b of the slot's symbol is set (the bit-sliced build's masks),
+// computed once per kernel as wave-uniform values.
 template <int NS>
-__device__ __forceinline__ void bc_build_word(const uint32_t (&D)[8], uint32_t syms, uint32_t *dst, uint32_t stride)
+struct BcPlaneMasks {
+    uint32_t c[NS][8];
+};
+
+template <int NS>
+__device__ __forceinline__ BcPlaneMasks<NS> bc_plane_masks(uint32_t syms)
+{
+    BcPlaneMasks<NS> pm;
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            uint32_t v = (uint32_t)__builtin_amdgcn_readfirstlane((int)(0u - ((syms >> (8 * s + b)) & 1u)));
+            // opaque to the optimiser (no instruction): otherwise it knows v is 0 or ~0 and turns each
+            // XOR with it into a scalar compare and a select, twice the vector ops
+            asm("" : "+s"(v));
+            pm.c[s][b] = v;
+        }
+    return pm;
+}
+
+template <int NS>
+__device__ __forceinline__ void bc_build_word(const uint32_t (&D)[8], uint32_t syms, const BcPlaneMasks<NS> &pm,
+                                              uint32_t (&out)[NS])
 {
     uint32_t E[8];
 #pragma unroll
@@ -1586,17 +1630,36 @@ __device__ __forceinline__ void bc_build_word(const uint32_t (&D)[8], uint32_t s
         E[4 * h + 2] = __builtin_amdgcn_perm(cdhi, abhi, 0x05040100u);
         E[4 * h + 3] = __builtin_amdgcn_perm(cdhi, abhi, 0x07060302u);
     }
+    if constexpr (NS >= 3) {
+        // three or four slots: bit-slice once, then 8 ops per slot.  Three butterfly stages
+        // transpose the 8 x 8 bit matrix of each byte lane across E[0..7] (rows: E index, columns:
+        // bit within the byte), after which bit 8k + d of E[b] is bit b of the byte at offset 8k + d:
+        // E[b] is the word's plane of bit b.  A byte matches symbol c where every plane agrees with
+        // c's bit.
+        bc_butterfly<4>(E, 0x0F0F0F0Fu);
+        bc_butterfly<2>(E, 0x33333333u);
+        bc_butterfly<1>(E, 0x55555555u);
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        const uint32_t rep = ((syms >> (8 * s)) & 0xFFu) * 0x01010101u;
-        uint32_t miss = 0;
+        for (int s = 0; s < NS; ++s) {
+            uint32_t miss = 0;
 #pragma unroll
-        for (int d = 0; d < 8; ++d) {
-            const uint32_t x = E[d] ^ rep;
-            const uint32_t y = ((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x;  // bit 8k + 7: byte k differs
-            miss |= __builtin_amdgcn_alignbit(y, y, 7u - (uint32_t)d) & (0x01010101u << d);
+            for (int b = 0; b < 8; ++b)
+                miss |= E[b] ^ pm.c[s][b];
+            out[s] = ~miss;
         }
-        dst[s * stride] = ~miss;
+    } else {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const uint32_t rep = ((syms >> (8 * s)) & 0xFFu) * 0x01010101u;
+            uint32_t miss = 0;
+#pragma unroll
+            for (int d = 0; d < 8; ++d) {
+                const uint32_t x = E[d] ^ rep;
+                const uint32_t y = ((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x;  // bit 8k + 7: byte k differs
+                miss |= __builtin_amdgcn_alignbit(y, y, 7u - (uint32_t)d) & (0x01010101u << d);
+            }
+            out[s] = ~miss;
+        }
     }
 }
 
@@ -1694,6 +1757,11 @@ __global__ __launch_bounds__(kWG) void k_count_bitmap(BmCountArgs a)
     auto tile_of = [&](uint64_t i) {
         return (((uint64_t)blockIdx.x + (i >> a.chunk_log2) * gridDim.x) << a.chunk_log2) + (i & kmask);
     };
+    // Wave w of the workgroup builds words 64 (w + 4c) .. + 63 (c < CPW), i.e. 2 KiB of the tile
+    // per c: lane L loads its 16-byte pieces L and 64 + L of those 2 KiB, so that each load
+    // instruction of the wave reads 1 KiB contiguously (whole cache lines), and builds the half
+    // words of both.
+    const uint32_t wave16 = tid & ~63u;  // 64 * w
     uint32_t X[CPW][8];
     // a tile wholly inside the text loads without per-chunk bound tests (a wave-uniform branch)
     auto load_tile = [&](uint64_t ts) {
@@ -1701,8 +1769,8 @@ __global__ __launch_bounds__(kWG) void k_count_bitmap(BmCountArgs a)
         if (ts + 32ull * W <= a.tv.end16) {
 #pragma unroll
             for (int c = 0; c < CPW; ++c) {
-                const uint8_t *q = tb + 32u * (tid + kWG * c);
-                const uint4 lo = load16<STREAM>(q), hi = load16<STREAM>(q + 16);
+                const uint8_t *q = tb + 32u * (wave16 + kWG * c) + 16u * lane;
+                const uint4 lo = load16<STREAM>(q), hi = load16<STREAM>(q + 1024);
                 X[c][0] = lo.x, X[c][1] = lo.y, X[c][2] = lo.z, X[c][3] = lo.w;
                 X[c][4] = hi.x, X[c][5] = hi.y, X[c][6] = hi.z, X[c][7] = hi.w;
             }
@@ -1710,9 +1778,9 @@ __global__ __launch_bounds__(kWG) void k_count_bitmap(BmCountArgs a)
         }
 #pragma unroll
         for (int c = 0; c < CPW; ++c) {
-            const uint64_t u = ts + 32ull * (tid + kWG * c);
+            const uint64_t u = ts + 32ull * (wave16 + kWG * c) + 16u * lane;
             const uint4 lo = u < a.tv.end16 ? load16<STREAM>(a.tv.base + u) : make_uint4(0, 0, 0, 0);
-            const uint4 hi = u + 16u < a.tv.end16 ? load16<STREAM>(a.tv.base + u + 16u) : make_uint4(0, 0, 0, 0);
+            const uint4 hi = u + 1024u < a.tv.end16 ? load16<STREAM>(a.tv.base + u + 1024u) : make_uint4(0, 0, 0, 0);
             X[c][0] = lo.x, X[c][1] = lo.y, X[c][2] = lo.z, X[c][3] = lo.w;
             X[c][4] = hi.x, X[c][5] = hi.y, X[c][6] = hi.z, X[c][7] = hi.w;
         }
@@ -1723,6 +1791,7 @@ __global__ __launch_bounds__(kWG) void k_count_bitmap(BmCountArgs a)
     for (int c = 0; c < CPW; ++c)
         inner[c] = tid + kWG * c < W - a.halo_words ? 0xFFFFFFFFu : 0u;
     const uint32_t ent0 = bc_entries<NS, W>(a, 0, lane);
+    const BcPlaneMasks<NS> pm = bc_plane_masks<NS>(a.syms);
     const uint32_t r = min(a.r, a.m);
     uint32_t acc = 0;
     uint64_t tile = tile_of(0);
@@ -1732,8 +1801,17 @@ __global__ __launch_bounds__(kWG) void k_count_bitmap(BmCountArgs a)
         const uint64_t ts = tile * S;
         uint32_t *buf = bml + (i & 1u) * (NS * W);
 #pragma unroll
-        for (int c = 0; c < CPW; ++c)
-            bc_build_word<NS>(X[c], a.syms, buf + tid + kWG * c, W);
+        for (int c = 0; c < CPW; ++c) {
+            uint32_t wd[NS];
+            bc_build_word<NS>(X[c], a.syms, pm, wd);
+            // half words (16 starts each) 2 (wave16 + kWG c) + lane and + 64 of every slot
+            uint16_t *hb = reinterpret_cast<uint16_t *>(buf) + 2u * (wave16 + kWG * c) + lane;
+#pragma unroll
+            for (int sl = 0; sl < NS; ++sl) {
+                hb[2u * W * sl] = (uint16_t)wd[sl];
+                hb[2u * W * sl + 64u] = (uint16_t)(wd[sl] >> 16);
+            }
+        }
         const uint64_t next = tile_of(i + 1);
         if (next < a.ntiles)
             load_tile(next * S);
