@@ -17,6 +17,7 @@ from __future__ import annotations
 
 import array
 import ctypes
+from operator import itemgetter
 from typing import Iterable, Sequence
 
 import numpy as np
@@ -341,9 +342,8 @@ def _marshal_batch(texts, queries, use_hist: bool):
     qarr = np.zeros(max(nq, 1), dtype=_QUERY_DT)
     if nq:
         sizes = set(map(len, qs))
-        cols = list(zip(*qs)) if len(sizes) == 1 else None   # column-wise in C when all queries agree
-        tids = cols[0] if cols else [q[0] for q in qs]
-        raw = cols[1] if cols else [q[1] for q in qs]
+        tids = list(map(itemgetter(0), qs))         # column-wise in C (twice as fast as zip(*qs))
+        raw = list(map(itemgetter(1), qs))
         if set(map(type, raw)) == {bytes}:          # fast path: one join, no per-pattern arrays
             blob = np.frombuffer(b"".join(raw) or b"\0", dtype=np.uint8)
             lens = np.frombuffer(array.array("Q", map(len, raw)), dtype=np.uint64)
@@ -352,10 +352,11 @@ def _marshal_batch(texts, queries, use_hist: bool):
             lens = np.fromiter((p.size for p in pats), dtype=np.uint64, count=nq)
             blob = np.concatenate(pats) if int(lens.sum()) else np.zeros(1, dtype=np.uint8)
         keep.append(blob)
-        offs = np.zeros(nq, dtype=np.uint64)
+        offs = np.empty(nq, dtype=np.uint64)
+        offs[0] = 0
         np.cumsum(lens[:-1], out=offs[1:])
         qarr["text_id"][:nq] = np.frombuffer(array.array("q", tids), dtype=np.int64).astype(np.uint32)
-        qarr["p"][:nq] = np.where(lens > 0, np.uint64(blob.ctypes.data) + offs, 0)
+        qarr["p"][:nq] = offs + np.uint64(blob.ctypes.data)   # an empty pattern is rejected whatever p is
         qarr["m"][:nq] = lens
         for i, q in (enumerate(qs) if max(sizes) > 2 else ()):   # queries with their own order
             if len(q) > 2 and q[2] is not None:

@@ -1428,14 +1428,13 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
     // ---- single-query chunks of counting batches go to deals of up to 2^kChunkLog2 tiles (one
     // record per deal); the rest form one global tile space
     std::vector<uint32_t> solo_q;     // per single-query chunk: its index in `staged`
-    std::vector<BatchDeal> solo;      // deals (tiles of one single-query chunk)
+    std::vector<uint64_t> solo_tiles; // per single-query chunk: its tiles
+    std::vector<uint64_t> solo_deal0; // per single-query chunk: its first deal (deals are written later)
+    uint64_t ndeals = 0;
     if (!rep) {
-        uint64_t est = 0;
-        for (auto &c : chunks)
-            if (c.q1 - c.q0 == 1)
-                est += ceil_div(texts[c.text].n + 16, T << kChunkLog2);
-        solo.reserve(est);
         solo_q.reserve(chunks.size());
+        solo_tiles.reserve(chunks.size());
+        solo_deal0.reserve(chunks.size());
     }
     uint32_t deal_halo = 16;
     uint64_t deal_bytes = 0;
@@ -1449,9 +1448,9 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
             const uint64_t ntiles = ceil_div((reinterpret_cast<uintptr_t>(tx.t) & 15u) + tx.n - c.m_min + 1, T);
             if (ntiles >= (1ull << 29))
                 return fail(SM_EINVAL, "batch text too long for a tile index");
-            for (uint64_t k0 = 0; k0 < ntiles; k0 += 1ull << kChunkLog2)
-                solo.push_back({(uint32_t)solo_q.size(),
-                                (uint32_t)(k0 << 3) | (uint32_t)std::min<uint64_t>(ntiles - k0, 1ull << kChunkLog2)});
+            solo_deal0.push_back(ndeals);
+            solo_tiles.push_back(ntiles);
+            ndeals += ceil_div(ntiles, 1ull << kChunkLog2);
             solo_q.push_back(c.q0);
             deal_halo = std::max(deal_halo, halo_for(c.m_max));
             deal_bytes += ntiles * T;
@@ -1520,7 +1519,7 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
         return fail(SM_EINVAL, "batch too large: pattern bytes in bitmap mode exceed 2^32");
     const size_t o_reports = o_bsteps + round_up(total_bm_steps * sizeof(uint32_t), 256);
     const size_t o_deals = o_reports + (rep ? round_up(std::max<size_t>(staged.size(), 1) * sizeof(BatchReport), 256) : 0);
-    const size_t o_solos = o_deals + round_up(solo.size() * sizeof(BatchDeal), 256);
+    const size_t o_solos = o_deals + round_up(ndeals * sizeof(BatchDeal), 256);
     const size_t bytes = o_solos + round_up(solo_q.size() * sizeof(BatchSolo), 256);
     uint8_t *uhost = nullptr, *udev = nullptr;
     SM_TRY(alloc(bytes, &uhost, &udev));
@@ -1665,21 +1664,30 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
         return fail(SM_ENOMEM, "batch planning ran out of host memory");
     std::vector<uint64_t> long_steps_off(st_off.begin() + n_st, st_off.end());
     {
-        std::copy(solo.begin(), solo.end(), reinterpret_cast<BatchDeal *>(uhost + o_deals));
+        // each single-query chunk's deals (runs of up to 2^kChunkLog2 of its tiles) and its record
+        BatchDeal *hdeal = reinterpret_cast<BatchDeal *>(uhost + o_deals);
         BatchSolo *hso = reinterpret_cast<BatchSolo *>(uhost + o_solos);
-        for (size_t i = 0; i < solo_q.size(); ++i) {
-            const BatchQuery &bq = hq[solo_q[i]];
-            const PlanQuery &pq = staged[solo_q[i]];
-            BatchSolo S{};
-            S.tv = make_view(texts[pq.text].t, texts[pq.text].n);
-            S.last = bq.last;
-            S.steps = reinterpret_cast<const uint64_t *>(udev + o_steps) + bq.steps_off;
-            S.halo = halo_for(pq.m);
-            S.m = bq.m;
-            S.r = bq.r;
-            S.out = bq.out;
-            hso[i] = S;
-        }
+        const bool filled = parallel_for(solo_q.size(), [&](size_t i0, size_t i1) {
+            for (size_t i = i0; i < i1; ++i) {
+                const BatchQuery &bq = hq[solo_q[i]];
+                const PlanQuery &pq = staged[solo_q[i]];
+                BatchSolo S{};
+                S.tv = make_view(texts[pq.text].t, texts[pq.text].n);
+                S.last = bq.last;
+                S.steps = reinterpret_cast<const uint64_t *>(udev + o_steps) + bq.steps_off;
+                S.halo = halo_for(pq.m);
+                S.m = bq.m;
+                S.r = bq.r;
+                S.out = bq.out;
+                hso[i] = S;
+                BatchDeal *dp = hdeal + solo_deal0[i];
+                for (uint64_t k0 = 0; k0 < solo_tiles[i]; k0 += 1ull << kChunkLog2)
+                    *dp++ = {(uint32_t)i,
+                             (uint32_t)(k0 << 3) | (uint32_t)std::min<uint64_t>(solo_tiles[i] - k0, 1ull << kChunkLog2)};
+            }
+        });
+        if (!filled)
+            return fail(SM_ENOMEM, "batch planning ran out of host memory");
     }
     {
         size_t k = 0;
@@ -1716,13 +1724,13 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
     lp->st_grid = std::max<uint64_t>(1, std::min<uint64_t>(ceil_div(tile_chunk.size(), 1ull << kChunkLog2), target));
     lp->o_deals = o_deals;
     lp->o_solos = o_solos;
-    lp->ndeals = solo.size();
+    lp->ndeals = ndeals;
     lp->deal_halo = deal_halo;
     // deals differ in length (texts' last deals are partial): twice the resident workgroups, dealt
     // round robin, let the ones that finish early take over the rest (measured 0.58 -> 0.51 ms on
     // 4,096 texts of 4 KiB - 4 MiB)
     lp->deal_grid = std::max<uint64_t>(
-        1, std::min<uint64_t>(solo.size(), (uint64_t)std::max(d.cus, 1) * deal_wpc));
+        1, std::min<uint64_t>(ndeals, (uint64_t)std::max(d.cus, 1) * deal_wpc));
     lp->deal_stream = deal_bytes >= kStreamLoadBytes;
     for (size_t i = 0; i < longq.size(); ++i) {
         const PlanQuery &pq = longq[i];
