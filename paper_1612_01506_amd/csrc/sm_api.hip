@@ -1014,6 +1014,7 @@ struct PlanQuery {
     uint32_t text;
     uint64_t m;
     uint32_t bucket;  // halo (byte tiles) or pattern-length (bitmaps) bucket
+    uint64_t first = 0;  // bitmap queries: symbol << 32 | word of the first compare (sort key)
 };
 
 // A text of at least kSoloMinBytes with at most kSoloMaxQueries byte-tile queries runs them
@@ -1397,7 +1398,31 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
         return a.text != b.text ? a.text < b.text : a.bucket < b.bucket;
     };
     std::stable_sort(staged.begin(), staged.end(), by_text_bucket);
-    std::stable_sort(bmq.begin(), bmq.end(), by_text_bucket);
+    // bitmap queries: within a text and bucket, sorted by the symbol and the 32-position word of
+    // their first compare, so that the 8 queries run in lock step mostly read the same bitmap words
+    // for it (the kernel then loads them once).  The first compare of the frequency order is the
+    // first position of the pattern's least frequent symbol; of a given order, its first entry.
+    if (!parallel_for(bmq.size(), [&](size_t k0, size_t k1) {
+            for (size_t k = k0; k < k1; ++k) {
+                const sm_query &Q = q[bmq[k].idx];
+                uint64_t j0 = 0;
+                if (Q.order) {
+                    j0 = (uint64_t)Q.order[0];
+                } else {
+                    const uint64_t *h = texts[Q.text_id].hist;
+                    for (uint64_t j = 1; j < Q.m; ++j)
+                        if (h[Q.p[j]] < h[Q.p[j0]])
+                            j0 = j;
+                }
+                bmq[k].first = ((uint64_t)Q.p[j0] << 32) | (j0 >> 5);
+            }
+        }))
+        return fail(SM_ENOMEM, "batch planning ran out of host memory");
+    std::stable_sort(bmq.begin(), bmq.end(), [](const PlanQuery &a, const PlanQuery &b) {
+        if (a.text != b.text)
+            return a.text < b.text;
+        return a.bucket != b.bucket ? a.bucket < b.bucket : a.first < b.first;
+    });
 
     struct Chunk {
         uint32_t text;

@@ -1456,14 +1456,36 @@ __device__ __forceinline__ void batch_bitmap(const BmArgs &a)
                     mr[i] = readlane(rv, (uint32_t)i * kBmRecWords);
                     rmin = min(rmin, mr[i] >> 24);
                 }
-                // the first compare sets f; on edge tiles it is then masked to the query's valid starts
+                // the first compare sets f; on edge tiles it is then masked to the query's valid starts.
+                // When the group's K first compares read the same two words per lane (same slot and
+                // j / 32: the planner sorts a chunk's queries by that key, so most groups do), the
+                // words are loaded once and only the shifts differ.
+                uint32_t e0[K];
+                bool shared = true;
 #pragma unroll
                 for (int i = 0; i < K; ++i) {
-                    const uint32_t e = readlane(rv, (uint32_t)i * kBmRecWords + 2u);
-                    const uint32_t *w = reinterpret_cast<const uint32_t *>(bmb + (e >> 5) + lane4);
+                    e0[i] = readlane(rv, (uint32_t)i * kBmRecWords + 2u);
+                    shared &= (e0[i] >> 7) == (e0[0] >> 7);
+                }
+                if (shared) {
+                    const uint32_t *w = reinterpret_cast<const uint32_t *>(bmb + (e0[0] >> 5) + lane4);
+                    uint32_t lo[kBmV], hi[kBmV];
 #pragma unroll
                     for (int v = 0; v < kBmV; ++v)
-                        f[i][v] = __builtin_amdgcn_alignbit(w[64 * v + 1], w[64 * v], e);
+                        lo[v] = w[64 * v], hi[v] = w[64 * v + 1];
+#pragma unroll
+                    for (int i = 0; i < K; ++i)
+#pragma unroll
+                        for (int v = 0; v < kBmV; ++v)
+                            f[i][v] = __builtin_amdgcn_alignbit(hi[v], lo[v], e0[i]);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < K; ++i) {
+                        const uint32_t *w = reinterpret_cast<const uint32_t *>(bmb + (e0[i] >> 5) + lane4);
+#pragma unroll
+                        for (int v = 0; v < kBmV; ++v)
+                            f[i][v] = __builtin_amdgcn_alignbit(w[64 * v + 1], w[64 * v], e0[i]);
+                    }
                 }
                 if (!inner) {
 #pragma unroll
