@@ -530,15 +530,43 @@ struct PatSyms {
 
 PatSyms pattern_syms(const uint8_t *p, uint64_t m)
 {
+    // eight pattern bytes at a time: a byte differs from all kept symbols when its high bit stays
+    // set in the AND over the symbols of ((v & 0x7F) + 0x7F) | v, v = byte ^ symbol (exact, no
+    // carries between bytes); the lowest such byte is the next new symbol
+    constexpr uint64_t kOnes = 0x0101010101010101ull, kLow7 = 0x7F7F7F7F7F7F7F7Full, kHigh = 0x8080808080808080ull;
     PatSyms ps;
-    for (uint64_t j = 0; j < m && ps.ns <= kBcMaxSyms; ++j) {
-        bool seen = false;
-        for (uint32_t c = 0; c < ps.ns; ++c)
-            seen |= ((ps.packed >> (8 * c)) & 0xFFu) == p[j];
-        if (!seen) {
-            if (ps.ns < kBcMaxSyms)
-                ps.packed |= (uint32_t)p[j] << (8 * ps.ns);
-            ++ps.ns;
+    if (m == 0)
+        return ps;
+    uint64_t rep[kBcMaxSyms];
+    for (auto &r : rep)
+        r = kOnes * p[0];
+    ps.packed = p[0];
+    ps.ns = 1;
+    // the last word ends at byte m - 1 (bytes read twice are already kept); under 8 bytes, the
+    // word is padded with the first symbol
+    const uint64_t nw = m >= 8 ? (m + 7) / 8 : 1;
+    for (uint64_t w = 0; w < nw; ++w) {
+        uint64_t x = rep[0];
+        if (m < 8)
+            for (uint64_t j = 0; j < m; ++j)
+                x = (x & ~(0xFFull << (8 * j))) | ((uint64_t)p[j] << (8 * j));
+        else
+            std::memcpy(&x, p + std::min<uint64_t>(8 * w, m - 8), 8);
+        while (true) {
+            uint64_t miss = kHigh;
+            for (uint32_t c = 0; c < kBcMaxSyms; ++c) {
+                const uint64_t v = x ^ rep[c];
+                miss &= ((v & kLow7) + kLow7) | v;
+            }
+            if (!miss)
+                break;
+            if (ps.ns == kBcMaxSyms) {
+                ps.ns = kBcMaxSyms + 1;
+                return ps;
+            }
+            const uint8_t b = (uint8_t)(x >> (__builtin_ctzll(miss) & ~7u));
+            ps.packed |= (uint32_t)b << (8 * ps.ns);
+            rep[ps.ns++] = kOnes * b;
         }
     }
     return ps;
@@ -1082,6 +1110,12 @@ struct LaunchPlan {
     uint32_t deal_halo = 16;
     uint64_t deal_grid = 0;
     bool deal_stream = false;
+    // single-query chunks on texts of at most 4 symbols: bitmap deals
+    size_t o_bmdeals = 0, o_bmsolos = 0;
+    uint64_t n_bmdeals = 0;
+    uint32_t bm_deal_halo = 1;
+    uint64_t bm_deal_grid = 0;
+    bool bm_deal_stream = false;
     // byte-tile launch
     uint64_t ntiles = 0;
     uint32_t halo_max = 0;
@@ -1204,7 +1238,7 @@ private:
                 done_cv_.notify_all();
         }
     }
-    static constexpr size_t kThreads = 8;
+    static constexpr size_t kThreads = 16;
     std::vector<std::thread> workers_;
     std::mutex run_mu_, mu_;
     std::condition_variable cv_, done_cv_;
@@ -1217,7 +1251,7 @@ private:
 // Runs body(begin, end) over [0, n) in contiguous ranges, on the planning
 // threads when n is large enough to pay for them.  Returns false if any range
 // threw (host memory exhaustion); the ranges are then incomplete.
-constexpr size_t kPlanPerPart = 256;
+constexpr size_t kPlanPerPart = 128;
 template <typename F>
 bool parallel_for(size_t n, const F &body)
 {
@@ -1281,16 +1315,26 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
     const int wpc_long = wpc_given ? wpc : 6;
     const uint64_t deal_wpc = wpc_given ? (uint64_t)wpc : (bt && bt->deal_wgs_per_cu > 0) ? (uint64_t)bt->deal_wgs_per_cu
                                                                                              : kDealsPerCu;
-    // alphabet class of a text with a histogram (symbols with a nonzero entry: <= 2, <= 4, <= 32, more)
+    // alphabet class of a text with a histogram (symbols with a nonzero entry: <= 2, <= 4, <= 32,
+    // more) and the histogram's total for the peel model, in one pass over each histogram
     std::vector<uint8_t> text_cls(nt, 3);
-    for (uint64_t t = 0; t < nt; ++t) {
-        if (!texts[t].hist)
-            continue;
-        int nsym = 0;
-        for (int b = 0; b < 256; ++b)
-            nsym += texts[t].hist[b] != 0;
-        text_cls[t] = nsym <= 2 ? 0 : nsym <= 4 ? 1 : nsym <= 32 ? 2 : 3;
-    }
+    std::vector<double> hsum(nt, 0.0);
+    if (!parallel_for(nt, [&](size_t t0, size_t t1) {
+            for (size_t t = t0; t < t1; ++t) {
+                const uint64_t *h = texts[t].hist;
+                if (!h)
+                    continue;
+                uint32_t nsym = 0;
+                uint64_t sum = 0;
+                for (int b = 0; b < 256; ++b) {
+                    nsym += h[b] != 0;
+                    sum += h[b];
+                }
+                text_cls[t] = nsym <= 2 ? 0 : nsym <= 4 ? 1 : nsym <= 32 ? 2 : 3;
+                hsum[t] = (double)sum;
+            }
+        }))
+        return fail(SM_ENOMEM, "batch planning ran out of host memory");
     auto bm_min_of = [&](uint64_t t) -> uint64_t {
         return (bt && bt->bm_min[text_cls[t]] > 0) ? (uint64_t)bt->bm_min[text_cls[t]] : kBmMinQueries;
     };
@@ -1463,11 +1507,41 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
     }
     uint32_t deal_halo = 16;
     uint64_t deal_bytes = 0;
+    // single-query chunks on texts whose histogram shows at most 4 symbols, with a pattern of at
+    // most 4 distinct symbols and a halo of at most half a tile: bitmap deals (8 KiB bitmap tiles)
+    std::vector<uint32_t> bms_q;       // index in `staged`
+    std::vector<uint32_t> bms_syms;    // distinct symbols, padded to 4 with the first
+    std::vector<uint64_t> bms_tiles, bms_deal0;
+    uint64_t n_bmdeals = 0, bm_deal_bytes = 0;
+    uint32_t bm_deal_halo = 1;
     // ---- byte-tile chunks in one global tile space
     std::vector<BatchChunk> bchunks_t;
     std::vector<uint32_t> tile_chunk;
     uint32_t halo_max = 16;
     for (auto &c : chunks) {
+        if (!rep && c.q1 - c.q0 == 1 && text_cls[c.text] <= 1) {
+            const sm_query &Q = q[staged[c.q0].idx];
+            const PatSyms sy = pattern_syms(Q.p, Q.m);
+            const uint32_t hw = (uint32_t)(((Q.m - 1) >> 5) + 1);
+            if (sy.ns <= kBcMaxSyms && hw <= kWG / 2) {
+                uint32_t packed = sy.packed;
+                for (uint32_t k = sy.ns; k < kBcMaxSyms; ++k)
+                    packed |= (sy.packed & 0xFFu) << (8 * k);
+                const sm_text &tx = texts[c.text];
+                const uint64_t last = (reinterpret_cast<uintptr_t>(tx.t) & 15u) + tx.n - Q.m;
+                const uint64_t ntiles = ceil_div(last + 1, 32ull * (kWG - hw));
+                if (ntiles >= (1ull << 29))
+                    return fail(SM_EINVAL, "batch text too long for a tile index");
+                bms_q.push_back(c.q0);
+                bms_syms.push_back(packed);
+                bms_tiles.push_back(ntiles);
+                bms_deal0.push_back(n_bmdeals);
+                n_bmdeals += ceil_div(ntiles, 1ull << kChunkLog2);
+                bm_deal_halo = std::max(bm_deal_halo, hw);
+                bm_deal_bytes += tx.n;
+                continue;
+            }
+        }
         if (!rep && c.q1 - c.q0 == 1) {
             const sm_text &tx = texts[c.text];
             const uint64_t ntiles = ceil_div((reinterpret_cast<uintptr_t>(tx.t) & 15u) + tx.n - c.m_min + 1, T);
@@ -1545,7 +1619,9 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
     const size_t o_reports = o_bsteps + round_up(total_bm_steps * sizeof(uint32_t), 256);
     const size_t o_deals = o_reports + (rep ? round_up(std::max<size_t>(staged.size(), 1) * sizeof(BatchReport), 256) : 0);
     const size_t o_solos = o_deals + round_up(ndeals * sizeof(BatchDeal), 256);
-    const size_t bytes = o_solos + round_up(solo_q.size() * sizeof(BatchSolo), 256);
+    const size_t o_bmdeals = o_solos + round_up(solo_q.size() * sizeof(BatchSolo), 256);
+    const size_t o_bmsolos = o_bmdeals + round_up(n_bmdeals * sizeof(BatchDeal), 256);
+    const size_t bytes = o_bmsolos + round_up(bms_q.size() * sizeof(BmSolo), 256);
     uint8_t *uhost = nullptr, *udev = nullptr;
     SM_TRY(alloc(bytes, &uhost, &udev));
     lp->bytes = bytes;
@@ -1569,20 +1645,10 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
     for (uint64_t i = 0; i < nq; ++i)
         if (!q[i].order && texts[q[i].text_id].hist)
             text_bytes[q[i].text_id] += q[i].m;
-    std::vector<double> hsum(nt, 0.0);  // histogram totals for the peel model
     const bool prepared = parallel_for(nt, [&](size_t t0, size_t t1) {
-        for (size_t t = t0; t < t1; ++t) {
-            if (!texts[t].hist)
-                continue;
-            if (text_bytes[t] >= kRanksMinBytes)
+        for (size_t t = t0; t < t1; ++t)
+            if (texts[t].hist && text_bytes[t] >= kRanksMinBytes)
                 ranks[t].reset(new FreqRanks(texts[t].hist));
-            if (!peel_given) {
-                uint64_t sum = 0;
-                for (int b = 0; b < 256; ++b)
-                    sum += texts[t].hist[b];
-                hsum[t] = (double)sum;
-            }
-        }
     });
     if (!prepared)
         return fail(SM_ENOMEM, "batch planning ran out of host memory");
@@ -1713,6 +1779,30 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
         });
         if (!filled)
             return fail(SM_ENOMEM, "batch planning ran out of host memory");
+        BatchDeal *hbd = reinterpret_cast<BatchDeal *>(uhost + o_bmdeals);
+        BmSolo *hbms = reinterpret_cast<BmSolo *>(uhost + o_bmsolos);
+        const bool bfilled = parallel_for(bms_q.size(), [&](size_t i0, size_t i1) {
+            for (size_t i = i0; i < i1; ++i) {
+                const BatchQuery &bq = hq[bms_q[i]];
+                const PlanQuery &pq = staged[bms_q[i]];
+                BmSolo S{};
+                S.tv = make_view(texts[pq.text].t, texts[pq.text].n);
+                S.last = bq.last;
+                S.steps = reinterpret_cast<const uint64_t *>(udev + o_steps) + bq.steps_off;
+                S.m = bq.m;
+                S.r = bq.r;
+                S.syms = bms_syms[i];
+                S.halo_words = (uint32_t)(((pq.m - 1) >> 5) + 1);
+                S.out = bq.out;
+                hbms[i] = S;
+                BatchDeal *dp = hbd + bms_deal0[i];
+                for (uint64_t k0 = 0; k0 < bms_tiles[i]; k0 += 1ull << kChunkLog2)
+                    *dp++ = {(uint32_t)i,
+                             (uint32_t)(k0 << 3) | (uint32_t)std::min<uint64_t>(bms_tiles[i] - k0, 1ull << kChunkLog2)};
+            }
+        });
+        if (!bfilled)
+            return fail(SM_ENOMEM, "batch planning ran out of host memory");
     }
     {
         size_t k = 0;
@@ -1757,6 +1847,12 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
     lp->deal_grid = std::max<uint64_t>(
         1, std::min<uint64_t>(ndeals, (uint64_t)std::max(d.cus, 1) * deal_wpc));
     lp->deal_stream = deal_bytes >= kStreamLoadBytes;
+    lp->o_bmdeals = o_bmdeals;
+    lp->o_bmsolos = o_bmsolos;
+    lp->n_bmdeals = n_bmdeals;
+    lp->bm_deal_halo = bm_deal_halo;
+    lp->bm_deal_grid = std::max<uint64_t>(1, std::min<uint64_t>(n_bmdeals, (uint64_t)std::max(d.cus, 1) * deal_wpc));
+    lp->bm_deal_stream = bm_deal_bytes >= kStreamLoadBytes;
     for (size_t i = 0; i < longq.size(); ++i) {
         const PlanQuery &pq = longq[i];
         LaunchPlan::Long L;
@@ -1809,6 +1905,14 @@ int launch_plan(Dev &d, const LaunchPlan &lp, const uint8_t *dev, unsigned long 
         a.counts = counts;
         a.halo_max = lp.deal_halo;
         HIP_TRY(launch_batch_deals(a, lp.cpl, lp.deal_stream, (unsigned)lp.deal_grid, s));
+    }
+    if (lp.n_bmdeals) {
+        BmDealArgs a{};
+        a.deals = reinterpret_cast<const BatchDeal *>(dev + lp.o_bmdeals);
+        a.solos = reinterpret_cast<const BmSolo *>(dev + lp.o_bmsolos);
+        a.ndeals = lp.n_bmdeals;
+        a.counts = counts;
+        HIP_TRY(launch_bm_deals(a, lp.bm_deal_halo, lp.bm_deal_stream, (unsigned)lp.bm_deal_grid, s));
     }
     if (lp.ntiles) {
         BatchArgs a{};

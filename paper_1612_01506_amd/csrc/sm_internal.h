@@ -195,12 +195,35 @@ struct BmCountArgs {
     uint32_t pad;
 };
 
+// Batched single-query texts through 8 KiB bitmap tiles: a query's record (its tiles have
+// 32 * (kWG - halo_words) starts) and deals (BatchDeal: record index, first tile << 3 | tiles).
+struct BmSolo {
+    TextView tv;
+    uint64_t last;             // coordinate of the query's last valid start
+    const uint64_t *steps;     // its step table
+    uint32_t m;
+    uint32_t r;                // peel factor, 1..min(kMaxPeel, m)
+    uint32_t syms;             // its distinct symbols, padded to kBcMaxSyms by repeating the first
+    uint32_t halo_words;       // ((m - 1) >> 5) + 1, at most kWG / 2
+    uint32_t out;              // output slot
+    uint32_t pad;
+};
+
+struct BmDealArgs {
+    const BatchDeal *deals;
+    const BmSolo *solos;
+    uint64_t ndeals;
+    unsigned long long *counts;
+};
+
 // Host-side launchers (sm_kernels.hip).  Each returns a hipError_t.
 // stream_loads: tile loads with the non-temporal cache policy (texts far larger than the last-level cache)
 hipError_t launch_count_staged(const CountArgs &a, int cpl, int r, bool stream_loads, unsigned grid, hipStream_t s);
 hipError_t launch_count_global(const CountArgs &a, int r, unsigned grid, hipStream_t s);
 // ns: distinct pattern symbols (1..kBcMaxSyms); cpw: bitmap words per thread and tile (1, 2 or 4)
 hipError_t launch_count_bitmap(const BmCountArgs &a, int ns, int cpw, bool stream_loads, unsigned grid, hipStream_t s);
+// halo_max: the largest halo_words of the deals' records (LDS pad)
+hipError_t launch_bm_deals(const BmDealArgs &a, uint32_t halo_max, bool stream_loads, unsigned grid, hipStream_t s);
 hipError_t launch_scan_groups(const unsigned long long *gs, uint64_t ngroups, unsigned long long *go,
                               unsigned long long *total, hipStream_t s);
 hipError_t launch_report_write(const CountArgs &a, uint32_t *bc, unsigned long long *gs, const unsigned long long *go,

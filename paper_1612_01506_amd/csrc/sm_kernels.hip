@@ -30,10 +30,16 @@
 //     non-temporal policy.
 //   * Counts: 32-bit lane accumulators, DPP wave reductions, one LDS
 //     reduction and one 64-bit atomicAdd per workgroup.
+//   * Small alphabets: a single search may instead build, per tile, one bitmap
+//     per distinct pattern symbol from the text bytes held in registers (byte
+//     transposes, then byte-equality tests or bit planes), after which every
+//     compare is a funnel shift and AND over 32 starts.
 //   * Batches: byte-tile kernels run many queries over one staged tile (or one
 //     query over runs of tiles, with a record per run), and the bitmap kernel
 //     turns every compare of every query into a funnel shift and AND over
 //     per-tile symbol bitmaps (one SIMDcompare per symbol and tile, shared).
+//     A lone query on a text of at most 4 symbols takes runs of bitmap tiles
+//     the same way (the single search's bitmap tile code, one record per run).
 #include "sm_internal.h"
 
 namespace smk {
@@ -1757,17 +1763,142 @@ __device__ __forceinline__ void bc_verify(const BmCountArgs &a, const uint32_t *
     }
 }
 
+// The 32 text bytes of each word a thread builds, into registers.  Wave w of
+// the workgroup builds words 64 (w + 4c) .. + 63 (c < CPW), i.e. 2 KiB of the
+// tile per c: lane L loads its 16-byte pieces L and 64 + L of those 2 KiB, so
+// that each load instruction of the wave reads 1 KiB contiguously (whole cache
+// lines).  A tile wholly inside the text loads without per-chunk bound tests
+// (a wave-uniform branch); chunks at or past end16 read as zeros otherwise.
+template <int CPW, bool STREAM>
+__device__ __forceinline__ void bc_load_tile(const TextView &tv, uint64_t ts, uint32_t tid, uint32_t (&X)[CPW][8])
+{
+    constexpr uint32_t W = kWG * CPW;
+    const uint32_t lane = tid & 63u, wave16 = tid & ~63u;
+    if (ts + 32ull * W <= tv.end16) {
+        const uint8_t *tb = tv.base + ts;
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) {
+            const uint8_t *q = tb + 32u * (wave16 + kWG * c) + 16u * lane;
+            const uint4 lo = load16<STREAM>(q), hi = load16<STREAM>(q + 1024);
+            X[c][0] = lo.x, X[c][1] = lo.y, X[c][2] = lo.z, X[c][3] = lo.w;
+            X[c][4] = hi.x, X[c][5] = hi.y, X[c][6] = hi.z, X[c][7] = hi.w;
+        }
+        return;
+    }
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+        const uint64_t u = ts + 32ull * (wave16 + kWG * c) + 16u * lane;
+        const uint4 lo = u < tv.end16 ? load16<STREAM>(tv.base + u) : make_uint4(0, 0, 0, 0);
+        const uint4 hi = u + 1024u < tv.end16 ? load16<STREAM>(tv.base + u + 1024u) : make_uint4(0, 0, 0, 0);
+        X[c][0] = lo.x, X[c][1] = lo.y, X[c][2] = lo.z, X[c][3] = lo.w;
+        X[c][4] = hi.x, X[c][5] = hi.y, X[c][6] = hi.z, X[c][7] = hi.w;
+    }
+}
+
+// The tile's slot words from the loaded bytes, stored as half words (16 starts
+// each): 2 (wave16 + kWG c) + lane and + 64 of every slot of buf.
+template <int NS, int CPW>
+__device__ __forceinline__ void bc_build_tile(const uint32_t (&X)[CPW][8], uint32_t syms, const BcPlaneMasks<NS> &pm,
+                                              uint32_t *buf, uint32_t tid)
+{
+    constexpr uint32_t W = kWG * CPW;
+    const uint32_t lane = tid & 63u, wave16 = tid & ~63u;
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+        uint32_t wd[NS];
+        bc_build_word<NS>(X[c], syms, pm, wd);
+        uint16_t *hb = reinterpret_cast<uint16_t *>(buf) + 2u * (wave16 + kWG * c) + lane;
+#pragma unroll
+        for (int sl = 0; sl < NS; ++sl) {
+            hb[2u * W * sl] = (uint16_t)wd[sl];
+            hb[2u * W * sl + 64u] = (uint16_t)(wd[sl] >> 16);
+        }
+    }
+}
+
+// Algorithm 4 over the thread's CPW words of a built tile: its starts at tile
+// offsets [lo, hi) (of S; `inner` masks the words with starts when lo = 0 and
+// hi = S), the first r compares unconditionally, then the zero test
+// (wave-wide) after each of the next kTestEach compares and after each group
+// of kGroup later ones, as in the byte-tile kernel; a handful of starts facing
+// kVerifyMin or more further compares are verified one at a time across the
+// lanes.  Entries of the first 64 compares are in ent0 (readlane); later ones
+// are computed per block of 64 when reached.  Returns the thread's matches.
+template <int NS, int CPW>
+__device__ __forceinline__ uint32_t bc_search_tile(const BmCountArgs &a, const uint32_t *buf, uint32_t ent0,
+                                                   uint32_t tid, uint32_t lo, uint32_t hi, uint32_t S,
+                                                   const uint32_t (&inner)[CPW])
+{
+    constexpr uint32_t W = kWG * CPW;
+    const uint32_t lane = tid & 63u;
+    const uint32_t r = min(a.r, a.m);
+    uint32_t f[CPW];
+    bc_step<CPW, true>(buf, readlane(ent0, 0), tid, f);
+    if (lo == 0u && hi == S) {
+#pragma unroll
+        for (int c = 0; c < CPW; ++c)
+            f[c] &= inner[c];
+    } else {
+#pragma unroll
+        for (int c = 0; c < CPW; ++c)
+            f[c] &= range_bits(32u * (tid + kWG * c), lo, hi);
+    }
+    uint32_t l = 1;
+    for (; l < r; ++l)
+        bc_step<CPW, false>(buf, readlane(ent0, l), tid, f);
+    uint32_t entx = 0, blk = 0;
+    auto entry = [&](uint32_t k) {
+        if (k < 64u)
+            return readlane(ent0, k);
+        if ((k >> 6) != blk) {
+            blk = k >> 6;
+            entx = bc_entries<NS, W>(a, blk, lane);
+        }
+        return readlane(entx, k & 63u);
+    };
+    const uint32_t l1 = min(a.m, l + kTestEach);
+    for (; l < l1 && bc_any(f); ++l)
+        bc_step<CPW, false>(buf, entry(l), tid, f);
+    bool grouped = false;
+    while (l < a.m && bc_any(f)) {
+        if (grouped && a.m - l >= kVerifyMin) {
+            uint32_t alive = 0;
+#pragma unroll
+            for (int c = 0; c < CPW; ++c)
+                alive += __popc(f[c]);
+            if (wave_sum32(alive) <= kVerifyMax) {
+                bc_verify<NS, CPW, W>(a, buf, l, tid, f);
+                break;
+            }
+        }
+        const uint32_t g = min(kGroup, a.m - l);
+#pragma unroll 1
+        for (uint32_t u = 0; u < g; ++u)
+            bc_step<CPW, false>(buf, entry(l + u), tid, f);
+        l += g;
+        grouped = true;
+    }
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < CPW; ++k)
+        c += __popc(f[k]);
+    return c;
+}
+
+// Valid starts of the tile at ts as tile offsets [lo, hi) (the tile holds at least one: last >= ts).
+__device__ __forceinline__ void bc_tile_range(const BmCountArgs &a, uint64_t ts, uint32_t S, uint32_t &lo,
+                                              uint32_t &hi)
+{
+    const uint64_t rem = a.last - ts;
+    hi = rem >= S ? S : (uint32_t)rem + 1u;
+    lo = ts < a.tv.first ? (uint32_t)(a.tv.first - ts) : 0u;
+}
+
 // Single search over bitmap tiles.  Tiles are dealt out as in the byte-tile
 // count kernel.  Thread tid owns words tid + kWG * c (c < CPW) of every tile:
-// it loads their 32 text bytes each into registers (the next tile's while the
-// current one is searched), builds their slot words into one of two LDS
-// buffers, and after the barrier runs Algorithm 4 on its 32 * CPW starts: the
-// first r compares unconditionally, then the zero test (wave-wide) after each
-// of the next kTestEach compares and after each group of kGroup later ones, as
-// in the byte-tile kernel; a handful of starts facing kVerifyMin or more
-// further compares are verified one at a time across the lanes.  Entries of
-// the first 64 compares stay in a register and are taken with readlane; later
-// ones are computed per block of 64 when reached.
+// it loads their bytes into registers (the next tile's while the current one
+// is searched), builds their slot words into one of two LDS buffers, and after
+// the barrier searches its 32 * CPW starts.
 template <int NS, int CPW, bool STREAM>
 __global__ __launch_bounds__(kWG) void k_count_bitmap(BmCountArgs a)
 {
@@ -1779,34 +1910,7 @@ __global__ __launch_bounds__(kWG) void k_count_bitmap(BmCountArgs a)
     auto tile_of = [&](uint64_t i) {
         return (((uint64_t)blockIdx.x + (i >> a.chunk_log2) * gridDim.x) << a.chunk_log2) + (i & kmask);
     };
-    // Wave w of the workgroup builds words 64 (w + 4c) .. + 63 (c < CPW), i.e. 2 KiB of the tile
-    // per c: lane L loads its 16-byte pieces L and 64 + L of those 2 KiB, so that each load
-    // instruction of the wave reads 1 KiB contiguously (whole cache lines), and builds the half
-    // words of both.
-    const uint32_t wave16 = tid & ~63u;  // 64 * w
     uint32_t X[CPW][8];
-    // a tile wholly inside the text loads without per-chunk bound tests (a wave-uniform branch)
-    auto load_tile = [&](uint64_t ts) {
-        const uint8_t *tb = a.tv.base + ts;
-        if (ts + 32ull * W <= a.tv.end16) {
-#pragma unroll
-            for (int c = 0; c < CPW; ++c) {
-                const uint8_t *q = tb + 32u * (wave16 + kWG * c) + 16u * lane;
-                const uint4 lo = load16<STREAM>(q), hi = load16<STREAM>(q + 1024);
-                X[c][0] = lo.x, X[c][1] = lo.y, X[c][2] = lo.z, X[c][3] = lo.w;
-                X[c][4] = hi.x, X[c][5] = hi.y, X[c][6] = hi.z, X[c][7] = hi.w;
-            }
-            return;
-        }
-#pragma unroll
-        for (int c = 0; c < CPW; ++c) {
-            const uint64_t u = ts + 32ull * (wave16 + kWG * c) + 16u * lane;
-            const uint4 lo = u < a.tv.end16 ? load16<STREAM>(a.tv.base + u) : make_uint4(0, 0, 0, 0);
-            const uint4 hi = u + 1024u < a.tv.end16 ? load16<STREAM>(a.tv.base + u + 1024u) : make_uint4(0, 0, 0, 0);
-            X[c][0] = lo.x, X[c][1] = lo.y, X[c][2] = lo.z, X[c][3] = lo.w;
-            X[c][4] = hi.x, X[c][5] = hi.y, X[c][6] = hi.z, X[c][7] = hi.w;
-        }
-    };
     // inner tiles: every start of the words below W - halo_words is valid
     uint32_t inner[CPW];
 #pragma unroll
@@ -1814,86 +1918,77 @@ __global__ __launch_bounds__(kWG) void k_count_bitmap(BmCountArgs a)
         inner[c] = tid + kWG * c < W - a.halo_words ? 0xFFFFFFFFu : 0u;
     const uint32_t ent0 = bc_entries<NS, W>(a, 0, lane);
     const BcPlaneMasks<NS> pm = bc_plane_masks<NS>(a.syms);
-    const uint32_t r = min(a.r, a.m);
     uint32_t acc = 0;
     uint64_t tile = tile_of(0);
     if (tile < a.ntiles)
-        load_tile(tile * S);
+        bc_load_tile<CPW, STREAM>(a.tv, tile * S, tid, X);
     for (uint64_t i = 0; tile < a.ntiles; ++i) {
         const uint64_t ts = tile * S;
         uint32_t *buf = bml + (i & 1u) * (NS * W);
-#pragma unroll
-        for (int c = 0; c < CPW; ++c) {
-            uint32_t wd[NS];
-            bc_build_word<NS>(X[c], a.syms, pm, wd);
-            // half words (16 starts each) 2 (wave16 + kWG c) + lane and + 64 of every slot
-            uint16_t *hb = reinterpret_cast<uint16_t *>(buf) + 2u * (wave16 + kWG * c) + lane;
-#pragma unroll
-            for (int sl = 0; sl < NS; ++sl) {
-                hb[2u * W * sl] = (uint16_t)wd[sl];
-                hb[2u * W * sl + 64u] = (uint16_t)(wd[sl] >> 16);
-            }
-        }
+        bc_build_tile<NS, CPW>(X, a.syms, pm, buf, tid);
         const uint64_t next = tile_of(i + 1);
         if (next < a.ntiles)
-            load_tile(next * S);
+            bc_load_tile<CPW, STREAM>(a.tv, next * S, tid, X);
         __syncthreads();  // the tile's bitmaps are complete; the other buffer is no longer read
-        // valid starts as tile offsets [lo, hi) (tile < ntiles, so last >= ts)
-        const uint64_t rem = a.last - ts;
-        const uint32_t hi = rem >= S ? S : (uint32_t)rem + 1u;
-        const uint32_t lo = ts < a.tv.first ? (uint32_t)(a.tv.first - ts) : 0u;
-        uint32_t f[CPW];
-        bc_step<CPW, true>(buf, readlane(ent0, 0), tid, f);
-        if (lo == 0u && hi == S) {
-#pragma unroll
-            for (int c = 0; c < CPW; ++c)
-                f[c] &= inner[c];
-        } else {
-#pragma unroll
-            for (int c = 0; c < CPW; ++c)
-                f[c] &= range_bits(32u * (tid + kWG * c), lo, hi);
-        }
-        uint32_t l = 1;
-        for (; l < r; ++l)
-            bc_step<CPW, false>(buf, readlane(ent0, l), tid, f);
-        uint32_t entx = 0, blk = 0;
-        auto entry = [&](uint32_t k) {
-            if (k < 64u)
-                return readlane(ent0, k);
-            if ((k >> 6) != blk) {
-                blk = k >> 6;
-                entx = bc_entries<NS, W>(a, blk, lane);
-            }
-            return readlane(entx, k & 63u);
-        };
-        const uint32_t l1 = min(a.m, l + kTestEach);
-        for (; l < l1 && bc_any(f); ++l)
-            bc_step<CPW, false>(buf, entry(l), tid, f);
-        bool grouped = false;
-        while (l < a.m && bc_any(f)) {
-            if (grouped && a.m - l >= kVerifyMin) {
-                uint32_t alive = 0;
-#pragma unroll
-                for (int c = 0; c < CPW; ++c)
-                    alive += __popc(f[c]);
-                if (wave_sum32(alive) <= kVerifyMax) {
-                    bc_verify<NS, CPW, W>(a, buf, l, tid, f);
-                    break;
-                }
-            }
-            const uint32_t g = min(kGroup, a.m - l);
-#pragma unroll 1
-            for (uint32_t u = 0; u < g; ++u)
-                bc_step<CPW, false>(buf, entry(l + u), tid, f);
-            l += g;
-            grouped = true;
-        }
-#pragma unroll
-        for (int c = 0; c < CPW; ++c)
-            acc += __popc(f[c]);
+        uint32_t lo, hi;
+        bc_tile_range(a, ts, S, lo, hi);
+        acc += bc_search_tile<NS, CPW>(a, buf, ent0, tid, lo, hi, S, inner);
         tile = next;
     }
     wg_add_count(acc, a.count, tid);
+}
+
+// Batched single-query texts of at most kBcMaxSyms symbols, through bitmap
+// tiles of 8 KiB: a persistent grid takes deals (runs of up to 2^chunk_log2
+// tiles of one query's text) in order, as k_batch_deals does for byte tiles.
+// Each deal's query record gives the search's constants (slots padded to four
+// with repeats of the first symbol: a repeated slot holds the same bitmap).
+// The two bitmap buffers alternate by the workgroup's running tile count, so
+// the one barrier per tile also separates a deal's first build from the
+// previous deal's searches; each wave adds its matches to the query's count.
+template <bool STREAM>
+__global__ __launch_bounds__(kWG) void k_bm_deals(BmDealArgs a)
+{
+    extern __shared__ __align__(16) uint32_t bml[];
+    constexpr int NS = (int)kBcMaxSyms;
+    constexpr uint32_t W = kWG;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u;
+    uint32_t X[1][8];
+    uint64_t gi = 0;  // tiles this workgroup has built
+    for (uint64_t k = blockIdx.x; k < a.ndeals; k += gridDim.x) {
+        const BatchDeal d = ldc(&a.deals[k]);
+        const BmSolo so = ldc(&a.solos[d.solo]);
+        BmCountArgs q{};
+        q.tv = so.tv;
+        q.last = so.last;
+        q.steps = so.steps;
+        q.m = so.m;
+        q.r = so.r;
+        q.syms = so.syms;
+        q.halo_words = so.halo_words;
+        const uint32_t S = 32u * (W - q.halo_words);
+        const uint32_t inner[1] = {tid < W - q.halo_words ? 0xFFFFFFFFu : 0u};
+        const uint32_t ent0 = bc_entries<NS, W>(q, 0, lane);
+        const BcPlaneMasks<NS> pm = bc_plane_masks<NS>(q.syms);
+        const uint64_t t0 = d.tiles >> 3;
+        const uint32_t nt = d.tiles & 7u;
+        bc_load_tile<1, STREAM>(q.tv, t0 * S, tid, X);
+        uint32_t acc = 0;
+        for (uint32_t i = 0; i < nt; ++i, ++gi) {
+            const uint64_t ts = (t0 + i) * S;
+            uint32_t *buf = bml + (gi & 1u) * (NS * W);
+            bc_build_tile<NS, 1>(X, q.syms, pm, buf, tid);
+            if (i + 1u < nt)
+                bc_load_tile<1, STREAM>(q.tv, ts + S, tid, X);
+            __syncthreads();
+            uint32_t lo, hi;
+            bc_tile_range(q, ts, S, lo, hi);
+            acc += bc_search_tile<NS, 1>(q, buf, ent0, tid, lo, hi, S, inner);
+        }
+        const uint32_t c = wave_sum32(acc);
+        if (lane == 0 && c)
+            atomicAdd(&a.counts[so.out], (unsigned long long)c);
+    }
 }
 
 // ---------------------------------------------------------------- launchers
@@ -1990,6 +2085,16 @@ static hipError_t launch_bitmap_c(const BmCountArgs &a, int ns, int cpw, unsigne
     case 4: return launch_bitmap_n<4, STREAM>(a, ns, grid, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_bm_deals(const BmDealArgs &a, uint32_t halo_max, bool stream_loads, unsigned grid, hipStream_t s)
+{
+    const uint32_t lds = (2u * kBcMaxSyms * kWG + halo_max + 1u) * 4u;
+    if (stream_loads)
+        hipLaunchKernelGGL((k_bm_deals<true>), dim3(grid), dim3(kWG), lds, s, a);
+    else
+        hipLaunchKernelGGL((k_bm_deals<false>), dim3(grid), dim3(kWG), lds, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_count_bitmap(const BmCountArgs &a, int ns, int cpw, bool stream_loads, unsigned grid, hipStream_t s)
