@@ -1508,7 +1508,7 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
     uint32_t deal_halo = 16;
     uint64_t deal_bytes = 0;
     // single-query chunks on texts whose histogram shows at most 4 symbols, with a pattern of at
-    // most 4 distinct symbols and a halo of at most half a tile: bitmap deals (8 KiB bitmap tiles)
+    // most 4 distinct symbols and a halo of at most half a tile: bitmap deals (16 KiB bitmap tiles)
     std::vector<uint32_t> bms_q;       // index in `staged`
     std::vector<uint32_t> bms_syms;    // distinct symbols, padded to 4 with the first
     std::vector<uint64_t> bms_tiles, bms_deal0;
@@ -1523,13 +1523,13 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
             const sm_query &Q = q[staged[c.q0].idx];
             const PatSyms sy = pattern_syms(Q.p, Q.m);
             const uint32_t hw = (uint32_t)(((Q.m - 1) >> 5) + 1);
-            if (sy.ns <= kBcMaxSyms && hw <= kWG / 2) {
+            if (sy.ns <= kBcMaxSyms && hw <= kWG * kBmDealCpw / 2) {
                 uint32_t packed = sy.packed;
                 for (uint32_t k = sy.ns; k < kBcMaxSyms; ++k)
                     packed |= (sy.packed & 0xFFu) << (8 * k);
                 const sm_text &tx = texts[c.text];
                 const uint64_t last = (reinterpret_cast<uintptr_t>(tx.t) & 15u) + tx.n - Q.m;
-                const uint64_t ntiles = ceil_div(last + 1, 32ull * (kWG - hw));
+                const uint64_t ntiles = ceil_div(last + 1, 32ull * (kWG * kBmDealCpw - hw));
                 if (ntiles >= (1ull << 29))
                     return fail(SM_EINVAL, "batch text too long for a tile index");
                 bms_q.push_back(c.q0);

@@ -1939,21 +1939,22 @@ __global__ __launch_bounds__(kWG) void k_count_bitmap(BmCountArgs a)
 }
 
 // Batched single-query texts of at most kBcMaxSyms symbols, through bitmap
-// tiles of 8 KiB: a persistent grid takes deals (runs of up to 2^chunk_log2
-// tiles of one query's text) in order, as k_batch_deals does for byte tiles.
-// Each deal's query record gives the search's constants (slots padded to four
-// with repeats of the first symbol: a repeated slot holds the same bitmap).
-// The two bitmap buffers alternate by the workgroup's running tile count, so
-// the one barrier per tile also separates a deal's first build from the
-// previous deal's searches; each wave adds its matches to the query's count.
-template <bool STREAM>
+// tiles of 8 KiB x CPW: a persistent grid takes deals (runs of up to
+// 2^chunk_log2 tiles of one query's text) in order, as k_batch_deals does for
+// byte tiles.  Each deal's query record gives the search's constants (slots
+// padded to four with repeats of the first symbol: a repeated slot holds the
+// same bitmap).  The two bitmap buffers alternate by the workgroup's running
+// tile count, so the one barrier per tile also separates a deal's first build
+// from the previous deal's searches; each wave adds its matches to the query's
+// count.
+template <int CPW, bool STREAM>
 __global__ __launch_bounds__(kWG) void k_bm_deals(BmDealArgs a)
 {
     extern __shared__ __align__(16) uint32_t bml[];
     constexpr int NS = (int)kBcMaxSyms;
-    constexpr uint32_t W = kWG;
+    constexpr uint32_t W = kWG * CPW;
     const uint32_t tid = threadIdx.x, lane = tid & 63u;
-    uint32_t X[1][8];
+    uint32_t X[CPW][8];
     uint64_t gi = 0;  // tiles this workgroup has built
     for (uint64_t k = blockIdx.x; k < a.ndeals; k += gridDim.x) {
         const BatchDeal d = ldc(&a.deals[k]);
@@ -1967,23 +1968,26 @@ __global__ __launch_bounds__(kWG) void k_bm_deals(BmDealArgs a)
         q.syms = so.syms;
         q.halo_words = so.halo_words;
         const uint32_t S = 32u * (W - q.halo_words);
-        const uint32_t inner[1] = {tid < W - q.halo_words ? 0xFFFFFFFFu : 0u};
+        uint32_t inner[CPW];
+#pragma unroll
+        for (int c = 0; c < CPW; ++c)
+            inner[c] = tid + kWG * c < W - q.halo_words ? 0xFFFFFFFFu : 0u;
         const uint32_t ent0 = bc_entries<NS, W>(q, 0, lane);
         const BcPlaneMasks<NS> pm = bc_plane_masks<NS>(q.syms);
         const uint64_t t0 = d.tiles >> 3;
         const uint32_t nt = d.tiles & 7u;
-        bc_load_tile<1, STREAM>(q.tv, t0 * S, tid, X);
+        bc_load_tile<CPW, STREAM>(q.tv, t0 * S, tid, X);
         uint32_t acc = 0;
         for (uint32_t i = 0; i < nt; ++i, ++gi) {
             const uint64_t ts = (t0 + i) * S;
             uint32_t *buf = bml + (gi & 1u) * (NS * W);
-            bc_build_tile<NS, 1>(X, q.syms, pm, buf, tid);
+            bc_build_tile<NS, CPW>(X, q.syms, pm, buf, tid);
             if (i + 1u < nt)
-                bc_load_tile<1, STREAM>(q.tv, ts + S, tid, X);
+                bc_load_tile<CPW, STREAM>(q.tv, ts + S, tid, X);
             __syncthreads();
             uint32_t lo, hi;
             bc_tile_range(q, ts, S, lo, hi);
-            acc += bc_search_tile<NS, 1>(q, buf, ent0, tid, lo, hi, S, inner);
+            acc += bc_search_tile<NS, CPW>(q, buf, ent0, tid, lo, hi, S, inner);
         }
         const uint32_t c = wave_sum32(acc);
         if (lane == 0 && c)
@@ -2089,11 +2093,11 @@ static hipError_t launch_bitmap_c(const BmCountArgs &a, int ns, int cpw, unsigne
 
 hipError_t launch_bm_deals(const BmDealArgs &a, uint32_t halo_max, bool stream_loads, unsigned grid, hipStream_t s)
 {
-    const uint32_t lds = (2u * kBcMaxSyms * kWG + halo_max + 1u) * 4u;
+    const uint32_t lds = (2u * kBcMaxSyms * kWG * kBmDealCpw + halo_max + 1u) * 4u;
     if (stream_loads)
-        hipLaunchKernelGGL((k_bm_deals<true>), dim3(grid), dim3(kWG), lds, s, a);
+        hipLaunchKernelGGL((k_bm_deals<kBmDealCpw, true>), dim3(grid), dim3(kWG), lds, s, a);
     else
-        hipLaunchKernelGGL((k_bm_deals<false>), dim3(grid), dim3(kWG), lds, s, a);
+        hipLaunchKernelGGL((k_bm_deals<kBmDealCpw, false>), dim3(grid), dim3(kWG), lds, s, a);
     return hipGetLastError();
 }
 

@@ -1,7 +1,7 @@
 """Lone queries on small-alphabet texts inside a batch (bitmap deals) against the oracle.
 
 A text holding one count query, whose histogram shows at most 4 symbols and whose pattern has at
-most 4 distinct symbols and m <= 4096, runs as runs of 8 KiB bitmap tiles: Section 2.1's
+most 4 distinct symbols and m <= 8192, runs as runs of 16 KiB bitmap tiles: Section 2.1's
 SIMDcompare of each distinct pattern symbol becomes one bit per text byte and tile, each compare a
 shift and AND of those bits, with Algorithm 4's peel and zero tests.  These cases cover texts from
 one byte to several tiles at every start alignment, patterns of 1 to 4 distinct symbols (and 5,
@@ -76,8 +76,8 @@ def test_ragged_texts_one_query_each(dev):
                 t = over(a, n, g)
                 texts.append(t)
                 queries.append((len(texts) - 1, pattern_for(t, k, g)))
-    # the longest pattern the bitmap tiles take (a halo of 128 words) and the next one
-    for m in (4095, 4096, 4097, 5000):
+    # the longest pattern the bitmap tiles take (a halo of 256 words) and the next one
+    for m in (4096, 8191, 8192, 8193, 9000):
         t = over(b"ab", 300_000, g)
         o = int(g.integers(0, 100_000))
         t[o + 100_000:o + 100_000 + m] = t[o:o + m]
