@@ -89,7 +89,7 @@ typedef struct sm_batch_tune {
     int32_t peel[4];     /* peel r of batched queries, 1..8; default: from the frequency model */
     int32_t tile_kib;    /* byte-tile batches: 4, 8 or 16 KiB tiles; default 8                       */
     int32_t wgs_per_cu;  /* byte-tile batches, chunks of several queries: 1..32; default 8           */
-    int32_t deal_wgs_per_cu; /* byte-tile batches, single-query chunks (deals): 1..64; default 16    */
+    int32_t deal_wgs_per_cu; /* single-query chunks (byte and bitmap deals): 1..64; default 16      */
     int32_t pad;
 } sm_batch_tune;
 
@@ -277,11 +277,17 @@ typedef struct sm_query {
 /* Batched count: counts_dev[i] (device, nq x uint64) is overwritten with the
  * count of query i in its text, exactly as sm_count would return it, for any
  * histogram values (an understated, stale or foreign histogram only costs
- * speed).  All
- * queries run in one persistent launch that stages each text tile once and
- * runs every query of an m-bucket over it.  Validation is all-or-nothing
- * before anything is launched (the message names the first bad query).
- * Asynchronous on `stream`: host inputs are consumed before return. */
+ * speed).  The queries run in a few persistent launches, each text tile
+ * staged once for all queries that share it: texts with a histogram and at
+ * least bm_min queries through per-tile symbol bitmaps, the other queries
+ * through byte tiles shared by a text's queries of one m-bucket.  A text's
+ * lone query runs as deals (runs of tiles, one record each): of bitmap tiles
+ * when the histogram shows at most 4 symbols and the pattern has at most 4
+ * distinct symbols, else of byte tiles.  Texts of 64 MiB or more with one or
+ * two such queries run them through the single-search kernel.  Validation is
+ * all-or-nothing before anything is launched (the message names the first
+ * bad query).  Asynchronous on `stream`: host inputs are consumed before
+ * return. */
 int32_t sm_count_batch(const sm_query *q, uint64_t nq, const sm_text *texts, uint64_t nt,
                        uint64_t *counts_dev, const sm_params *params, void *stream);
 
