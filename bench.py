@@ -270,6 +270,7 @@ def run_zipf(args):
             "report_searches": len(rep_idx), "searches_per_step": searches,
             "pct_hbm_peak": round(100.0 * value / HBM_PEAK_GBS, 1),
             "launch_by_m": launch_by_m,
+            "tuning_table": autotune.table_status(),
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -10,8 +10,10 @@ and r = 5 for DNA (Section 3).  Cells of texts over at most 4 symbols also
 time the bitmap compares (SM_BITMAP: bitmap tile size, workgroups per CU and
 r), and a cell records which mode won.
 
-The table is one JSON file per GPU architecture (`tuning/<arch>.json` next to
-this module), which records the HIP version it was measured with.  The
+The table is a JSON file per GPU architecture and HIP version next to this
+module: `tuning/<arch>-hip<version>.json` when one was measured with the
+running HIP version, else `tuning/<arch>.json` (any version; `table_status()`
+says which file is in use and whether its recorded HIP version matches).  The
 binding consults it for searches on texts whose histogram it knows (`Text`
 objects) when the caller gives no explicit parameters; with no table for the
 current device it passes nothing and the library's defaults apply.
@@ -52,6 +54,7 @@ BM_GRID = [(tk, w, r) for tk in BM_TILE_KIB for w in BM_WGS_PER_CU for r in BM_P
 
 _table = None
 _table_key = None
+_table_path = None
 _device_keys: dict = {}   # device index -> (architecture, HIP version)
 
 
@@ -79,25 +82,49 @@ def _device_key():
     return key
 
 
+def table_paths(arch: str, hip: str) -> list:
+    """Candidate table files for a device, most specific first."""
+    return [os.path.join(TABLE_DIR, f"{arch}-hip{hip}.json"), os.path.join(TABLE_DIR, f"{arch}.json")]
+
+
 def load_table(path: str | None = None):
-    global _table, _table_key
+    global _table, _table_key, _table_path
     if path is None:
         try:
             arch, hip = _device_key()
         except Exception:  # noqa: BLE001 - no device: no table
             return None
-        path = os.path.join(TABLE_DIR, f"{arch}.json")
         key = (arch, hip)
+        if _table_key == key:
+            return _table
+        path = next((c for c in table_paths(arch, hip) if os.path.exists(c)), None)
     else:
         key = ("file", path)
-    if _table_key == key:
-        return _table
+        if _table_key == key:
+            return _table
     _table_key = key
     _table = None
-    if os.path.exists(path):
+    _table_path = None
+    if path is not None and os.path.exists(path):
         with open(path) as f:
             _table = json.load(f)
+        _table_path = path
     return _table
+
+
+def table_status() -> dict:
+    """The tuning table in use for the current device: its file, the HIP version it records and
+    whether that is the running one (a table from another version still applies: its settings
+    only change speed)."""
+    tab = load_table()
+    try:
+        hip = _device_key()[1]
+    except Exception:  # noqa: BLE001 - no device
+        hip = None
+    if not tab:
+        return {"table": None, "runtime_hip": hip}
+    return {"table": os.path.basename(_table_path), "table_hip": tab.get("hip"), "runtime_hip": hip,
+            "same_hip": tab.get("hip") == hip}
 
 
 def params_for(hist, m: int, n: int) -> dict | None:

@@ -127,3 +127,24 @@ def test_tuned_params_carry_the_compare_mode(monkeypatch):
         assert (p.peel, p.tile_kib, p.wgs_per_cu) == (e["peel"], e["tile_kib"], e["wgs_per_cu"])
         flipped = sm._params(text=FakeText(h, n), m=m, bitmap=not e.get("bitmap"))._obj
         assert bool(flipped.flags & _lib.SM_BITMAP) != bool(e.get("bitmap")) and flipped.tile_kib == 0
+
+
+def test_table_of_the_running_hip_version_is_preferred(monkeypatch, tmp_path):
+    """tuning/<arch>-hip<version>.json beats tuning/<arch>.json; either is reported with its version."""
+    monkeypatch.setattr(autotune, "TABLE_DIR", str(tmp_path))
+    monkeypatch.setattr(autotune, "_device_key", lambda: ("gfxT", "9.9.1"))
+    for name in ("_table", "_table_key", "_table_path"):     # restored with the cache they form
+        monkeypatch.setattr(autotune, name, None)
+    assert autotune.load_table() is None
+    assert autotune.table_status() == {"table": None, "runtime_hip": "9.9.1"}
+    (tmp_path / "gfxT.json").write_text(json.dumps({"hip": "9.8.0", "cells": {}, "tag": "any"}))
+    monkeypatch.setattr(autotune, "_table_key", None)
+    assert autotune.load_table()["tag"] == "any"
+    assert autotune.table_status() == {"table": "gfxT.json", "table_hip": "9.8.0", "runtime_hip": "9.9.1",
+                                       "same_hip": False}
+    (tmp_path / "gfxT-hip9.9.1.json").write_text(json.dumps({"hip": "9.9.1", "cells": {}, "tag": "exact"}))
+    monkeypatch.setattr(autotune, "_table_key", None)
+    assert autotune.load_table()["tag"] == "exact"
+    assert autotune.table_status()["same_hip"] is True
+    monkeypatch.setattr(autotune, "_device_key", lambda: ("gfxT", "9.7.0"))   # another runtime version
+    assert autotune.load_table()["tag"] == "any"
