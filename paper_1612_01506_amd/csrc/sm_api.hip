@@ -5,6 +5,7 @@
 #include "sm_internal.h"
 
 #include <algorithm>
+#include <chrono>
 #include <atomic>
 #include <condition_variable>
 #include <cstring>
@@ -1096,6 +1097,7 @@ int validate_batch(const sm_query *q, uint64_t nq, const sm_text *texts, uint64_
 // into that buffer, so a plan is bound to the buffer it was filled for.
 struct LaunchPlan {
     size_t bytes = 0;
+    bool fill_counts = true;  // launch_plan zeroes counts[0, nq) first (false: the caller did)
     size_t o_items = 0, o_tchunk = 0, o_queries = 0, o_steps = 0, o_bitems = 0, o_bq = 0, o_bout = 0,
            o_smap = 0, o_bsteps = 0, o_reports = 0;  // o_reports: reporting batches only (0: none)
     uint64_t nq = 0;
@@ -1164,11 +1166,17 @@ public:
             parts_ = std::max<size_t>(parts, 1);
             next_ = 0;
             done_ = 0;
+            adone_.store(0, std::memory_order_relaxed);
             ok_ = true;
             ++gen_;
+            agen_.store(gen_, std::memory_order_release);
         }
         cv_.notify_all();
         work();
+        // the other parts usually end within microseconds: spin a little before sleeping
+        const auto t0 = std::chrono::steady_clock::now();
+        while (adone_.load(std::memory_order_acquire) != parts_ && std::chrono::steady_clock::now() - t0 < kSpin)
+            std::this_thread::yield();
         std::unique_lock<std::mutex> lk(mu_);
         done_cv_.wait(lk, [&] { return done_ == parts_; });
         body_ = nullptr;
@@ -1191,6 +1199,7 @@ private:
         {
             std::lock_guard<std::mutex> lk(mu_);
             stop_ = true;
+            astop_.store(true, std::memory_order_release);
         }
         cv_.notify_all();
         for (auto &t : workers_)
@@ -1199,15 +1208,20 @@ private:
     void loop()
     {
         uint64_t seen = 0;
-        std::unique_lock<std::mutex> lk(mu_);
         while (true) {
+            // a batch's planning issues several ranges in quick succession: wait for the next one
+            // spinning (yielding the core) for a while, then sleeping
+            const auto t0 = std::chrono::steady_clock::now();
+            while (agen_.load(std::memory_order_acquire) == seen && !astop_.load(std::memory_order_acquire) &&
+                   std::chrono::steady_clock::now() - t0 < kSpin)
+                std::this_thread::yield();
+            std::unique_lock<std::mutex> lk(mu_);
             cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
             if (stop_)
                 return;
             seen = gen_;
             lk.unlock();
             work();
-            lk.lock();
         }
     }
     void work()
@@ -1234,11 +1248,16 @@ private:
             }
             std::lock_guard<std::mutex> lk(mu_);
             ok_ = ok_ && good;
+            adone_.store(done_ + 1, std::memory_order_release);
             if (++done_ == parts_)
                 done_cv_.notify_all();
         }
     }
     static constexpr size_t kThreads = 16;
+    static constexpr std::chrono::microseconds kSpin{300};
+    std::atomic<uint64_t> agen_{0};   // gen_, readable without the mutex
+    std::atomic<size_t> adone_{0};    // done_, likewise
+    std::atomic<bool> astop_{false};
     std::vector<std::thread> workers_;
     std::mutex run_mu_, mu_;
     std::condition_variable cv_, done_cv_;
@@ -1294,9 +1313,12 @@ using AllocFn = std::function<int(size_t, uint8_t **, uint8_t **)>;
 // long), builds every table into host memory obtained from `alloc` (which
 // also names the device address the tables will live at) and fills `lp`.
 int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uint64_t nt, const sm_params *params,
-               const AllocFn &alloc, LaunchPlan *lp, const ReportScratch *rep = nullptr)
+               const AllocFn &alloc, LaunchPlan *lp, const ReportScratch *rep = nullptr,
+               const uint32_t *out_map = nullptr)
 {
     lp->nq = nq;
+    // output slot of query i: i, or out_map[i] when the queries are part of a larger batch
+    auto out_of = [&](uint64_t i) -> uint32_t { return out_map ? out_map[i] : (uint32_t)i; };
     if (rep)
         lp->steps_of.assign(nq, ~0ull);
     // params has passed check_flags.  Explicit peel / tile / workgroups take precedence over the
@@ -1316,13 +1338,17 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
     const uint64_t deal_wpc = wpc_given ? (uint64_t)wpc : (bt && bt->deal_wgs_per_cu > 0) ? (uint64_t)bt->deal_wgs_per_cu
                                                                                              : kDealsPerCu;
     // alphabet class of a text with a histogram (symbols with a nonzero entry: <= 2, <= 4, <= 32,
-    // more) and the histogram's total for the peel model, in one pass over each histogram
+    // more) and the histogram's total for the peel model, in one pass over each histogram of a
+    // text some query reads
+    std::vector<uint8_t> used(nt, 0);
+    for (uint64_t i = 0; i < nq; ++i)
+        used[q[i].text_id] = 1;
     std::vector<uint8_t> text_cls(nt, 3);
     std::vector<double> hsum(nt, 0.0);
     if (!parallel_for(nt, [&](size_t t0, size_t t1) {
             for (size_t t = t0; t < t1; ++t) {
                 const uint64_t *h = texts[t].hist;
-                if (!h)
+                if (!h || !used[t])
                     continue;
                 uint32_t nsym = 0;
                 uint64_t sum = 0;
@@ -1721,7 +1747,7 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
             bq.last = (reinterpret_cast<uintptr_t>(tx.t) & 15u) + tx.n - pq.m;
             bq.m = (uint32_t)pq.m;
             bq.r = r;
-            bq.out = (uint32_t)pq.idx;
+            bq.out = out_of(pq.idx);
             hq[k] = bq;
             if (rep)
                 hrep[k] = BatchReport{rep->bc[pq.idx], rep->gs[pq.idx]};
@@ -1744,7 +1770,7 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
         rq[1] = (uint32_t)bm_off[i];
         for (uint32_t l = 0; l < kBmRecSteps; ++l)
             rq[2 + l] = e[std::min<uint64_t>(l, Q.m - 1)];
-        hbout[i] = (uint32_t)pq.idx;
+        hbout[i] = out_of(pq.idx);
     };
     const bool planned = parallel_for(n_st + n_lg + n_bm, [&](size_t k0, size_t k1) {
         Scratch w;
@@ -1859,7 +1885,7 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
         L.tv = make_view(texts[pq.text].t, texts[pq.text].n);
         L.m = pq.m;
         L.steps_off = long_steps_off[i];
-        L.out = pq.idx;
+        L.out = out_of(pq.idx);
         // long patterns: 4 KiB tiles (room for the halo); solo queries: the single-search tile
         const bool fits8 = 2 * (8192 + halo_for(pq.m)) <= kMaxLds;
         L.tu = Tune{(int)long_peel[i], (texts[pq.text].n >= (8ull << 20) && fits8) ? 2 : 1, wpc_long,
@@ -1886,7 +1912,8 @@ int plan_batch(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uin
 // and no allocation, so it can be captured in a graph.
 int launch_plan(Dev &d, const LaunchPlan &lp, const uint8_t *dev, unsigned long long *counts, hipStream_t s)
 {
-    HIP_TRY(launch_fill_u64(counts, lp.nq, 0ull, s));
+    if (lp.fill_counts)
+        HIP_TRY(launch_fill_u64(counts, lp.nq, 0ull, s));
     if (lp.n_bitems) {
         BmArgs a{};
         a.items = reinterpret_cast<const BmItem *>(dev + lp.o_bitems);
@@ -2362,6 +2389,52 @@ int32_t sm_patterns_report_noalloc(const sm_patterns *ps, uint64_t i, const uint
                                tot, s);
 }
 
+// Plans, uploads and launches one validated count batch, or part of one: out_map gives each
+// query's output slot, and counts[0, fill_n) are zeroed after the planning succeeded and before
+// the kernels run (a batch's first part zeroes the whole batch's counts, the second none).  The
+// caller holds d.mu.
+static int count_batch_part(Dev &d, const sm_query *q, uint64_t nq, const sm_text *texts, uint64_t nt,
+                            const sm_params *params, unsigned long long *counts, hipStream_t s,
+                            const uint32_t *out_map, uint64_t fill_n)
+{
+    Upload u;
+    LaunchPlan lp;
+    bool reserved = false;
+    AllocFn alloc = [&](size_t bytes, uint8_t **h, uint8_t **dv) {
+        SM_TRY(ring_reserve(d, bytes, &u));
+        reserved = true;
+        *h = u.host;
+        *dv = u.dev;
+        return (int)SM_OK;
+    };
+    {
+        const int prc = plan_batch(d, q, nq, texts, nt, params, alloc, &lp, nullptr, out_map);
+        if (prc < 0) {
+            const std::string msg = g_err;
+            if (reserved)
+                (void)ring_commit(d, u, s);  // give the reservation back
+            return fail(prc, msg);
+        }
+    }
+    lp.fill_counts = false;
+    int rc = ring_copy(u, lp.bytes, s);
+    if (rc == SM_OK && fill_n)
+        rc = launch_fill_u64(counts, fill_n, 0ull, s) == hipSuccess ? SM_OK
+                                                                      : fail(SM_EDEVICE, "launching the counts fill");
+    if (rc == SM_OK)
+        rc = launch_plan(d, lp, u.dev, counts, s);
+    const std::string msg = g_err;
+    const int rc2 = ring_commit(d, u, s);
+    if (rc < 0)
+        return fail(rc, msg);
+    return rc2;
+}
+
+// One-shot batches of at least this many queries over at least this many texts are planned in
+// two parts, so that the GPU runs the first while the host plans the second.
+constexpr uint64_t kSplitMinQueries = 2048;
+constexpr uint64_t kSplitMinTexts = 512;
+
 int32_t sm_count_batch(const sm_query *q, uint64_t nq, const sm_text *texts, uint64_t nt,
                        uint64_t *counts_dev, const sm_params *params, void *stream)
 {
@@ -2376,33 +2449,35 @@ int32_t sm_count_batch(const sm_query *q, uint64_t nq, const sm_text *texts, uin
     SM_TRY(get_dev(&d));
     std::lock_guard<std::mutex> lk(d->mu);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    Upload u;
-    LaunchPlan lp;
-    bool reserved = false;
-    AllocFn alloc = [&](size_t bytes, uint8_t **h, uint8_t **dv) {
-        SM_TRY(ring_reserve(*d, bytes, &u));
-        reserved = true;
-        *h = u.host;
-        *dv = u.dev;
-        return (int)SM_OK;
-    };
-    {
-        const int prc = plan_batch(*d, q, nq, texts, nt, params, alloc, &lp);
-        if (prc < 0) {
-            const std::string msg = g_err;
-            if (reserved)
-                (void)ring_commit(*d, u, s);  // give the reservation back
-            return fail(prc, msg);
+    unsigned long long *counts = reinterpret_cast<unsigned long long *>(counts_dev);
+    if (nq >= kSplitMinQueries && nt >= kSplitMinTexts) {
+        // The parts are split by text id at about half the queries, so each text's queries stay in
+        // one part and every text gets the launch mode it would get in a single plan.
+        std::vector<uint64_t> per_text(nt, 0);
+        for (uint64_t i = 0; i < nq; ++i)
+            per_text[q[i].text_id]++;
+        uint64_t below = 0, cut = 0;
+        while (cut < nt && 2 * below < nq)
+            below += per_text[cut++];
+        if (below > 0 && below < nq) {
+            std::vector<sm_query> part[2];
+            std::vector<uint32_t> map[2];
+            part[0].reserve(below);
+            map[0].reserve(below);
+            part[1].reserve(nq - below);
+            map[1].reserve(nq - below);
+            for (uint64_t i = 0; i < nq; ++i) {
+                const int h = q[i].text_id < cut ? 0 : 1;
+                part[h].push_back(q[i]);
+                map[h].push_back((uint32_t)i);
+            }
+            for (int h = 0; h < 2; ++h)
+                SM_TRY(count_batch_part(*d, part[h].data(), part[h].size(), texts, nt, params, counts, s,
+                                        map[h].data(), h == 0 ? nq : 0));
+            return SM_OK;
         }
     }
-    int rc = ring_copy(u, lp.bytes, s);
-    if (rc == SM_OK)
-        rc = launch_plan(*d, lp, u.dev, reinterpret_cast<unsigned long long *>(counts_dev), s);
-    const std::string msg = g_err;
-    const int rc2 = ring_commit(*d, u, s);
-    if (rc < 0)
-        return fail(rc, msg);
-    return rc2;
+    return count_batch_part(*d, q, nq, texts, nt, params, counts, s, nullptr, nq);
 }
 
 // One reporting batch whose scratch fits (see sm_report_batch); the caller
