@@ -371,7 +371,7 @@ def _marshal_batch(texts, queries, use_hist: bool):
 
 def count_batch(texts: Sequence, queries: Iterable, peel=None, tile_kib=None, wgs_per_cu=None,
                 stream=None, use_hist: bool = True, tune: bool = True) -> torch.Tensor:
-    """Counts of many (text_id, pattern[, order]) queries in one persistent launch (asynchronous).
+    """Counts of many (text_id, pattern[, order]) queries in a few persistent launches (asynchronous).
 
     Returns a device int64 tensor with one count per query.  Queries without an
     explicit order use the frequency order when the text's histogram is known

@@ -5,8 +5,8 @@ scheduler keeps up to `max_inflight` device batches in flight on separate
 streams; whenever a slot frees up, the requests queued by then are admitted,
 in arrival order, while the batch's estimated device time stays within
 `batch_budget_us` (and at most `max_batch` requests), and sent to the device
-in one batched count (sm_count_batch: one persistent launch shared by all
-patterns of a text).  The estimate comes from a cost model of the executor
+in one batched count (sm_count_batch: a few persistent launches, each text
+tile staged once for all patterns of its text).  The estimate comes from a cost model of the executor
 (per text pass, per query by alphabet class and kernel mode), so a burst of
 arrivals is split into batches of bounded latency instead of one long one.
 A reporting request is counted first; its position buffer (count x 8 bytes)
